@@ -1,0 +1,178 @@
+"""Pins of the schedule enumerator and the grid-size model.
+
+* the paper's worked examples (golden fixture, each entry cites its passage);
+* exhaustive tiny problems: every (tile, k) covered once, one writer per tile
+  holding k = 0, at most one partial per workgroup, owner peers contiguous
+  and above the owner, even share within one, at most two contributors per
+  tile when the Stream-K region has at least as many tiles as workgroups;
+* the generalisations stated in the Stream-K subsection: g = t behaves like
+  data-parallel, g = s * t like fixed-split s (when s divides the iterations
+  per tile);
+* the model reproduces the three published best grid sizes.
+"""
+import itertools
+import json
+import os
+
+import pytest
+
+from oracle import schedule as S
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "streamk_worked_examples.json")))
+
+
+def test_dp_ceilings():
+    for e in GOLDEN["dp_ceiling"]:
+        tm, tn, t, _, _ = S.iteration_space(e["M"], e["N"], e["K"], e["BM"], e["BN"], 1)
+        assert t == e["tiles"]
+        assert S.dp_utilization_ceiling(t, e["p"]) == pytest.approx(e["ceiling"])
+
+
+def test_fixed_split_example():
+    e = GOLDEN["fixed_split"][0]
+    _, _, t, ipt, _ = S.iteration_space(e["M"], e["N"], e["K"], e["BM"], e["BN"], e["BK"])
+    sched = S.fixed_split_schedule(t, ipt, e["s"])
+    assert len(sched) == e["grid"]
+    assert all((segs[0].k_hi - segs[0].k_lo) * e["BK"] == e["k_per_cta"] for segs in sched)
+    assert S.dp_utilization_ceiling(len(sched), e["p"]) == pytest.approx(e["efficiency"])
+
+
+def test_basic_streamk_example():
+    e = GOLDEN["basic_streamk"][0]
+    pl = S.make_plan(e["M"], e["N"], e["K"], e["BM"], e["BN"], e["BK"], p=e["g"], policy="sk", force_g=e["g"])
+    assert pl.ipt == e["iters_per_tile"]
+    sched = S.enumerate_schedule(pl)
+    for segs in sched:
+        n = sum(s.k_hi - s.k_lo for s in segs)
+        assert n == e["iters_per_cta"]
+        assert n * e["BK"] == e["k_volume_per_cta"]
+    S.check_invariants(pl, sched)
+
+
+def test_skew_example():
+    e = GOLDEN["skew"][0]
+    pl = S.make_plan(e["M"], e["N"], e["K"], e["BM"], e["BN"], e["BK"], p=e["g"], policy="sk", force_g=e["g"])
+    sched = S.enumerate_schedule(pl)
+    assert [segs[0].k_lo * e["BK"] for segs in sched] == e["k_offsets"]
+
+
+def test_hybrid_examples_peer_counts():
+    # 896x384x128 on four SMs, 128x128x4 tiles: two-tile SK + DP gives each owner
+    # exactly one peer; DP + one-tile SK puts three peers on one owner.
+    two = S.make_plan(896, 384, 128, 128, 128, 4, p=4, policy="2tile_sk_dp")
+    one = S.make_plan(896, 384, 128, 128, 128, 4, p=4, policy="dp_1tile_sk")
+    auto = S.make_plan(896, 384, 128, 128, 128, 4, p=4)
+    assert auto.policy == "2tile_sk_dp"
+    owners2 = [s for segs in S.enumerate_schedule(two) for s in segs if s.role == S.OWNER]
+    owners1 = [s for segs in S.enumerate_schedule(one) for s in segs if s.role == S.OWNER]
+    assert owners2 and all(len(s.peers) == 1 for s in owners2)
+    assert len(owners1) == 1 and owners1[0].peers == (1, 2, 3)
+    assert two.sk_tiles == 5 and one.sk_tiles == 1
+    for pl in (two, one):
+        S.check_invariants(pl, S.enumerate_schedule(pl))
+
+
+def test_model_reproduces_published_grid_sizes():
+    tile = GOLDEN["model_tile"]
+    for e in GOLDEN["model"]:
+        _, _, t, ipt, T = S.iteration_space(e["M"], e["N"], e["K"], tile["BM"], tile["BN"], tile["BK"])
+        assert (t, ipt) == (e["tiles"], e["iters_per_tile"])
+        g = S.model_best_g(t, ipt, tile["p"], (0.0, 20.0, 1.0, 8.0))
+        assert g == e["g_best"]
+        pl = S.make_plan(e["M"], e["N"], e["K"], tile["BM"], tile["BN"], tile["BK"], p=tile["p"],
+                         policy="sk", force_g=g)
+        counts = sorted({sum(s.k_hi - s.k_lo for s in segs) for segs in S.enumerate_schedule(pl)})
+        assert counts == e["iters_per_cta"]
+
+
+def test_model_sensitivity():
+    """A dropped term of the model changes at least one published choice."""
+    tile = GOLDEN["model_tile"]
+    shapes = [(e["M"], e["N"], e["K"]) for e in GOLDEN["model"]]
+    want = [e["g_best"] for e in GOLDEN["model"]]
+    for consts in [(0, 0, 1, 8), (0, 20, 1, 0), (0, 20, 0, 8)]:
+        got = []
+        for M, N, K in shapes:
+            _, _, t, ipt, _ = S.iteration_space(M, N, K, tile["BM"], tile["BN"], tile["BK"])
+            got.append(S.model_best_g(t, ipt, tile["p"], consts))
+        assert got != want
+
+
+def _tiny_cases():
+    for M, N, K in itertools.product(range(1, 6), range(1, 6), range(0, 6)):
+        yield M, N, K
+
+
+@pytest.mark.parametrize("policy", ["sk", "dp", "dp_1tile_sk", "2tile_sk_dp", "auto"])
+def test_exhaustive_tiny_invariants(policy):
+    BM = BN = 2
+    BK = 1
+    n_checked = 0
+    for M, N, K in _tiny_cases():
+        _, _, t, ipt, T = S.iteration_space(M, N, K, BM, BN, BK)
+        for p in range(1, max(T, t) + 2):
+            gs = range(1, T + 1) if policy == "sk" and T else [0]
+            for g in gs:
+                pl = S.make_plan(M, N, K, BM, BN, BK, p=p, policy=policy, force_g=g)
+                sched = S.enumerate_schedule(pl)
+                S.check_invariants(pl, sched)
+                if pl.g_sk:
+                    shares = [sum(s.k_hi - s.k_lo for s in S.streamk_share(x, pl)) for x in range(pl.g_sk)]
+                    q = pl.sk_iters // pl.g_sk
+                    assert set(shares) <= {q, q + 1}
+                    if pl.sk_tiles >= pl.g_sk:
+                        contrib = {}
+                        for x in range(pl.g_sk):
+                            for s in S.streamk_share(x, pl):
+                                contrib.setdefault(s.tile, set()).add(x)
+                        assert max(len(v) for v in contrib.values()) <= 2
+                n_checked += 1
+    assert n_checked > 100
+
+
+def test_sk_with_g_equal_t_is_data_parallel():
+    for M, N, K in [(384, 384, 128), (1000, 300, 77), (128, 128, 1)]:
+        pl = S.make_plan(M, N, K, 128, 128, 4, p=1024, policy="sk", force_g=0)
+        force = S.make_plan(M, N, K, 128, 128, 4, p=1024, policy="sk", force_g=pl.t)
+        dp = S.make_plan(M, N, K, 128, 128, 4, p=1024, policy="dp")
+        assert S.enumerate_schedule(force) == S.enumerate_schedule(dp)
+
+
+@pytest.mark.parametrize("s", [2, 4, 8])
+def test_sk_with_g_multiple_of_t_is_fixed_split(s):
+    M, N, K = 384, 256, 256
+    pl = S.make_plan(M, N, K, 128, 128, 8, p=4096, policy="sk", force_g=0)
+    assert pl.ipt % s == 0
+    sk = S.make_plan(M, N, K, 128, 128, 8, p=4096, policy="sk", force_g=s * pl.t)
+    assert S.enumerate_schedule(sk) == S.fixed_split_schedule(pl.t, pl.ipt, s)
+
+
+def test_auto_policy_regimes():
+    p = 256
+    # full waves only -> data-parallel
+    assert S.make_plan(8192, 8192, 8192, 256, 256, 64, p).policy == "dp"
+    # fewer tiles than workgroups -> basic Stream-K, g within [t, p]
+    pl = S.make_plan(384, 384, 1024, 128, 128, 32, p, model=(0, 20, 1, 8))
+    assert pl.policy == "sk" and pl.t <= pl.g_sk <= p
+    # one full wave plus a remainder -> DP + one-tile SK
+    pl = S.make_plan(256 * 17, 256 * 16, 1024, 256, 256, 64, p)
+    assert pl.policy == "dp_1tile_sk" and pl.sk_tiles == 16
+    # two or more waves plus a remainder -> two-tile SK + DP with one fewer DP wave
+    pl = S.make_plan(256 * 33, 256 * 16, 1024, 256, 256, 64, p)
+    assert pl.policy == "2tile_sk_dp" and pl.sk_tiles == 16 + 256 and pl.g_sk == 256
+
+
+def test_planted_mistake_is_caught():
+    """The invariant checker fails on a schedule with a dropped iteration and on
+    one whose owner lists the wrong peer."""
+    pl = S.make_plan(896, 384, 128, 128, 128, 4, p=4, policy="sk", force_g=4)
+    sched = S.enumerate_schedule(pl)
+    broken = [list(x) for x in sched]
+    s0 = broken[0][-1]
+    broken[0][-1] = S.Segment(s0.tile, s0.k_lo, s0.k_hi - 1, s0.role, s0.peers)
+    with pytest.raises(AssertionError):
+        S.check_invariants(pl, broken)
+    broken = [list(x) for x in sched]
+    broken[0][-1] = S.Segment(s0.tile, s0.k_lo, s0.k_hi, s0.role, (2,))
+    with pytest.raises(AssertionError):
+        S.check_invariants(pl, broken)
