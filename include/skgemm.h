@@ -1,0 +1,159 @@
+/*
+ * skgemm: Stream-K GEMM for AMD Instinct MI355X (gfx950).
+ *
+ * Computes C = alpha * (s_A * s_B) * A * B + beta * C, the GEMM problem of the
+ * Background section of "Stream-K: Work-centric Parallel Decomposition for
+ * Dense Matrix-Matrix Multiplication on the GPU" (dissertation chapter of
+ * arXiv 2212.08964), with the work split by MAC-loop iteration across a grid
+ * of persistent workgroups as in the basic Stream-K algorithm and its
+ * data-parallel hybrids (Data-parallel Hybridization subsection).
+ *
+ * Conventions shared by every entry point:
+ *  - Shapes: A is M x K, B is K x N, C is M x N.  Each operand is row- or
+ *    column-major with its own leading dimension (elements, not bytes).
+ *  - Element types: A and B share one input type; C is FP32, BF16 or FP16
+ *    (FP8 inputs write FP32, BF16 or FP16).  Accumulation and the fix-up of
+ *    partial tiles are FP32.  Output rounding is round-to-nearest-even.
+ *  - Device pointers: A, B, C, scales, workspace, trace and descriptor arrays
+ *    are device memory owned by the caller.  The library owns only plans.
+ *  - Streams: runs are asynchronous on the given hipStream_t (NULL = default
+ *    stream).  Plans are immutable after creation and may be shared by
+ *    threads; a workspace must not be used by two runs in flight at once.
+ *  - Errors: every call returns a status and never throws.  Argument errors
+ *    are reported before anything is launched.  beta == 0 never reads C.
+ *    K == 0 gives C = beta * C; M == 0 or N == 0 launches nothing.
+ */
+#ifndef SKGEMM_H
+#define SKGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SKGEMM_OK = 0,
+    SKGEMM_ERR_INVALID_ARG = 1,   /* bad shape, leading dimension, pointer or enum */
+    SKGEMM_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+    SKGEMM_ERR_WORKSPACE = 3,     /* workspace missing, misaligned or too small */
+    SKGEMM_ERR_CAPACITY = 4,      /* grid larger than the co-resident workgroups */
+    SKGEMM_ERR_HIP = 5,           /* a HIP runtime call failed */
+    SKGEMM_ERR_TIMEOUT = 6        /* a bounded fix-up wait expired on the device */
+} skgemm_status_t;
+
+typedef enum { SKGEMM_ROW_MAJOR = 0, SKGEMM_COL_MAJOR = 1 } skgemm_layout_t;
+
+typedef enum {
+    SKGEMM_F32 = 0,
+    SKGEMM_F16 = 1,
+    SKGEMM_BF16 = 2,
+    SKGEMM_F8E4M3 = 3             /* OCP E4M3FN, used with per-tensor scales */
+} skgemm_dtype_t;
+
+/* Work decomposition (Work Decomposition Strategies section and
+ * Data-parallel Hybridization subsection). */
+typedef enum {
+    SKGEMM_POLICY_AUTO = 0,       /* DP when tiles fill whole waves, basic SK with the
+                                     model's grid when tiles < workgroups, else a hybrid */
+    SKGEMM_POLICY_DP = 1,         /* one workgroup per output tile */
+    SKGEMM_POLICY_SK = 2,         /* basic Stream-K over all tiles */
+    SKGEMM_POLICY_DP_1TILE_SK = 3,/* full DP waves, Stream-K over the remainder tiles */
+    SKGEMM_POLICY_2TILE_SK_DP = 4 /* Stream-K over remainder + one wave, then DP waves */
+} skgemm_policy_t;
+
+typedef struct {
+    skgemm_policy_t policy;       /* default SKGEMM_POLICY_AUTO */
+    int32_t force_g;              /* >0: Stream-K grid size instead of the model's choice */
+    int32_t tile_m, tile_n, tile_k;   /* 0 = the dtype's default tile; else must name
+                                         a compiled tile configuration */
+    int32_t hybrid_min_waves;     /* full waves needed for the two-tile hybrid (default 2) */
+    int32_t num_cus;              /* >0: plan for this many CUs instead of querying */
+    int32_t occupancy;            /* >0: workgroups per CU instead of querying */
+} skgemm_options_t;
+
+/* Fills *opt with the defaults. */
+void skgemm_default_options(skgemm_options_t* opt);
+
+typedef struct skgemm_plan_s* skgemm_plan_t;
+
+/* Plan one GEMM (host arithmetic only; queries device 0's properties unless
+ * opt->num_cus and opt->occupancy are set).  la / lb / lc are the layouts of
+ * A, B and C; ta == tb is required.  FP8 needs A row-major and B
+ * column-major (K contiguous in both); skgemm_quantize_e4m3 writes either.
+ * On success *out receives a plan that skgemm_plan_destroy frees. */
+skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
+                            skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc,
+                            skgemm_dtype_t ta, skgemm_dtype_t tb, skgemm_dtype_t tc,
+                            const skgemm_options_t* opt);
+
+/* Bytes of device workspace a run of this plan needs (0 when the plan has no
+ * Stream-K region).  The workspace holds the FP32 partial tiles, one per
+ * Stream-K workgroup, their ready flags and an error word.  It must be
+ * 256-byte aligned and zero-filled once after allocation; the kernel leaves
+ * its flags at zero again on success, so it can be reused without clearing.
+ * After SKGEMM_ERR_TIMEOUT it must be zero-filled again. */
+skgemm_status_t skgemm_workspace_size(skgemm_plan_t plan, size_t* bytes);
+
+/* Run a planned GEMM.  lda/ldb/ldc follow each operand's layout and must be
+ * at least its contiguous extent.  scale_a / scale_b point to one FP32 value
+ * on the device each (NULL = 1).  workspace may be NULL when the workspace
+ * size is 0. */
+skgemm_status_t skgemm_run(skgemm_plan_t plan,
+                           const void* A, int64_t lda, const void* B, int64_t ldb,
+                           void* C, int64_t ldc, float alpha, float beta,
+                           const float* scale_a, const float* scale_b,
+                           void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Number of schedule records a traced run of this plan can write: the number
+ * of launched workgroups times the most segments any of them performs. */
+skgemm_status_t skgemm_trace_capacity(skgemm_plan_t plan, size_t* n_records);
+
+/* Same as skgemm_run, and each workgroup also writes one record of 8 int32
+ * per segment it performs, in execution order, into trace (device memory of
+ * at least skgemm_trace_capacity records; unused records are untouched):
+ *   {workgroup, sequence number, tile, first k-iteration, end k-iteration,
+ *    role (0 full, 1 partial, 2 owner), first peer, last peer (-1 if none)}.
+ * Record (wg, seq) is at index wg * (capacity / grid) + seq. */
+skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
+                                  const void* A, int64_t lda, const void* B, int64_t ldb,
+                                  void* C, int64_t ldc, float alpha, float beta,
+                                  const float* scale_a, const float* scale_b,
+                                  void* workspace, size_t ws_bytes,
+                                  int32_t* trace, size_t trace_records, hipStream_t stream);
+
+/* Resolved plan, for logging and for comparing with an independent
+ * enumerator of the schedule.  info[] receives, in order:
+ *   0 M', 1 N', 2 K (problem as launched: M' = N and N' = M when C is
+ *     column-major and the operands were swapped), 3 swapped (0/1),
+ *   4 BM, 5 BN, 6 BK, 7 tiles_m, 8 tiles_n, 9 tiles, 10 iters_per_tile,
+ *   11 policy (resolved skgemm_policy_t), 12 sk_tiles, 13 g_sk, 14 grid,
+ *   15 sk_first (0/1), 16 p (co-resident workgroups), 17 hybrid_min_waves,
+ *   18 A K-contiguous (0/1), 19 B K-contiguous (0/1).
+ * n is the capacity of info; up to 20 values are written. */
+skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
+
+/* Analytical grid-size model constants (Analytical Modeling subsection)
+ * used by the plan for the dtype of the plan: time = a + b*[peers > 1] +
+ * c*iters_per_cta + d*(peers - 1).  Writes 4 doubles. */
+skgemm_status_t skgemm_model_constants(skgemm_plan_t plan, double* abcd);
+
+/* Host-side copy of the schedule the plan launches, in the same record
+ * format as skgemm_run_traced (no device access). */
+skgemm_status_t skgemm_schedule(skgemm_plan_t plan, int32_t* records, size_t cap, size_t* n);
+
+/* Reads the workspace's error word (synchronises the stream).  Returns
+ * SKGEMM_ERR_TIMEOUT if a fix-up wait expired in an earlier run. */
+skgemm_status_t skgemm_check_device_error(const void* workspace, hipStream_t stream);
+
+skgemm_status_t skgemm_plan_destroy(skgemm_plan_t plan);
+
+const char* skgemm_status_string(skgemm_status_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKGEMM_H */

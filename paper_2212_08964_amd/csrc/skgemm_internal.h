@@ -1,0 +1,57 @@
+// Internal declarations shared by the library's planner, ABI layer and kernels.
+#pragma once
+
+#include <stdint.h>
+#include <stddef.h>
+
+namespace skg {
+
+enum DType : int32_t { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
+enum Role : int32_t { ROLE_FULL = 0, ROLE_PARTIAL = 1, ROLE_OWNER = 2 };
+
+constexpr int kFlagStrideInts = 32;        // one 128-byte line per ready flag
+constexpr size_t kWsHeaderBytes = 256;     // error word lives at offset 0
+constexpr int kTraceFields = 8;
+constexpr int32_t kErrTimeout = 6;
+
+// Compiled tile configurations per input type (BM x BN x BK).
+struct TileCfg { int bm, bn, bk; };
+constexpr TileCfg kTileF32 = {128, 128, 32};
+constexpr TileCfg kTile16 = {256, 256, 64};    // bf16 and f16
+constexpr TileCfg kTileF8 = {256, 256, 128};
+
+// Kernel arguments, passed by value.  Operands are described relative to the
+// reduction: an operand is "K-contiguous" when consecutive k are adjacent in
+// memory (row-major A, column-major B).
+struct KArgs {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t tm, tn, t, ipt;
+    int32_t sk_tiles, g_sk, sk_iters, sk_q, sk_r, grid;
+    int32_t sk_first, dp_only;
+    float alpha, beta;
+    const float* scale_a;
+    const float* scale_b;
+    int32_t out_dtype;
+    int32_t vec_a, vec_b;      // bytes per vector global load: 16, 8, 4, 2 or 1
+    float* partials;
+    int32_t* flags;
+    int32_t* err;
+    int32_t* trace;
+    int32_t trace_per_wg;
+    int32_t spin_limit;
+};
+
+// Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
+int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, const KArgs& args, int grid,
+                void* stream);
+// Workgroups of the kernel that fit on one CU at once (0 on failure).
+int kernel_occupancy(int dtype, bool a_kcontig, bool b_kcontig);
+bool kernel_exists(int dtype, bool a_kcontig, bool b_kcontig);
+// Threads per workgroup of the dtype's kernel.
+int kernel_threads(int dtype);
+
+}  // namespace skg

@@ -1,0 +1,651 @@
+// Persistent Stream-K GEMM kernels for gfx950 (CDNA4).
+//
+// One kernel template covers the data-parallel, basic Stream-K and hybrid
+// schedules (Work Decomposition Strategies section, basic Stream-K algorithm;
+// Data-parallel Hybridization subsection): each workgroup walks its even share
+// of MAC-loop iterations across tile seams, then (or first) its whole
+// data-parallel tiles.  A segment that does not start its tile publishes an
+// FP32 partial tile and a ready flag; the segment holding the tile's k = 0
+// iteration adds the partials of the following workgroups in ascending order
+// and writes C, so results are deterministic for a fixed plan.
+//
+// MAC loop (the MacLoop subroutine): a WM x WN grid of wave64 wavefronts
+// (2 x 2 for the FP32 128x128 tile, 2 x 4 for the 256x256 16-bit and FP8
+// tiles, so no lane holds more than 128 FP32 accumulators).  Each k-iteration
+// moves a BM x BK slab of A and a BK x BN slab of B straight from global
+// memory into LDS with buffer loads that write LDS directly (no register
+// staging); two LDS stages alternate so the next slab is in flight while the
+// MFMAs consume the current one.  Each wave accumulates its (BM/WM) x (BN/WN)
+// block with 32x32 MFMA instructions into FP32 registers.
+//
+// LDS layouts (no padding; 16-byte chunks XOR-swizzled per row so that the
+// fragment reads of one instruction fall on distinct banks):
+//  * K-contiguous operand: [rows][128 bytes of k]; chunk c of row r sits at
+//    position c ^ (r mod 8).
+//  * MN-contiguous operand: [k][512 bytes of rows]; chunk c of row k sits at
+//    position c ^ 4 (k mod 4) for 16-bit types (read with the LDS transpose
+//    read, four k of one column per lane) and c ^ 8 ((k / 4) mod 2) for FP32
+//    (read with plain 4-byte reads).
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "skgemm_internal.h"
+
+namespace skg {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Tile per input type and the wave grid that covers it (WM x WN wavefronts).
+template <int DT> struct Cfg;
+template <> struct Cfg<DT_F32> { static constexpr int EB = 4, BM = kTileF32.bm, BN = kTileF32.bn, BK = kTileF32.bk, WM = 2, WN = 2; };
+template <> struct Cfg<DT_F16> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
+template <> struct Cfg<DT_BF16> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
+template <> struct Cfg<DT_F8> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4; };
+
+template <int DT>
+constexpr int kThreadsOf = 64 * Cfg<DT>::WM * Cfg<DT>::WN;
+
+// Buffer descriptor word 3 for untyped buffer loads on gfx9-family targets.
+constexpr int kBufferFlags = 0x00020000;
+
+__device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// ------------------------------------------------------------------ slab loads
+
+// Position swizzle of a row of a slab in LDS (see the layout note above).
+template <int EB, bool KC>
+__device__ __forceinline__ int swz(int row) {
+    if constexpr (KC) return row & 7;
+    else if constexpr (EB == 4) return 8 * ((row >> 2) & 1);
+    else return 4 * (row & 3);
+}
+
+// One operand's slab of a k-iteration: R rows of the output dimension by BK.
+// The workgroup's waves split the slab's LDS image into 1 KiB blocks (64 lanes
+// x 16 bytes); each lane fetches the global chunk whose swizzled position is
+// its slot in the block.  Loads go through a buffer descriptor rebased at
+// every k-iteration, so a lane keeps only 32-bit offsets, and the hardware
+// returns zero for bytes past the end of the operand (rows beyond M or N of a
+// K-contiguous operand, k beyond K of an MN-contiguous one).  Chunks that
+// reach past the inner edge of a row (k beyond K, or columns beyond M or N)
+// are skipped by the wide load (offset forced out of range: zero, no memory
+// access) and, where partly inside, reloaded element by element.
+template <int EB, int R, int BK, bool KC, int THREADS>
+struct Slab {
+    static constexpr int VE = 16 / EB;
+    static constexpr int ROWB = KC ? BK * EB : R * EB;      // LDS row bytes
+    static constexpr int BYTES = KC ? R * ROWB : BK * ROWB;
+    static constexpr int NW = THREADS / 64;
+    static constexpr int BLOCKS = BYTES / 1024;
+    static constexpr int PER_WAVE = BLOCKS / NW;
+    static_assert(BK * EB == 128, "k slab must be 128 bytes");
+    static_assert(KC || ROWB == 512, "MN-contiguous slab rows must be 512 bytes");
+    static_assert(BLOCKS % NW == 0, "slab must split evenly over the waves");
+
+    uint32_t voff[PER_WAVE];     // byte offset of the lane's chunk from the slab origin
+    int inner[PER_WAVE];         // its first inner-dimension element within the slab row
+    const unsigned char* base;   // operand address of (outer o0, k of the first iteration)
+    int64_t bytes;               // operand bytes from base to its end
+    int64_t step;                // bytes between consecutive k-iterations
+
+    __device__ __forceinline__ void init(const void* X, int64_t ld, int o0, int dout, int kbeg, int K,
+                                         int tid) {
+        const int k0 = kbeg * BK;
+        const unsigned char* p = reinterpret_cast<const unsigned char*>(X);
+        if constexpr (KC) {
+            base = p + ((int64_t)o0 * ld + k0) * EB;
+            bytes = ((int64_t)(dout - o0 - 1) * ld + (K - k0)) * EB;
+            step = BK * EB;
+        } else {
+            base = p + ((int64_t)k0 * ld + o0) * EB;
+            bytes = ((int64_t)(K - k0 - 1) * ld + (dout - o0)) * EB;
+            step = (int64_t)BK * ld * EB;
+        }
+        const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+        for (int j = 0; j < PER_WAVE; ++j) {
+            const int pos = (w + j * NW) * 1024 + lane * 16;
+            const int row = pos / ROWB;
+            const int c = ((pos % ROWB) >> 4) ^ swz<EB, KC>(row);
+            voff[j] = uint32_t(row) * uint32_t(ld * EB) + uint32_t(c * 16);
+            inner[j] = c * VE;
+        }
+    }
+
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int it) const {
+        const int64_t skip = (int64_t)it * step;
+        const int64_t left = bytes - skip;
+        const int nrec = left <= 0 ? 0 : (left > 0x7fffffff ? 0x7fffffff : int(left));
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(base + skip), (short)0, nrec,
+                                                 kBufferFlags);
+    }
+
+    // Elements of the lane's chunk j inside the inner edge (VE when not at the edge).
+    __device__ __forceinline__ int keep(int j, bool tail, int lim) const {
+        return tail ? min(max(lim - inner[j], 0), VE) : VE;
+    }
+
+    // Issue the direct-to-LDS loads of iteration `it` (counted from kbeg), whose
+    // first k is k0, into the stage at `lds`.
+    __device__ __forceinline__ void issue(int it, int k0, int K, int o0, int dout, unsigned char* lds,
+                                          int tid) const {
+        const __amdgpu_buffer_rsrc_t rs = rsrc(it);
+        const bool tail = KC ? (k0 + BK > K) : (o0 + R > dout);
+        const int lim = KC ? (K - k0) : (dout - o0);
+        const int w = tid >> 6;
+#pragma unroll
+        for (int j = 0; j < PER_WAVE; ++j) {
+            const uint32_t off = keep(j, tail, lim) == VE ? voff[j] : 0x80000000u;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + (w + j * NW) * 1024), 16, int(off), 0, 0, 0);
+        }
+    }
+
+    // After the stage's loads have landed: write the partly-inside chunks of
+    // an edge slab element by element.
+    __device__ __forceinline__ void fix_edge(int it, int k0, int K, int o0, int dout, unsigned char* lds,
+                                             int tid) const {
+        const bool tail = KC ? (k0 + BK > K) : (o0 + R > dout);
+        if (!tail) return;
+        const int lim = KC ? (K - k0) : (dout - o0);
+        const __amdgpu_buffer_rsrc_t rs = rsrc(it);
+        const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+        for (int j = 0; j < PER_WAVE; ++j) {
+            const int kp = keep(j, tail, lim);
+            if (kp > 0 && kp < VE) {
+                uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int e = 0; e < VE; ++e) {
+                    if (e < kp) {
+                        const int off = int(voff[j]) + e * EB;
+                        if constexpr (EB == 4) {
+                            v[e] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                        } else if constexpr (EB == 2) {
+                            v[e >> 1] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0)) << (16 * (e & 1));
+                        } else {
+                            v[e >> 2] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0)) << (8 * (e & 3));
+                        }
+                    }
+                }
+                *reinterpret_cast<u32x4*>(lds + (w + j * NW) * 1024 + lane * 16) = u32x4{v[0], v[1], v[2], v[3]};
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------------------ LDS fragment reads
+
+// 16 bytes = 8 k-values of one row of a K-contiguous slab, chunk q (0..7).
+__device__ __forceinline__ u32x4 lds_row_chunk(const unsigned char* lds, int row, int q) {
+    return *reinterpret_cast<const u32x4*>(lds + row * 128 + ((q ^ (row & 7)) << 4));
+}
+
+// Byte address of element (k, col) of an MN-contiguous slab.
+template <int EB>
+__device__ __forceinline__ int mn_addr(int k, int col) {
+    constexpr int VE = 16 / EB;
+    return k * 512 + (((col / VE) ^ swz<EB, false>(k)) << 4) + (col % VE) * EB;
+}
+
+// Eight consecutive k (kb .. kb+7) of column (ob + lane % 32) of an MN-contiguous
+// 16-bit slab, via two LDS transpose reads of four k each.  Within each group
+// of 16 lanes the transpose read returns, to lane i, element i mod 4 of the
+// 8-byte words fetched by lanes 4e + i / 4 (e = 0..3); so lane j of the group
+// fetches row kb + j / 4, columns 4 (j mod 4) .. +3 of its 16-column half.
+__device__ __forceinline__ u32x4 lds_tr16(const unsigned char* lds, int kb, int ob, int lane) {
+    const int sub = lane & 15, h = lane >> 4;
+    const int col = ob + 16 * (h & 1) + 4 * (sub & 3);
+    const int k = kb + (sub >> 2);
+    typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+    lds_i16x4* p0 = (lds_i16x4*)(lds + mn_addr<2>(k, col));
+    lds_i16x4* p1 = (lds_i16x4*)(lds + mn_addr<2>(k + 4, col));
+    const i16x4 v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(p0);
+    const i16x4 v1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(p1);
+    const u32x2 a = __builtin_bit_cast(u32x2, v0);
+    const u32x2 b = __builtin_bit_cast(u32x2, v1);
+    return u32x4{a.x, a.y, b.x, b.y};
+}
+
+// ------------------------------------------------------------------ MFMA
+
+template <int DT>
+__device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f32x16& c) {
+    if constexpr (DT == DT_BF16) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    } else {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+    }
+}
+
+// ------------------------------------------------------------------ output conversion
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+template <int OUT>
+__device__ __forceinline__ uint16_t f32_to_half(float x) {
+    if constexpr (OUT == DT_BF16) return f32_to_bf16_rne(x);
+    else return __builtin_bit_cast(uint16_t, _Float16(x));
+}
+
+template <int OUT>
+__device__ __forceinline__ float half_to_f32(uint16_t h) {
+    if constexpr (OUT == DT_BF16) return __builtin_bit_cast(float, uint32_t(h) << 16);
+    else return float(__builtin_bit_cast(_Float16, h));
+}
+
+template <int OUT>
+__device__ __forceinline__ float load_c1(const void* C, int64_t off) {
+    if constexpr (OUT == DT_F32) return reinterpret_cast<const float*>(C)[off];
+    else return half_to_f32<OUT>(reinterpret_cast<const uint16_t*>(C)[off]);
+}
+
+template <int OUT>
+__device__ __forceinline__ void store_c1(void* C, int64_t off, float v) {
+    if constexpr (OUT == DT_F32) reinterpret_cast<float*>(C)[off] = v;
+    else reinterpret_cast<uint16_t*>(C)[off] = f32_to_half<OUT>(v);
+}
+
+// ------------------------------------------------------------------ the kernel
+
+template <int DT, bool AKC, bool BKC>
+struct Gemm {
+    static constexpr int EB = Cfg<DT>::EB, BM = Cfg<DT>::BM, BN = Cfg<DT>::BN, BK = Cfg<DT>::BK;
+    static constexpr int WM = Cfg<DT>::WM, WN = Cfg<DT>::WN, THREADS = 64 * WM * WN, NW = WM * WN;
+    static constexpr int WTM = BM / WM, WTN = BN / WN;    // wave tile
+    static constexpr int FM = WTM / 32, FN = WTN / 32;    // 32x32 MFMA blocks per wave
+    using SA = Slab<EB, BM, BK, AKC, THREADS>;
+    using SB = Slab<EB, BN, BK, BKC, THREADS>;
+    static constexpr int STAGE = SA::BYTES + SB::BYTES;
+    static_assert(2 * STAGE <= 160 * 1024, "LDS budget");
+
+    struct Acc { f32x16 v[FM][FN]; };
+
+    // MFMAs over one staged k-slab.
+    static __device__ __forceinline__ void compute(const unsigned char* As, const unsigned char* Bs,
+                                                   Acc& acc, int wm, int wn, int lane) {
+        const int g = lane >> 5, l32 = lane & 31;
+        if constexpr (DT == DT_BF16 || DT == DT_F16) {
+#pragma unroll
+            for (int s = 0; s < BK / 16; ++s) {
+                u32x4 af[FM], bf[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    if constexpr (AKC) af[i] = lds_row_chunk(As, wm * WTM + i * 32 + l32, 2 * s + g);
+                    else af[i] = lds_tr16(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    if constexpr (BKC) bf[j] = lds_row_chunk(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
+                    else bf[j] = lds_tr16(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(af[i], bf[j], acc.v[i][j]);
+                // Keep each step's fragment reads next to its MFMAs: hoisting all
+                // steps' reads would need more registers than the accumulators leave.
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if constexpr (DT == DT_F32) {
+            // Lane group g handles k = 8c + 4g + u of step (c, u).
+#pragma unroll
+            for (int c = 0; c < BK / 8; ++c) {
+                f32x4 af[FM], bf[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int row = wm * WTM + i * 32 + l32;
+                    if constexpr (AKC) {
+                        af[i] = __builtin_bit_cast(f32x4, lds_row_chunk(As, row, 2 * c + g));
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            af[i][u] = *reinterpret_cast<const float*>(As + mn_addr<4>(8 * c + 4 * g + u, row));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int col = wn * WTN + j * 32 + l32;
+                    if constexpr (BKC) {
+                        bf[j] = __builtin_bit_cast(f32x4, lds_row_chunk(Bs, col, 2 * c + g));
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            bf[j][u] = *reinterpret_cast<const float*>(Bs + mn_addr<4>(8 * c + 4 * g + u, col));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc.v[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][u], bf[j][u], acc.v[i][j], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            static_assert(AKC && BKC, "FP8 operands must be K-contiguous");
+            // Lane group g handles k = 64s + 32g .. +31 of step s (two chunks).
+#pragma unroll
+            for (int s = 0; s < BK / 64; ++s) {
+                i32x8 af[FM], bf[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int row = wm * WTM + i * 32 + l32;
+                    const u32x4 lo = lds_row_chunk(As, row, 4 * s + 2 * g);
+                    const u32x4 hi = lds_row_chunk(As, row, 4 * s + 2 * g + 1);
+                    af[i] = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int row = wn * WTN + j * 32 + l32;
+                    const u32x4 lo = lds_row_chunk(Bs, row, 4 * s + 2 * g);
+                    const u32x4 hi = lds_row_chunk(Bs, row, 4 * s + 2 * g + 1);
+                    bf[j] = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
+                }
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc.v[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            af[i], bf[j], acc.v[i][j], 0, 0, 0, 127, 0, 127);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    // One step of the MAC loop: start the loads of iteration kk+1 (if any) into
+    // stage `nx`, run the MFMAs of stage `cu`, then wait for the loads and
+    // synchronise.  Stages are distinct LDS objects, so the compiler can see
+    // that the loads in flight do not touch the stage being read.
+    static __device__ __forceinline__ bool step(const KArgs& a, const SA& sa, const SB& sb, int kk, int klo,
+                                                int khi, int m0, int n0, unsigned char* cu, unsigned char* nx,
+                                                Acc& acc, int tid) {
+        const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
+        const bool more = kk + 1 < khi;
+        if (more) {
+            sa.issue(kk + 1 - klo, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
+            sb.issue(kk + 1 - klo, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+        }
+        compute(cu, cu + SA::BYTES, acc, wm, wn, lane);
+        if (more) {
+            wait_vmem();
+            sa.fix_edge(kk + 1 - klo, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
+            sb.fix_edge(kk + 1 - klo, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+        }
+        __syncthreads();
+        return more;
+    }
+
+    // MAC-loop iterations [klo, khi) of one tile into acc (zeroed first).
+    static __device__ __forceinline__ void mac_loop(const KArgs& a, unsigned char* s0, unsigned char* s1,
+                                                    int tile, int klo, int khi, Acc& acc, int tid) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc.v[i][j] = f32x16{0};
+        if (klo >= khi) return;
+        const int m0 = (tile / a.tn) * BM, n0 = (tile % a.tn) * BN;
+        SA sa;
+        SB sb;
+        sa.init(a.A, a.lda, m0, a.M, klo, a.K, tid);
+        sb.init(a.B, a.ldb, n0, a.N, klo, a.K, tid);
+        __syncthreads();   // the previous segment's epilogue may still be using LDS
+        sa.issue(0, klo * BK, a.K, m0, a.M, s0, tid);
+        sb.issue(0, klo * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
+        wait_vmem();
+        sa.fix_edge(0, klo * BK, a.K, m0, a.M, s0, tid);
+        sb.fix_edge(0, klo * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
+        __syncthreads();
+        for (int kk = klo;; kk += 2) {
+            if (!step(a, sa, sb, kk, klo, khi, m0, n0, s0, s1, acc, tid)) break;
+            if (!step(a, sa, sb, kk + 1, klo, khi, m0, n0, s1, s0, acc, tid)) break;
+        }
+    }
+
+    // Partial tiles are stored in fragment order: float4 group q of thread tid
+    // at slot[(q * THREADS + tid) * 4], so each store instruction of the
+    // workgroup writes THREADS * 16 bytes contiguously and the reader uses the
+    // same mapping.
+    static __device__ __forceinline__ void store_partial(float* slot, const Acc& acc, int tid) {
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r, ++q) {
+                    const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
+                                     acc.v[i][j][4 * r + 3]};
+                    *reinterpret_cast<f32x4*>(slot + ((size_t)q * THREADS + tid) * 4) = v;
+                }
+    }
+
+    static __device__ __forceinline__ void add_partial(const float* slot, Acc& acc, int tid) {
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r, ++q) {
+                    const f32x4 v = *reinterpret_cast<const f32x4*>(slot + ((size_t)q * THREADS + tid) * 4);
+                    acc.v[i][j][4 * r] += v.x;
+                    acc.v[i][j][4 * r + 1] += v.y;
+                    acc.v[i][j][4 * r + 2] += v.z;
+                    acc.v[i][j][4 * r + 3] += v.w;
+                }
+    }
+
+    // C = alpha * s_A * s_B * acc + beta * C over the tile.  Each wave stages
+    // one 32-row band of its block at a time in its own LDS area (FP32, rows
+    // padded by 8 floats; waves of the first half use stage 0, the others
+    // stage 1), then every lane converts eight consecutive columns of one row
+    // and writes them with one store, predicated at the M and N edges.  The
+    // caller guarantees all waves have left the MAC loop's LDS.
+    static constexpr int EPI_LD = WTN + 8;
+    static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
+    static_assert(EPI_BYTES * (NW / 2) <= STAGE, "epilogue staging must fit in one stage");
+    static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
+
+    template <int OUT>
+    static __device__ __forceinline__ void epilogue_t(const KArgs& a, int tile, const Acc& acc, int tid,
+                                                      unsigned char* s0, unsigned char* s1) {
+        const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
+        const int g = lane >> 5, l32 = lane & 31;
+        const int m0 = (tile / a.tn) * BM + wm * WTM, n0 = (tile % a.tn) * BN + wn * WTN;
+        float* st = reinterpret_cast<float*>((w < NW / 2 ? s0 : s1) + (w % (NW / 2)) * EPI_BYTES);
+        float s = a.alpha;
+        if (a.scale_a) s *= *a.scale_a;
+        if (a.scale_b) s *= *a.scale_b;
+        constexpr int LPR = WTN / 8;          // lanes per row
+        constexpr int RPP = 64 / LPR;         // rows per pass
+        const int col = n0 + (lane % LPR) * 8;
+        const int ncol = min(max(a.N - col, 0), 8);
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int pass = 0; pass < 32 / RPP; ++pass) {
+                const int rl = pass * RPP + lane / LPR;
+                const int row = m0 + i * 32 + rl;
+                const f32x4 lo = *reinterpret_cast<const f32x4*>(st + rl * EPI_LD + (lane % LPR) * 8);
+                const f32x4 hi = *reinterpret_cast<const f32x4*>(st + rl * EPI_LD + (lane % LPR) * 8 + 4);
+                const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                if (row < a.M && ncol > 0) {
+                    const int64_t off = (int64_t)row * a.ldc + col;
+                    if (ncol == 8) {
+                        if constexpr (OUT == DT_F32) {
+                            f32x4* cp = reinterpret_cast<f32x4*>(reinterpret_cast<float*>(a.C) + off);
+                            f32x4 o0 = {v[0], v[1], v[2], v[3]}, o1 = {v[4], v[5], v[6], v[7]};
+                            o0 *= s;
+                            o1 *= s;
+                            if (a.beta != 0.0f) {
+                                o0 += a.beta * cp[0];
+                                o1 += a.beta * cp[1];
+                            }
+                            cp[0] = o0;
+                            cp[1] = o1;
+                        } else {
+                            u32x4* cp = reinterpret_cast<u32x4*>(reinterpret_cast<uint16_t*>(a.C) + off);
+                            float cin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                            if (a.beta != 0.0f) {
+                                const u32x4 cv = *cp;
+#pragma unroll
+                                for (int e = 0; e < 8; ++e)
+                                    cin[e] = half_to_f32<OUT>(uint16_t(cv[e >> 1] >> (16 * (e & 1))));
+                            }
+                            u32x4 o;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float x0 = s * v[2 * e] + a.beta * cin[2 * e];
+                                const float x1 = s * v[2 * e + 1] + a.beta * cin[2 * e + 1];
+                                o[e] = uint32_t(f32_to_half<OUT>(x0)) | (uint32_t(f32_to_half<OUT>(x1)) << 16);
+                            }
+                            *cp = o;
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            if (e < ncol) {
+                                float x = s * v[e];
+                                if (a.beta != 0.0f) x += a.beta * load_c1<OUT>(a.C, off + e);
+                                store_c1<OUT>(a.C, off + e, x);
+                            }
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+
+    static __device__ __forceinline__ void epilogue(const KArgs& a, int tile, const Acc& acc, int tid,
+                                                    unsigned char* s0, unsigned char* s1) {
+        if (a.out_dtype == DT_F32) epilogue_t<DT_F32>(a, tile, acc, tid, s0, s1);
+        else if (a.out_dtype == DT_BF16) epilogue_t<DT_BF16>(a, tile, acc, tid, s0, s1);
+        else epilogue_t<DT_F16>(a, tile, acc, tid, s0, s1);
+    }
+
+    static __device__ __forceinline__ int share_start(int x, int q, int r) { return x * q + min(x, r); }
+
+    static __device__ __forceinline__ int owner_of(int i, int q, int r) {
+        return (i < r * (q + 1)) ? i / (q + 1) : r + (i - r * (q + 1)) / q;
+    }
+
+    static __device__ __forceinline__ void run(const KArgs& a, unsigned char* s0, unsigned char* s1) {
+        const int tid = threadIdx.x;
+        const int wg = blockIdx.x;
+        int sk_it = 0, sk_end = 0;
+        if (wg < a.g_sk) {
+            sk_it = share_start(wg, a.sk_q, a.sk_r);
+            sk_end = share_start(wg + 1, a.sk_q, a.sk_r);
+        }
+        int dp_tile = a.sk_tiles + wg;
+        int seq = 0;
+        Acc acc;
+        for (;;) {
+            const bool sk_left = sk_it < sk_end, dp_left = dp_tile < a.t;
+            if (!sk_left && !dp_left) break;
+            const bool take_sk = a.sk_first ? sk_left : !dp_left;
+            int tile, lo, hi, role, peer_end = -1;
+            if (take_sk) {
+                tile = sk_it / a.ipt;
+                const int first = tile * a.ipt, last = first + a.ipt;
+                lo = sk_it - first;
+                hi = min(sk_end, last) - first;
+                if (sk_it != first) {
+                    role = ROLE_PARTIAL;
+                } else if (sk_end < last) {
+                    role = ROLE_OWNER;
+                    peer_end = owner_of(last - 1, a.sk_q, a.sk_r);
+                } else {
+                    role = ROLE_FULL;
+                }
+                sk_it = last;
+            } else {
+                tile = dp_tile;
+                lo = 0;
+                hi = a.ipt;
+                role = ROLE_FULL;
+                dp_tile += a.grid;
+            }
+            if (a.trace && tid == 0 && seq < a.trace_per_wg) {
+                int32_t* rec = a.trace + ((size_t)wg * a.trace_per_wg + seq) * kTraceFields;
+                rec[0] = wg; rec[1] = seq; rec[2] = tile; rec[3] = lo; rec[4] = hi; rec[5] = role;
+                rec[6] = role == ROLE_OWNER ? wg + 1 : -1;
+                rec[7] = role == ROLE_OWNER ? peer_end : -1;
+            }
+            ++seq;
+
+            mac_loop(a, s0, s1, tile, lo, hi, acc, tid);
+
+            if (role == ROLE_PARTIAL) {
+                store_partial(a.partials + (size_t)wg * (BM * BN), acc, tid);
+                __threadfence();          // this thread's partial stores, visible device-wide
+                __syncthreads();
+                if (tid == 0)
+                    __hip_atomic_store(a.flags + (size_t)wg * kFlagStrideInts, 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                if (role == ROLE_OWNER) {
+                    for (int peer = wg + 1; peer <= peer_end; ++peer) {
+                        int32_t* flag = a.flags + (size_t)peer * kFlagStrideInts;
+                        if (tid == 0) {
+                            int spins = 0;
+                            while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                                __builtin_amdgcn_s_sleep(2);
+                                if (++spins > a.spin_limit) {
+                                    __hip_atomic_store(a.err, kErrTimeout, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                    break;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        __threadfence();      // acquire side for every reading thread
+                        add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);
+                        if (tid == 0) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                epilogue(a, tile, acc, tid, s0, s1);
+            }
+        }
+    }
+};
+
+template <int DT, bool AKC, bool BKC>
+__global__ void __launch_bounds__(kThreadsOf<DT>) skgemm_kernel(KArgs a) {
+    using G = Gemm<DT, AKC, BKC>;
+    __shared__ __attribute__((aligned(1024))) unsigned char stage0[G::STAGE];
+    __shared__ __attribute__((aligned(1024))) unsigned char stage1[G::STAGE];
+    G::run(a, stage0, stage1);
+}
+
+}  // namespace skg

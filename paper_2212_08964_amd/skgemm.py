@@ -1,0 +1,280 @@
+"""ctypes binding of libskgemm.so (the C ABI in include/skgemm.h).
+
+Argument marshalling only: every step of the GEMM runs in the library's HIP
+kernels.  The functions mirror the C entry points by name; ``matmul`` adds
+the torch-tensor convenience layer (layouts from strides, the current HIP
+stream, a cached zero-filled workspace per device).
+
+Loading fails loudly when the library has not been built: there is no other
+execution path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libskgemm.so")
+
+# enums of include/skgemm.h
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CAPACITY, ERR_HIP, ERR_TIMEOUT = range(7)
+ROW_MAJOR, COL_MAJOR = 0, 1
+F32, F16, BF16, F8E4M3 = 0, 1, 2, 3
+POLICY = {"auto": 0, "dp": 1, "sk": 2, "dp_1tile_sk": 3, "2tile_sk_dp": 4}
+POLICY_NAME = {v: k for k, v in POLICY.items()}
+ROLE_NAME = {0: "full", 1: "partial", 2: "owner"}
+
+EXPORTED = [
+    "skgemm_default_options", "skgemm_plan", "skgemm_workspace_size", "skgemm_run",
+    "skgemm_trace_capacity", "skgemm_run_traced", "skgemm_plan_info", "skgemm_model_constants",
+    "skgemm_schedule", "skgemm_check_device_error", "skgemm_plan_destroy", "skgemm_status_string",
+]
+
+INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
+               "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int), ("force_g", ctypes.c_int32), ("tile_m", ctypes.c_int32),
+                ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
+                ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
+
+
+class SkgemmError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})" if what else status_string(status))
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2212_08964_amd/build.py")
+                L = ctypes.CDLL(LIB_PATH)
+                vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+                P = ctypes.POINTER
+                L.skgemm_default_options.argtypes = [P(Options)]
+                L.skgemm_default_options.restype = None
+                L.skgemm_plan.argtypes = [P(vp), i64, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Options)]
+                L.skgemm_workspace_size.argtypes = [vp, P(sz)]
+                L.skgemm_run.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_float, ctypes.c_float,
+                                         vp, vp, vp, sz, vp]
+                L.skgemm_trace_capacity.argtypes = [vp, P(sz)]
+                L.skgemm_run_traced.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_float, ctypes.c_float,
+                                                vp, vp, vp, sz, vp, sz, vp]
+                L.skgemm_plan_info.argtypes = [vp, P(i64), i32]
+                L.skgemm_model_constants.argtypes = [vp, P(ctypes.c_double)]
+                L.skgemm_schedule.argtypes = [vp, vp, sz, P(sz)]
+                L.skgemm_check_device_error.argtypes = [vp, vp]
+                L.skgemm_plan_destroy.argtypes = [vp]
+                L.skgemm_status_string.argtypes = [ctypes.c_int]
+                L.skgemm_status_string.restype = ctypes.c_char_p
+                for name in EXPORTED:
+                    if name not in ("skgemm_default_options", "skgemm_status_string"):
+                        getattr(L, name).restype = ctypes.c_int
+                _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().skgemm_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise SkgemmError(status, what)
+
+
+def default_options() -> Options:
+    o = Options()
+    lib().skgemm_default_options(ctypes.byref(o))
+    return o
+
+
+class Plan:
+    """Owns one skgemm_plan_t."""
+
+    def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0):
+        self._h = ctypes.c_void_p()
+        o = default_options()
+        o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
+        o.force_g = int(force_g)
+        o.hybrid_min_waves = int(hybrid_min_waves)
+        o.num_cus = int(num_cus)
+        o.occupancy = int(occupancy)
+        tc = ta if tc is None else tc
+        _check(lib().skgemm_plan(ctypes.byref(self._h), int(M), int(N), int(K), la, lb, lc, ta, ta, tc,
+                                 ctypes.byref(o)), "skgemm_plan")
+        self.M, self.N, self.K = int(M), int(N), int(K)
+        self.la, self.lb, self.lc, self.ta, self.tc = la, lb, lc, ta, tc
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.skgemm_plan_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().skgemm_workspace_size(self._h, ctypes.byref(n)), "skgemm_workspace_size")
+        return n.value
+
+    def trace_capacity(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().skgemm_trace_capacity(self._h, ctypes.byref(n)), "skgemm_trace_capacity")
+        return n.value
+
+    def info(self) -> dict:
+        buf = (ctypes.c_int64 * 20)()
+        _check(lib().skgemm_plan_info(self._h, buf, 20), "skgemm_plan_info")
+        d = dict(zip(INFO_FIELDS, list(buf)))
+        d["policy_name"] = POLICY_NAME[d["policy"]]
+        return d
+
+    def model_constants(self):
+        buf = (ctypes.c_double * 4)()
+        _check(lib().skgemm_model_constants(self._h, buf), "skgemm_model_constants")
+        return tuple(buf)
+
+    def schedule(self):
+        """Host-side schedule records: list of (wg, seq, tile, lo, hi, role, first_peer, last_peer)."""
+        n = ctypes.c_size_t()
+        _check(lib().skgemm_schedule(self._h, None, 0, ctypes.byref(n)), "skgemm_schedule")
+        buf = (ctypes.c_int32 * (8 * max(1, n.value)))()
+        _check(lib().skgemm_schedule(self._h, buf, n.value, ctypes.byref(n)), "skgemm_schedule")
+        flat = list(buf)
+        return [tuple(flat[8 * i:8 * i + 8]) for i in range(n.value)]
+
+    def run(self, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0, scale_a=None, scale_b=None,
+            workspace=None, ws_bytes=0, stream=None):
+        """Raw pointers (ints) for every buffer; stream is a hipStream_t as int or None."""
+        _check(lib().skgemm_run(self._h, A, int(lda), B, int(ldb), C, int(ldc), float(alpha), float(beta),
+                                scale_a, scale_b, workspace, int(ws_bytes), stream), "skgemm_run")
+
+    def run_traced(self, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes,
+                   trace, trace_records, stream=None):
+        _check(lib().skgemm_run_traced(self._h, A, int(lda), B, int(ldb), C, int(ldc), float(alpha),
+                                       float(beta), scale_a, scale_b, workspace, int(ws_bytes), trace,
+                                       int(trace_records), stream), "skgemm_run_traced")
+
+
+def check_device_error(workspace_ptr, stream=None):
+    _check(lib().skgemm_check_device_error(workspace_ptr, stream), "skgemm_check_device_error")
+
+
+# ---------------------------------------------------------------- torch layer
+
+_TORCH_DT = None
+
+
+def _torch_dtypes():
+    global _TORCH_DT
+    if _TORCH_DT is None:
+        import torch
+        _TORCH_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16,
+                     torch.float8_e4m3fn: F8E4M3}
+    return _TORCH_DT
+
+
+def _layout(t):
+    """(layout, ld) of a 2-D tensor, or None if neither dimension is contiguous."""
+    r, c = t.shape
+    s0, s1 = t.stride()
+    if s1 == 1 or c <= 1:
+        return ROW_MAJOR, max(s0, c, 1)
+    if s0 == 1 or r <= 1:
+        return COL_MAJOR, max(s1, r, 1)
+    return None
+
+
+_ws_cache = {}
+_plan_cache = {}
+
+
+def workspace(nbytes: int, device):
+    """A zero-filled, 256-byte aligned device workspace of at least nbytes,
+    cached per device (runs on one device must not overlap in time)."""
+    import torch
+    key = torch.device(device).index
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2):
+    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves)
+    p = _plan_cache.get(key)
+    if p is None:
+        p = Plan(M, N, K, la, lb, lc, ta, tc, policy=policy, force_g=force_g, hybrid_min_waves=hybrid_min_waves)
+        if len(_plan_cache) > 4096:
+            _plan_cache.clear()
+        _plan_cache[key] = p
+    return p
+
+
+def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None, scale_b=None,
+           policy="auto", force_g=0, hybrid_min_waves=2, trace=None):
+    """C = alpha * s_A * s_B * A @ B + beta * C on torch tensors (2-D, on one GPU).
+
+    Layouts come from the strides (a non-contiguous operand is copied).  When
+    ``out`` is given it receives the result and supplies C for beta != 0.
+    ``trace``, when given, is an int32 device tensor of at least
+    8 * plan.trace_capacity() elements that receives the schedule records."""
+    import torch
+    dts = _torch_dtypes()
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("matmul needs A (M x K) and B (K x N)")
+    if A.dtype != B.dtype or A.dtype not in dts:
+        raise ValueError(f"unsupported input dtypes {A.dtype}, {B.dtype}")
+    if not A.is_cuda or A.device != B.device:
+        raise ValueError("operands must live on the same GPU")
+    M, K = A.shape
+    N = B.shape[1]
+    la = _layout(A)
+    if la is None:
+        A = A.contiguous()
+        la = _layout(A)
+    lb = _layout(B)
+    if lb is None:
+        B = B.contiguous()
+        lb = _layout(B)
+    if out is None:
+        if out_dtype is None:
+            out_dtype = torch.float32 if A.dtype in (torch.float32, torch.float8_e4m3fn) else A.dtype
+        out = torch.empty((M, N), dtype=out_dtype, device=A.device)
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+    lc = _layout(out)
+    if lc is None or out.shape != (M, N):
+        raise ValueError("out must be an M x N tensor with one contiguous dimension")
+    plan = get_plan(M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy, force_g, hybrid_min_waves)
+    nws = plan.workspace_size()
+    ws = workspace(nws, A.device) if nws else None
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    args = (A.data_ptr() if A.numel() else None, la[1], B.data_ptr() if B.numel() else None, lb[1],
+            out.data_ptr() if out.numel() else None, lc[1], alpha, beta,
+            scale_a.data_ptr() if scale_a is not None else None,
+            scale_b.data_ptr() if scale_b is not None else None,
+            ws.data_ptr() if ws is not None else None, nws)
+    if trace is None:
+        plan.run(*args, stream=stream)
+    else:
+        plan.run_traced(*args, trace.data_ptr(), trace.numel() // 8, stream=stream)
+    return out

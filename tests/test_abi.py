@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI (no GPU compute calls).
+
+* libskgemm.so loads and exports every function include/skgemm.h declares;
+* argument errors are reported as status codes before anything launches;
+* the planner's host-side schedule equals the oracle enumerator's, record by
+  record, over many shapes, policies, grid sizes and processor widths.
+"""
+import ctypes
+import itertools
+import os
+import re
+
+import pytest
+
+from helpers import POLICY_BY_ID, oracle_plan_for, records_to_schedule
+from oracle import schedule as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2212_08964_amd import skgemm
+    return skgemm
+
+
+def test_library_exports_every_declared_symbol():
+    sk = _lib()
+    L = sk.lib()
+    header = open(os.path.join(ROOT, "include", "skgemm.h")).read()
+    names = set(re.findall(r"^\s*(?:const char\*|void|skgemm_status_t)\s+(skgemm_\w+)\s*\(", header, re.M))
+    assert len(names) >= 12
+    for n in sorted(names):
+        assert hasattr(L, n), f"missing export {n}"
+    assert set(sk.EXPORTED) == names
+
+
+def test_plan_argument_errors():
+    sk = _lib()
+    L = sk.lib()
+    h = ctypes.c_void_p()
+    o = sk.default_options()
+    o.num_cus, o.occupancy = 256, 1
+    bad = [
+        (-1, 4, 4, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16, sk.ERR_INVALID_ARG),
+        (4, 4, 4, 2, 0, 0, sk.BF16, sk.BF16, sk.BF16, sk.ERR_INVALID_ARG),
+        (4, 4, 4, 0, 0, 0, sk.BF16, sk.F16, sk.BF16, sk.ERR_UNSUPPORTED),
+        (4, 4, 4, 0, 0, 0, sk.F32, sk.F32, sk.BF16, sk.ERR_UNSUPPORTED),
+        (4, 4, 4, 0, 0, 0, sk.F8E4M3, sk.F8E4M3, sk.F32, sk.ERR_UNSUPPORTED),   # FP8 needs B column-major
+        (4, 4, 4, 0, 0, 0, sk.BF16, sk.BF16, sk.F8E4M3, sk.ERR_UNSUPPORTED),
+        (1 << 31, 4, 4, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16, sk.ERR_INVALID_ARG),
+    ]
+    for M, N, K, la, lb, lc, ta, tb, tc, want in bad:
+        assert L.skgemm_plan(ctypes.byref(h), M, N, K, la, lb, lc, ta, tb, tc, ctypes.byref(o)) == want
+    assert L.skgemm_plan(None, 4, 4, 4, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16, None) == sk.ERR_INVALID_ARG
+    # a Stream-K grid beyond the co-resident capacity is refused
+    o.policy, o.force_g = sk.POLICY["sk"], 300
+    assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                         ctypes.byref(o)) == sk.ERR_CAPACITY
+    o.tile_m = 64
+    o.force_g = 0
+    assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                         ctypes.byref(o)) == sk.ERR_UNSUPPORTED
+
+
+def test_run_argument_errors_before_launch():
+    sk = _lib()
+    p = sk.Plan(300, 200, 100, ta=sk.BF16, policy="sk", num_cus=256, occupancy=1)
+    ws = p.workspace_size()
+    assert ws > 0
+    fake = 1 << 40   # never dereferenced: every call below fails its host checks first
+    cases = [
+        dict(lda=99, ldb=200, ldc=200, ws=fake, wsb=ws, want=sk.ERR_INVALID_ARG),    # lda < K
+        dict(lda=100, ldb=199, ldc=200, ws=fake, wsb=ws, want=sk.ERR_INVALID_ARG),   # ldb < N
+        dict(lda=100, ldb=200, ldc=199, ws=fake, wsb=ws, want=sk.ERR_INVALID_ARG),   # ldc < N
+        dict(lda=100, ldb=200, ldc=200, ws=None, wsb=ws, want=sk.ERR_WORKSPACE),
+        dict(lda=100, ldb=200, ldc=200, ws=fake, wsb=ws - 1, want=sk.ERR_WORKSPACE),
+        dict(lda=100, ldb=200, ldc=200, ws=fake + 16, wsb=ws, want=sk.ERR_WORKSPACE),  # misaligned
+    ]
+    for c in cases:
+        st = sk.lib().skgemm_run(p.handle, fake, c["lda"], fake, c["ldb"], fake, c["ldc"], 1.0, 0.0,
+                                 None, None, c["ws"], c["wsb"], None)
+        assert st == c["want"], c
+    st = sk.lib().skgemm_run(p.handle, fake, 100, fake, 200, None, 200, 1.0, 0.0, None, None, fake, ws, None)
+    assert st == sk.ERR_INVALID_ARG
+    z = sk.Plan(0, 200, 100, ta=sk.BF16, num_cus=256, occupancy=1)
+    assert sk.lib().skgemm_run(z.handle, None, 100, None, 200, None, 200, 1.0, 0.0, None, None, None, 0,
+                               None) == sk.OK
+    assert sk.status_string(sk.ERR_TIMEOUT) != sk.status_string(sk.OK)
+
+
+SHAPES = [(384, 384, 1024), (896, 384, 128), (1, 1, 1), (300, 500, 700), (4096, 4096, 64), (128, 8192, 8192),
+          (2048, 2048, 8192), (8192, 8192, 8192), (1000, 130, 5), (7, 3000, 4000), (513, 257, 0),
+          (256 * 17, 256 * 16, 1000), (256 * 33, 256 * 9, 300)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("policy", ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
+def test_planner_schedule_matches_enumerator(dtype, policy):
+    sk = _lib()
+    ta = {"f32": sk.F32, "bf16": sk.BF16}[dtype]
+    for (M, N, K), (cus, occ), lc in itertools.product(SHAPES, [(256, 1), (256, 2), (4, 1), (37, 3)],
+                                                       [sk.ROW_MAJOR, sk.COL_MAJOR]):
+        try:
+            p = sk.Plan(M, N, K, ta=ta, lc=lc, policy=policy, num_cus=cus, occupancy=occ)
+        except sk.SkgemmError as e:
+            assert e.status == sk.ERR_CAPACITY
+            continue
+        info = p.info()
+        ref = oracle_plan_for(info, p.model_constants(), policy)
+        assert (ref.policy, ref.sk_tiles, ref.g_sk, ref.grid, ref.sk_first) == (
+            POLICY_BY_ID[info["policy"]], info["sk_tiles"], info["g_sk"], info["grid"], bool(info["sk_first"]))
+        got = records_to_schedule(p.schedule(), info["grid"])
+        want = S.enumerate_schedule(ref)
+        assert got == want, (M, N, K, cus, occ, policy)
+        if info["t"]:
+            S.check_invariants(ref, got)
+        assert p.trace_capacity() == info["grid"] * max([len(s) for s in want] + [0])
+
+
+@pytest.mark.parametrize("g", [1, 2, 3, 5, 9, 16, 36, 100, 288, 300])
+def test_planner_forced_grid_matches_enumerator(g):
+    sk = _lib()
+    p = sk.Plan(384, 384, 1024, ta=sk.F32, policy="sk", force_g=g, num_cus=256, occupancy=2)
+    info = p.info()
+    ref = oracle_plan_for(info, p.model_constants(), "sk", force_g=g)
+    got = records_to_schedule(p.schedule(), info["grid"])
+    assert got == S.enumerate_schedule(ref)
+    S.check_invariants(ref, got)
+
+
+def test_workspace_scales_with_grid_not_problem():
+    sk = _lib()
+    small = sk.Plan(300, 300, 4096, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1)
+    big = sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1)
+    assert small.workspace_size() == big.workspace_size()
+    dp = sk.Plan(3000, 3000, 4096, ta=sk.BF16, policy="dp", num_cus=256, occupancy=1)
+    assert dp.workspace_size() == 0

@@ -1,0 +1,247 @@
+"""GPU parity of the Stream-K GEMM against the FP64 oracle (through the C ABI).
+
+Tolerances (relative Frobenius error against the float64 oracle of the stored
+inputs): FP32 1e-5; BF16/FP16 inputs with FP32 output 1e-5 (accumulation
+only); BF16/FP16 output 1e-2 (includes the output rounding).  Integer-valued
+inputs are exact in FP32 accumulation and fix-up, so those results must be
+bit-identical to the oracle under every policy and grid size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from helpers import oracle_plan_for, records_to_schedule, to_f64
+from oracle import gemm as og
+from oracle import schedule as S
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+TOL_16_OUT32 = 1e-5
+TOL_16 = 1e-2
+
+POLICIES = ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"]
+
+
+def sk():
+    from paper_2212_08964_amd import skgemm
+    return skgemm
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def mm(A, B, **kw):
+    out = sk().matmul(A, B, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle(A, B, alpha=1.0, beta=0.0, C=None):
+    Cin = to_f64(C) if C is not None else None
+    return og.gemm_f64(to_f64(A), to_f64(B), alpha, beta, Cin)
+
+
+def rel(x, ref):
+    return og.rel_frobenius(to_f64(x), ref)
+
+
+# ------------------------------------------------------------------ FP32 quantisation case
+
+def test_plain_f32_all_policies():
+    a, b = W.plain_f32(seed=0)
+    A = torch.from_numpy(a).to(dev())
+    B = torch.from_numpy(b).to(dev())
+    ref = og.gemm_f64(a, b)
+    bound = (384 * 2.0 ** -24) * (np.abs(a).astype(np.float64) @ np.abs(b).astype(np.float64)) * 1.01
+    for pol in POLICIES:
+        C = mm(A, B, policy=pol)
+        assert rel(C, ref) <= TOL_F32, pol
+        assert np.all(np.abs(to_f64(C) - ref) <= bound * (1024 / 384)), pol
+
+
+def _capacity(M, N, K, ta):
+    return sk().Plan(M, N, K, ta=ta, tc=ta if ta != sk().BF16 else sk().F32, policy="dp").info()["p"]
+
+
+@pytest.mark.parametrize("g", [1, 2, 9, 16, 36, 64, 100, 200, 256, 288, 500])
+def test_integer_f32_bit_exact_every_grid(g):
+    """g up to the co-resident capacity p; g > 288 (= total iterations) leaves
+    some workgroups without work."""
+    if g > _capacity(384, 384, 1024, sk().F32):
+        pytest.skip("grid larger than the co-resident capacity of this GPU")
+    a, b = W.plain_f32(seed=0, integer=True)
+    A = torch.from_numpy(a).to(dev())
+    B = torch.from_numpy(b).to(dev())
+    ref = og.gemm_f64(a, b)
+    C = mm(A, B, policy="sk", force_g=g)
+    assert np.array_equal(to_f64(C), ref)
+
+
+def test_capacity_refused_beyond_resident():
+    p = _capacity(384, 384, 1024, sk().F32)
+    with pytest.raises(sk().SkgemmError) as e:
+        sk().Plan(384, 384, 1024, ta=sk().F32, policy="sk", force_g=p + 1)
+    assert e.value.status == sk().ERR_CAPACITY
+
+
+def test_integer_f32_bit_exact_every_policy():
+    a, b = W.plain_f32(seed=0, integer=True)
+    A = torch.from_numpy(a).to(dev())
+    B = torch.from_numpy(b).to(dev())
+    ref = og.gemm_f64(a, b)
+    for pol in POLICIES:
+        assert np.array_equal(to_f64(mm(A, B, policy=pol)), ref), pol
+
+
+# ------------------------------------------------------------------ schedule parity
+
+def _trace(A, B, policy, force_g=0, out_dtype=None):
+    p = sk().get_plan(A.shape[0], B.shape[1], A.shape[1], 0, 0, 0, sk()._torch_dtypes()[A.dtype],
+                      sk()._torch_dtypes()[out_dtype or A.dtype], policy, force_g, 2)
+    cap = p.trace_capacity()
+    tr = torch.full((max(cap, 1) * 8,), -7, dtype=torch.int32, device=dev())
+    mm(A, B, policy=policy, force_g=force_g, trace=tr, out_dtype=out_dtype)
+    recs = tr.cpu().numpy().reshape(-1, 8)
+    info = p.info()
+    recs = [tuple(int(v) for v in r) for r in recs if r[0] != -7]
+    return p, info, recs
+
+
+@pytest.mark.parametrize("shape,policy,g", [
+    ((384, 384, 1024), "auto", 0), ((384, 384, 1024), "sk", 4), ((384, 384, 1024), "sk", 36),
+    ((384, 384, 1024), "sk", 200), ((896, 384, 128), "sk", 4), ((896, 384, 128), "2tile_sk_dp", 0),
+    ((2000, 1500, 333), "dp_1tile_sk", 0), ((2000, 1500, 333), "2tile_sk_dp", 0), ((128, 128, 4096), "sk", 0),
+])
+def test_trace_matches_enumerator_f32(shape, policy, g):
+    M, N, K = shape
+    g_ = W.rng(1)
+    A = torch.from_numpy(W.integer_f32(g_, (M, K))).to(dev())
+    B = torch.from_numpy(W.integer_f32(g_, (K, N))).to(dev())
+    p, info, recs = _trace(A, B, policy, g)
+    got = records_to_schedule(recs, info["grid"])
+    ref = oracle_plan_for(info, p.model_constants(), policy, force_g=g)
+    assert got == S.enumerate_schedule(ref)
+
+
+@pytest.mark.parametrize("shape,policy", [((256 * 5 + 7, 256 * 3, 1000), "auto"), ((4096, 4096, 512), "auto"),
+                                          ((300, 3000, 2000), "sk"), ((256 * 17, 256 * 16, 256), "auto")])
+def test_trace_matches_enumerator_bf16(shape, policy):
+    M, N, K = shape
+    A = torch.ones((M, K), dtype=torch.bfloat16, device=dev())
+    B = torch.ones((K, N), dtype=torch.bfloat16, device=dev())
+    p, info, recs = _trace(A, B, policy, 0, out_dtype=torch.float32)
+    got = records_to_schedule(recs, info["grid"])
+    ref = oracle_plan_for(info, p.model_constants(), policy)
+    assert got == S.enumerate_schedule(ref)
+
+
+# ------------------------------------------------------------------ 16-bit inputs
+
+SHAPES16 = [(1, 1, 1), (3, 5, 7), (256, 256, 64), (257, 255, 65), (300, 500, 700), (513, 1031, 129),
+            (1000, 130, 5), (64, 3000, 2048), (640, 768, 4099)]
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+@pytest.mark.parametrize("shape", SHAPES16)
+def test_16bit_parity(dtype, shape):
+    M, N, K = shape
+    a, b = W.normal_pair(M, N, K, seed=M + N + K)
+    A = torch.from_numpy(a).to(dtype).to(dev())
+    B = torch.from_numpy(b).to(dtype).to(dev())
+    ref = oracle(A, B)
+    for pol in ("auto", "dp", "sk"):
+        C32 = mm(A, B, policy=pol, out_dtype=torch.float32)
+        assert rel(C32, ref) <= TOL_16_OUT32, (pol, "f32 out")
+        C16 = mm(A, B, policy=pol)
+        assert C16.dtype == dtype
+        assert rel(C16, ref) <= TOL_16, (pol, "16-bit out")
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+def test_16bit_integer_exact_all_policies(dtype):
+    M, N, K = 700, 900, 1500
+    g = W.rng(3)
+    A = torch.from_numpy(W.integer_f32(g, (M, K))).to(dtype).to(dev())
+    B = torch.from_numpy(W.integer_f32(g, (K, N))).to(dtype).to(dev())
+    ref = oracle(A, B)
+    for pol in POLICIES:
+        for fg in ([0] if pol != "sk" else [0, 5, 17, 200]):
+            C = mm(A, B, policy=pol, force_g=fg, out_dtype=torch.float32)
+            assert np.array_equal(to_f64(C), ref), (pol, fg)
+
+
+@pytest.mark.parametrize("layouts", ["nn", "nt", "tn", "tt"])
+@pytest.mark.parametrize("c_col", [False, True])
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_layouts(layouts, c_col, dtype):
+    M, N, K = 333, 517, 290
+    a, b = W.normal_pair(M, N, K, seed=11)
+    A = torch.from_numpy(a).to(dtype).to(dev())
+    B = torch.from_numpy(b).to(dtype).to(dev())
+    if layouts[0] == "t":
+        A = A.t().contiguous().t()      # column-major view of the same values
+    if layouts[1] == "t":
+        B = B.t().contiguous().t()
+    ref = oracle(A, B)
+    odt = torch.float32
+    out = torch.empty((N, M), dtype=odt, device=dev()).t() if c_col else torch.empty((M, N), dtype=odt, device=dev())
+    for pol in ("auto", "sk", "dp"):
+        C = mm(A, B, out=out, policy=pol)
+        tol = TOL_F32 if dtype == torch.float32 else TOL_16_OUT32
+        assert rel(C, ref) <= tol, (layouts, c_col, pol)
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_alpha_beta_and_nan_c(dtype):
+    M, N, K = 260, 300, 500
+    a, b = W.normal_pair(M, N, K, seed=5)
+    A = torch.from_numpy(a).to(dtype).to(dev())
+    B = torch.from_numpy(b).to(dtype).to(dev())
+    c0 = torch.from_numpy(W.normal_f32(W.rng(6), (M, N))).to(dtype).to(dev())
+    ref = oracle(A, B, alpha=0.5, beta=-2.0, C=c0)
+    for pol in ("sk", "dp", "auto"):
+        C = c0.clone()
+        mm(A, B, out=C, alpha=0.5, beta=-2.0, policy=pol)
+        tol = TOL_F32 if dtype == torch.float32 else TOL_16
+        assert rel(C, ref) <= tol, pol
+        Cn = torch.full((M, N), float("nan"), dtype=dtype, device=dev())
+        mm(A, B, out=Cn, alpha=1.0, beta=0.0, policy=pol)
+        assert not torch.isnan(Cn).any(), pol
+
+
+def test_k_zero_and_empty():
+    A = torch.zeros((100, 0), dtype=torch.bfloat16, device=dev())
+    B = torch.zeros((0, 70), dtype=torch.bfloat16, device=dev())
+    C = torch.full((100, 70), 3.0, dtype=torch.bfloat16, device=dev())
+    mm(A, B, out=C, beta=0.5)
+    assert torch.all(C.float() == 1.5)
+    mm(A, B, out=C, beta=0.0)
+    assert torch.all(C.float() == 0.0)
+    E = torch.empty((0, 16), dtype=torch.bfloat16, device=dev())
+    F = torch.ones((16, 5), dtype=torch.bfloat16, device=dev())
+    assert mm(E, F).shape == (0, 5)
+
+
+def test_determinism_repeated_runs():
+    M, N, K = 1000, 1000, 3000
+    a, b = W.normal_pair(M, N, K, seed=9)
+    A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+    first = mm(A, B, policy="sk", out_dtype=torch.float32).clone()
+    for _ in range(20):
+        assert torch.equal(mm(A, B, policy="sk", out_dtype=torch.float32), first)
+
+
+def test_full_size_sampled_rows_bf16():
+    """The benchmark's largest shape (8192^3, bf16, auto policy) on sampled rows."""
+    M = N = K = 8192
+    g = torch.Generator(device="cpu").manual_seed(0)
+    A = torch.randn((M, K), generator=g, dtype=torch.float32).to(torch.bfloat16).to(dev())
+    B = torch.randn((K, N), generator=g, dtype=torch.float32).to(torch.bfloat16).to(dev())
+    C = mm(A, B)
+    rows = np.array([0, 1, 255, 256, 4095, 8191])
+    ref = og.gemm_rows_f64(to_f64(A), to_f64(B), rows)
+    assert og.rel_frobenius(to_f64(C[torch.from_numpy(rows).to(dev())]), ref) <= TOL_16
