@@ -1,0 +1,278 @@
+"""Benchmark: Stream-K vs data-parallel tiles on the BF16 shape sweep (one MI355X).
+
+One step = one pass of the Stream-K GEMM (automatic policy: data-parallel
+waves plus a Stream-K remainder) over the 1000-shape BF16 sweep: M, N, K
+log-uniform in [128, 8192], half of them multiples of 128 and half with
++1..127 offsets, A and B iid N(0, 1) in bf16, FP32 accumulation, bf16 output.
+Inputs for every shape are resident in HBM before timing starts (distinct
+buffers per shape).  Plans are built once before the timed region.
+
+Printed JSON line (rank 0):
+  value        whole-sweep throughput of the Stream-K path, TFLOP/s
+               (2*M*N*K useful flops over the wall time of the step)
+  roofline     the dominant kernel (the BF16 Stream-K kernel) against the
+               dense BF16 MFMA peak: achieved = flops per launch / average
+               launch duration from HIP events around every launch
+  dp_*         the same kernel with the data-parallel policy (one workgroup
+               per tile) over the same shapes: the paper's baseline
+  sk_over_dp_* per-shape speedups (geomean / min / median / max), over all
+               shapes and over the quantisation-bound subset (tiles fill
+               less than 90% of the last wave)
+  cpu_baseline the FP64 oracle on the host cores over a bounded sample of
+               the sweep
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TFLOP/s & % MFMA peak, Stream-K vs data-parallel tiles, bf16 shape sweep"
+PEAK_BF16_TFLOPS = 2516.6      # MI355X dense BF16 MFMA, 256 CU x 4096 flop/clk x 2.4 GHz
+HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--shapes", type=int, default=1000)
+    ap.add_argument("--reps", type=int, default=3, help="timed repetitions per shape for the per-shape ratios")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-per-shape", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many Stream-K steps (for profiler runs) and print timings")
+    return ap.parse_args()
+
+
+class Case:
+    __slots__ = ("M", "N", "K", "A", "B", "C", "sk", "dp", "flops", "t", "p")
+
+
+def build_cases(shapes, torch, sk):
+    cases = []
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    for (M, N, K) in shapes:
+        c = Case()
+        c.M, c.N, c.K = M, N, K
+        c.A = torch.randn((M, K), generator=gen, device=dev, dtype=torch.float32).to(torch.bfloat16)
+        c.B = torch.randn((K, N), generator=gen, device=dev, dtype=torch.float32).to(torch.bfloat16)
+        c.C = torch.empty((M, N), device=dev, dtype=torch.bfloat16)
+        c.sk = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="auto")
+        c.dp = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="dp")
+        info = c.sk.info()
+        c.t, c.p = info["t"], info["p"]
+        c.flops = 2.0 * M * N * K
+        cases.append(c)
+    return cases
+
+
+def make_launcher(c, plan, ws, stream):
+    """Pre-resolved C-ABI call for one GEMM (argument marshalling only)."""
+    import ctypes
+    from paper_2212_08964_amd import skgemm as sk
+    L = sk.lib()
+    nws = plan.workspace_size()
+    args = (plan.handle, ctypes.c_void_p(c.A.data_ptr()), c.K, ctypes.c_void_p(c.B.data_ptr()), c.N,
+            ctypes.c_void_p(c.C.data_ptr()), c.N, ctypes.c_float(1.0), ctypes.c_float(0.0), None, None,
+            ctypes.c_void_p(ws.data_ptr()) if nws else None, nws, ctypes.c_void_p(stream))
+    fn = L.skgemm_run
+
+    def launch():
+        st = fn(*args)
+        if st != 0:
+            raise sk.SkgemmError(st, "skgemm_run")
+    return launch
+
+
+def cpu_baseline(shapes, budget_s):
+    """FP64 oracle on the host over a prefix of the sweep (bounded by budget_s)."""
+    import numpy as np
+    from oracle import gemm as og
+    g = np.random.default_rng(1)
+    # smallest-first prefix of a fixed random order of the sweep, so the sample
+    # spans many shapes within the budget
+    order = g.permutation(len(shapes))
+    flops, secs, used = 0.0, 0.0, []
+    threads = og.num_threads()
+    for i in order:
+        M, N, K = shapes[i]
+        est = 2.0 * M * N * K
+        if used and secs + est / max(flops / max(secs, 1e-9), 1e9) > budget_s:
+            continue
+        A = g.standard_normal((M, K))
+        B = g.standard_normal((K, N))
+        t0 = time.perf_counter()
+        og.gemm_f64(A, B)
+        secs += time.perf_counter() - t0
+        flops += est
+        used.append(int(i))
+        if secs >= budget_s or len(used) >= 64:
+            break
+    return {"value": flops / secs / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(used)} shapes of the sweep (random order, fitted to a {budget_s:.0f} s budget), "
+                      f"{flops / 1e9:.1f} GFLOP in {secs:.1f} s, FP64 triple loop with OpenMP over rows"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (single-GPU build); --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2212_08964_amd import skgemm as sk
+
+    shapes = W.sweep_shapes(args.shapes, seed=0)
+    t0 = time.perf_counter()
+    cases = build_cases(shapes, torch, sk)
+    plan_s = time.perf_counter() - t0
+    # planning cost alone (host, microseconds per plan)
+    tp = time.perf_counter()
+    for (M, N, K) in shapes[:200]:
+        sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16)
+    plan_us = (time.perf_counter() - tp) / min(200, len(shapes)) * 1e6
+
+    ws_bytes = max(max(c.sk.workspace_size(), c.dp.workspace_size()) for c in cases)
+    ws = torch.zeros(max(ws_bytes, 256), dtype=torch.uint8, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    sptr = stream.cuda_stream
+    sk_launch = [make_launcher(c, c.sk, ws, sptr) for c in cases]
+    dp_launch = [make_launcher(c, c.dp, ws, sptr) for c in cases]
+    total_flops = sum(c.flops for c in cases)
+    torch.cuda.synchronize()
+
+    def run_pass(launchers):
+        for f in launchers:
+            f()
+
+    if args.profile_steps:
+        for s in range(args.profile_steps):
+            t1 = time.perf_counter()
+            run_pass(sk_launch)
+            torch.cuda.synchronize()
+            print(f"profile step {s}: {(time.perf_counter() - t1) * 1e3:.2f} ms", flush=True)
+        return
+
+    for _ in range(args.warmup):
+        run_pass(sk_launch)
+        run_pass(dp_launch)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K steps of the Stream-K pass, events around every launch
+    n = len(cases)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(n + 1)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for s in range(args.steps):
+        e = ev[s]
+        e[0].record(stream)
+        for i, f in enumerate(sk_launch):
+            f()
+            e[i + 1].record(stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = start.elapsed_time(end)
+    ms_per_step = wall_ms / args.steps
+    per_launch_ms = np.zeros(n)
+    for s in range(args.steps):
+        for i in range(n):
+            per_launch_ms[i] += ev[s][i].elapsed_time(ev[s][i + 1])
+    per_launch_ms /= args.steps
+    value = total_flops / (ms_per_step * 1e-3) / 1e12
+    achieved = total_flops / (per_launch_ms.sum() * 1e-3) / 1e12
+
+    # ---- the data-parallel baseline pass, timed the same way
+    start.record(stream)
+    for s in range(args.steps):
+        run_pass(dp_launch)
+    end.record(stream)
+    torch.cuda.synchronize()
+    dp_ms_per_step = start.elapsed_time(end) / args.steps
+    dp_value = total_flops / (dp_ms_per_step * 1e-3) / 1e12
+
+    # ---- per-shape times (both policies, back-to-back launches, best-of events)
+    ratios = None
+    if not args.no_per_shape:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t_sk = np.zeros(n)
+        t_dp = np.zeros(n)
+        for i in range(n):
+            for arr, f in ((t_sk, sk_launch[i]), (t_dp, dp_launch[i])):
+                f()
+                e0.record(stream)
+                for _ in range(args.reps):
+                    f()
+                e1.record(stream)
+                e1.synchronize()
+                arr[i] = e0.elapsed_time(e1) / args.reps
+        ratios = t_dp / t_sk
+        qb = np.array([c.t / (c.p * math.ceil(c.t / c.p)) < 0.9 for c in cases])
+
+        def stats(r):
+            return {"geomean": float(np.exp(np.mean(np.log(r)))), "min": float(r.min()),
+                    "median": float(np.median(r)), "max": float(r.max()), "n": int(r.size)}
+        flops_arr = np.array([c.flops for c in cases])
+        per_shape = {
+            "all": stats(ratios),
+            "quantization_bound": stats(ratios[qb]) if qb.any() else None,
+            "sk_tflops_geomean": float(np.exp(np.mean(np.log(flops_arr / (t_sk * 1e-3) / 1e12)))),
+            "dp_tflops_geomean": float(np.exp(np.mean(np.log(flops_arr / (t_dp * 1e-3) / 1e12)))),
+            "sk_tflops_max": float((flops_arr / (t_sk * 1e-3) / 1e12).max()),
+        }
+    torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "bf16 shape sweep: 1000 GEMMs, M,N,K log-uniform in [128,8192] "
+                               "(half multiples of 128, half +1..127), A,B iid N(0,1) bf16, FP32 accumulate, "
+                               "bf16 out, row-major",
+                   "n_shapes": n, "policy": "auto (DP waves + Stream-K remainder)",
+                   "baseline": "same kernel, policy=dp (one workgroup per 256x256 tile)",
+                   "total_gflop": round(total_flops / 1e9, 1), "parallelism": "single GPU"},
+        "pct_mfma_peak": round(100.0 * value / PEAK_BF16_TFLOPS, 2),
+        "dp_value": round(dp_value, 3),
+        "dp_ms_per_step": round(dp_ms_per_step, 4),
+        "sk_over_dp_aggregate": round(value / dp_value, 4),
+        "sk_over_dp_per_shape": ratios is not None and per_shape or None,
+        "plan_us_per_gemm": round(plan_us, 2),
+        "setup_s": round(plan_s, 2),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                     "kernel": "skgemm_kernel<BF16, A K-contiguous, B N-contiguous>",
+                     "avg_launch_us": round(per_launch_ms.mean() * 1e3, 3),
+                     "flops_per_launch": round(total_flops / n, 1)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(shapes, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
