@@ -1,0 +1,84 @@
+"""Measure the grid-size model constants on the local GPU.
+
+The Analytical Modeling subsection models the runtime of one tile-producing
+workgroup as a + b*[peers > 1] + c*iters_per_cta + d*(peers - 1), with the
+constants found by microbenchmarks once per blocking factor, data type and
+GPU.  This script runs basic Stream-K with forced grid sizes over synthetic
+problems (tile counts t, iterations per tile ipt, grid sizes g in [t, p]),
+times each with HIP events, and fits (a, b, c, d) by least squares.  It
+prints the constants normalised to c = 1, in the form the library's model
+table uses.
+
+Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32|f8]
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+
+def model_terms(t, ipt, g):
+    ipc = math.ceil(t * ipt / g)
+    peers = math.ceil(ipt / ipc)
+    return [1.0, 1.0 if peers > 1 else 0.0, float(ipc), float(peers - 1)]
+
+
+def measure(dtype="bf16", reps=20, verbose=True):
+    import numpy as np
+    import torch
+
+    from . import skgemm as sk
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}[dtype]
+    cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32}[dtype]
+    probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp").info()
+    BM, BN, BK, p = probe["BM"], probe["BN"], probe["BK"], probe["p"]
+    rows, ys = [], []
+    for t in (1, 2, 4, 8, 16, 32, 64, 128):
+        for ipt in (4, 16, 64):
+            tm = 1
+            while tm * tm < t:
+                tm *= 2
+            tn = t // tm
+            M, N, K = BM * tm, BN * tn, BK * ipt
+            A = torch.randn(M, K, device="cuda").to(tdt)
+            B = torch.randn(K, N, device="cuda").to(tdt)
+            C = torch.empty(M, N, device="cuda", dtype=tdt)
+            gs = sorted({g for g in (t, 2 * t, 3 * t, 4 * t, 6 * t, 8 * t, 12 * t, 16 * t, p)
+                         if t <= g <= min(p, t * ipt)})
+            for g in gs:
+                sk.matmul(A, B, out=C, policy="sk", force_g=g)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                best = float("inf")
+                for _ in range(3):
+                    e0.record()
+                    for _ in range(reps):
+                        sk.matmul(A, B, out=C, policy="sk", force_g=g)
+                    e1.record()
+                    e1.synchronize()
+                    best = min(best, e0.elapsed_time(e1) / reps * 1e3)
+                rows.append(model_terms(t, ipt, g))
+                ys.append(best)
+                if verbose:
+                    print(f"t={t:4d} ipt={ipt:3d} g={g:4d}: {best:8.2f} us", flush=True)
+    X = np.array(rows)
+    y = np.array(ys)
+    coef, *_ = np.linalg.lstsq(X, y, rcond=None)
+    a, b, c, d = (float(v) for v in coef)
+    return (a / c, b / c, 1.0, d / c), (a, b, c, d), X, y
+
+
+def main():
+    dtype = sys.argv[1] if len(sys.argv) > 1 else "bf16"
+    norm, raw, X, y = measure(dtype)
+    a, b, c, d = raw
+    pred = X @ [a, b, c, d]
+    import numpy as np
+    err = float(np.sqrt(np.mean((pred - y) ** 2)))
+    print(f"raw (us): a={a:.3f} b={b:.3f} c={c:.3f} d={d:.3f}  rms residual {err:.2f} us over {len(y)} runs")
+    print(f"normalised (c=1): a={norm[0]:.3f} b={norm[1]:.3f} c=1 d={norm[3]:.3f}")
+
+
+if __name__ == "__main__":
+    main()

@@ -21,7 +21,8 @@
 // LDS layouts (no padding; 16-byte chunks XOR-swizzled per row so that the
 // fragment reads of one instruction fall on distinct banks):
 //  * K-contiguous operand: [rows][128 bytes of k]; chunk c of row r sits at
-//    position c ^ (r mod 8).
+//    position c ^ (r mod 8) ^ ((r / 8) mod 2), so the 16-byte reads of 16
+//    consecutive rows (one LDS cycle of 64 banks) touch distinct banks.
 //  * MN-contiguous operand: [k][512 bytes of rows]; chunk c of row k sits at
 //    position c ^ 4 (k mod 4) for 16-bit types (read with the LDS transpose
 //    read, four k of one column per lane) and c ^ 8 ((k / 4) mod 2) for FP32
@@ -66,7 +67,7 @@ __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" 
 // Position swizzle of a row of a slab in LDS (see the layout note above).
 template <int EB, bool KC>
 __device__ __forceinline__ int swz(int row) {
-    if constexpr (KC) return row & 7;
+    if constexpr (KC) return (row & 7) ^ ((row >> 3) & 1);
     else if constexpr (EB == 4) return 8 * ((row >> 2) & 1);
     else return 4 * (row & 3);
 }
@@ -188,7 +189,7 @@ struct Slab {
 
 // 16 bytes = 8 k-values of one row of a K-contiguous slab, chunk q (0..7).
 __device__ __forceinline__ u32x4 lds_row_chunk(const unsigned char* lds, int row, int q) {
-    return *reinterpret_cast<const u32x4*>(lds + row * 128 + ((q ^ (row & 7)) << 4));
+    return *reinterpret_cast<const u32x4*>(lds + row * 128 + ((q ^ swz<2, true>(row)) << 4));
 }
 
 // Byte address of element (k, col) of an MN-contiguous slab.
@@ -283,26 +284,43 @@ struct Gemm {
                                                    Acc& acc, int wm, int wn, int lane) {
         const int g = lane >> 5, l32 = lane & 31;
         if constexpr (DT == DT_BF16 || DT == DT_F16) {
-#pragma unroll
-            for (int s = 0; s < BK / 16; ++s) {
-                u32x4 af[FM], bf[FN];
+            // Fragments are double-buffered across the k16 steps: the reads of
+            // step s+1 are interleaved between the MFMAs of step s, so LDS
+            // latency hides behind matrix work instead of stalling it.
+            constexpr int KS = BK / 16;
+            u32x4 af[2][FM], bf[2][FN];
+            auto load = [&](int s, int buf) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
-                    if constexpr (AKC) af[i] = lds_row_chunk(As, wm * WTM + i * 32 + l32, 2 * s + g);
-                    else af[i] = lds_tr16(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
+                    if constexpr (AKC) af[buf][i] = lds_row_chunk(As, wm * WTM + i * 32 + l32, 2 * s + g);
+                    else af[buf][i] = lds_tr16(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
                 }
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    if constexpr (BKC) bf[j] = lds_row_chunk(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
-                    else bf[j] = lds_tr16(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
+                    if constexpr (BKC) bf[buf][j] = lds_row_chunk(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
+                    else bf[buf][j] = lds_tr16(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
                 }
+            };
+            constexpr int READS = FM * (AKC ? 1 : 2) + FN * (BKC ? 1 : 2);   // LDS reads per step
+            load(0, 0);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int cur = s & 1;
+                if (s + 1 < KS) load(s + 1, cur ^ 1);
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(af[i], bf[j], acc.v[i][j]);
-                // Keep each step's fragment reads next to its MFMAs: hoisting all
-                // steps' reads would need more registers than the accumulators leave.
-                __builtin_amdgcn_sched_barrier(0);
+                    for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(af[cur][i], bf[cur][j], acc.v[i][j]);
+                if (s + 1 < KS) {
+                    constexpr int MF = FM * FN, PAIRS = READS < MF ? READS : MF;
+#pragma unroll
+                    for (int r = 0; r < PAIRS; ++r) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+                    }
+                    if constexpr (MF > PAIRS) __builtin_amdgcn_sched_group_barrier(0x008, MF - PAIRS, 0);
+                    if constexpr (READS > PAIRS) __builtin_amdgcn_sched_group_barrier(0x100, READS - PAIRS, 0);
+                }
             }
         } else if constexpr (DT == DT_F32) {
             // Lane group g handles k = 8c + 4g + u of step (c, u).
@@ -424,7 +442,22 @@ struct Gemm {
     // at slot[(q * THREADS + tid) * 4], so each store instruction of the
     // workgroup writes THREADS * 16 bytes contiguously and the reader uses the
     // same mapping.
+    //
+    // The eight XCDs keep separate, non-coherent L2 caches, and the reader of a
+    // partial usually runs on another XCD.  Partials and flags therefore move
+    // with device-coherent (SC1) stores and loads, the cache policy the
+    // compiler uses for agent-scope atomics: the data reaches the device
+    // coherence point before the store completes, and the reader fetches it
+    // from there, so neither side needs a whole-L2 write-back or invalidate
+    // (which would also evict the A/B slabs of every workgroup on that XCD).
+    static constexpr int kCoherent = 16;   // SC1 cache-policy bit
+
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(float* slot) {
+        return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, BM * BN * 4, kBufferFlags);
+    }
+
     static __device__ __forceinline__ void store_partial(float* slot, const Acc& acc, int tid) {
+        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot);
         int q = 0;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -434,11 +467,13 @@ struct Gemm {
                 for (int r = 0; r < 4; ++r, ++q) {
                     const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
                                      acc.v[i][j][4 * r + 3]};
-                    *reinterpret_cast<f32x4*>(slot + ((size_t)q * THREADS + tid) * 4) = v;
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs,
+                                                           (q * THREADS + tid) * 16, 0, kCoherent);
                 }
     }
 
     static __device__ __forceinline__ void add_partial(const float* slot, Acc& acc, int tid) {
+        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(const_cast<float*>(slot));
         int q = 0;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -446,7 +481,8 @@ struct Gemm {
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r, ++q) {
-                    const f32x4 v = *reinterpret_cast<const f32x4*>(slot + ((size_t)q * THREADS + tid) * 4);
+                    const f32x4 v = __builtin_bit_cast(
+                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent));
                     acc.v[i][j][4 * r] += v.x;
                     acc.v[i][j][4 * r + 1] += v.y;
                     acc.v[i][j][4 * r + 2] += v.z;
@@ -608,18 +644,20 @@ struct Gemm {
 
             if (role == ROLE_PARTIAL) {
                 store_partial(a.partials + (size_t)wg * (BM * BN), acc, tid);
-                __threadfence();          // this thread's partial stores, visible device-wide
-                __syncthreads();
+                wait_vmem();              // this wave's coherent partial stores have completed
+                __syncthreads();          // ... and so have every other wave's
                 if (tid == 0)
-                    __hip_atomic_store(a.flags + (size_t)wg * kFlagStrideInts, 1, __ATOMIC_RELEASE,
+                    __hip_atomic_store(a.flags + (size_t)wg * kFlagStrideInts, 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 if (role == ROLE_OWNER) {
                     for (int peer = wg + 1; peer <= peer_end; ++peer) {
                         int32_t* flag = a.flags + (size_t)peer * kFlagStrideInts;
                         if (tid == 0) {
+                            // Relaxed agent-scope polling: coherent loads of the
+                            // flag, with no cache invalidation per poll.
                             int spins = 0;
-                            while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
                                 __builtin_amdgcn_s_sleep(2);
                                 if (++spins > a.spin_limit) {
                                     __hip_atomic_store(a.err, kErrTimeout, __ATOMIC_RELAXED,
@@ -629,8 +667,7 @@ struct Gemm {
                             }
                         }
                         __syncthreads();
-                        __threadfence();      // acquire side for every reading thread
-                        add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);
+                        add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);   // coherent loads
                         if (tid == 0) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
