@@ -131,8 +131,10 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
  *   4 BM, 5 BN, 6 BK, 7 tiles_m, 8 tiles_n, 9 tiles, 10 iters_per_tile,
  *   11 policy (resolved skgemm_policy_t), 12 sk_tiles, 13 g_sk, 14 grid,
  *   15 sk_first (0/1), 16 p (co-resident workgroups), 17 hybrid_min_waves,
- *   18 A K-contiguous (0/1), 19 B K-contiguous (0/1).
- * n is the capacity of info; up to 20 values are written. */
+ *   18 A K-contiguous (0/1), 19 B K-contiguous (0/1), 20 G (problems of a
+ *   grouped plan, 0 for one GEMM; fields 0-2, 7, 8 and 10 are 0 then and
+ *   field 9 is the total tile count).
+ * n is the capacity of info; up to 21 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)
@@ -143,6 +145,66 @@ skgemm_status_t skgemm_model_constants(skgemm_plan_t plan, double* abcd);
 /* Host-side copy of the schedule the plan launches, in the same record
  * format as skgemm_run_traced (no device access). */
 skgemm_status_t skgemm_schedule(skgemm_plan_t plan, int32_t* records, size_t cap, size_t* n);
+
+/* ---------------------------------------------------------------- grouped GEMM
+ * Several independent problems in ONE persistent launch: the problems' tiles
+ * and MAC-loop iterations are concatenated (problem 0 first) into a single
+ * iteration space, which the same policies split over the grid exactly as for
+ * one GEMM (a Stream-K share may cross from one problem into the next).  All
+ * problems share layouts and dtypes; each has its own M, N, K, pointers,
+ * leading dimensions, alpha and beta.  K must be > 0 for every problem with
+ * M, N > 0.  The run is a single kernel launch reading a device table, so it
+ * can be captured in a HIP graph and replayed. */
+typedef struct {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    float alpha, beta;
+} skgemm_group_args_t;
+
+skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t* M, const int64_t* N,
+                                    const int64_t* K, skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc,
+                                    skgemm_dtype_t ta, skgemm_dtype_t tb, skgemm_dtype_t tc,
+                                    const skgemm_options_t* opt);
+
+/* Bytes of the per-problem table a grouped run reads (128 bytes per problem). */
+skgemm_status_t skgemm_grouped_table_size(skgemm_plan_t plan, size_t* bytes);
+
+/* Validates args[0..G) (host array, device pointers inside) and writes the
+ * table into host memory `table` (at least skgemm_grouped_table_size bytes);
+ * the caller copies it to device memory once and may reuse it for many runs
+ * while the pointers stay valid. */
+skgemm_status_t skgemm_grouped_table(skgemm_plan_t plan, const skgemm_group_args_t* args, void* table,
+                                     size_t bytes);
+
+/* One persistent launch over all problems; table_dev is the table in device
+ * memory; workspace as for skgemm_run (skgemm_workspace_size of this plan). */
+skgemm_status_t skgemm_grouped_run(skgemm_plan_t plan, const void* table_dev, void* workspace, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/* Same, writing schedule records as skgemm_run_traced does (tile = global
+ * tile index: problem i's tiles follow those of problems 0..i-1). */
+skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_dev, void* workspace,
+                                          size_t ws_bytes, int32_t* trace, size_t trace_records,
+                                          hipStream_t stream);
+
+/* ---------------------------------------------------------------- FP8 front end
+ * Per-tensor E4M3 quantisation of a rows x cols matrix X (FP32, BF16 or
+ * FP16, layout lx, leading dimension ldx) into Q (E4M3FN bytes, layout lq,
+ * leading dimension ldq; lq may differ from lx, e.g. to produce the
+ * column-major B the FP8 GEMM needs):
+ *   *scale = absmax(X) / 448 rounded to FP32 (1 if X is all zero),
+ *   Q = round-to-nearest-even E4M3 of clamp(X / scale, -448, 448), the
+ *       quotient rounded to FP32.
+ * scale is one FP32 on the device, to be passed as scale_a / scale_b of the
+ * FP8 GEMM.  workspace: device scratch of skgemm_quantize_workspace_size
+ * bytes, 4-byte aligned, no initialisation needed.  Inputs must be finite.
+ * Asynchronous on stream (three kernel launches). */
+skgemm_status_t skgemm_quantize_workspace_size(size_t* bytes);
+skgemm_status_t skgemm_quantize_e4m3(const void* X, skgemm_dtype_t tx, int64_t rows, int64_t cols,
+                                     skgemm_layout_t lx, int64_t ldx, void* Q, skgemm_layout_t lq, int64_t ldq,
+                                     float* scale, void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* Reads the workspace's error word (synchronises the stream).  Returns
  * SKGEMM_ERR_TIMEOUT if a fix-up wait expired in an earlier run. */

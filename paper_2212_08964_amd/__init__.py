@@ -6,4 +6,4 @@ hand-written HIP kernels behind the C ABI of include/skgemm.h.  This package
 is the thin Python layer over that library.
 """
 from . import skgemm  # noqa: F401
-from .skgemm import Plan, matmul  # noqa: F401
+from .skgemm import GroupedPlan, Plan, grouped_matmul, matmul, matmul_fp8, quantize_e4m3  # noqa: F401

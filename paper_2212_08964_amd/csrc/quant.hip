@@ -1,0 +1,189 @@
+// Per-tensor FP8 (OCP E4M3FN) quantisation for the FP8 GEMM front end.
+//
+//   s = absmax(X) / 448   (1 when X is all zero), rounded to FP32
+//   Q = E4M3_RNE(clamp(X / s, -448, 448))
+//
+// Three launches, all HBM-bound: absmax_partial reads X once (16-byte loads
+// when rows are aligned) and writes one maximum per workgroup; absmax_finish
+// (one workgroup) reduces those and writes s on the device, so no host round
+// trip or memset is needed and the sequence can be captured in a graph;
+// quantize_tiles reads X again in 64x64 tiles through LDS, so it can change
+// the layout on the way out (the FP8 GEMM wants both operands K-contiguous)
+// with coalesced reads and writes on both sides.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "skgemm_internal.h"
+
+namespace skg {
+
+constexpr int kQThreads = 256;
+constexpr int kAbsmaxBlocks = 1024;
+constexpr float kE4M3Max = 448.0f;
+
+template <int DT>
+__device__ __forceinline__ float elem(const void* x, int64_t i) {
+    if constexpr (DT == DT_F32) return reinterpret_cast<const float*>(x)[i];
+    else if constexpr (DT == DT_BF16) return __builtin_bit_cast(float, uint32_t(reinterpret_cast<const uint16_t*>(x)[i]) << 16);
+    else return float(reinterpret_cast<const _Float16*>(x)[i]);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float block_max(float v, float* red) {
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        v = lane < int(blockDim.x >> 6) ? red[lane] : 0.0f;
+        v = wave_max(v);
+    }
+    return v;
+}
+
+// Logical matrix `outer` x `inner` with the inner dimension contiguous and
+// leading dimension ld; vec says 16-byte loads are aligned for every row.
+template <int DT>
+__global__ void __launch_bounds__(kQThreads) absmax_partial(const void* x, int64_t outer, int64_t inner, int64_t ld,
+                                                            int vec, float* partial) {
+    __shared__ float red[kQThreads / 64];
+    constexpr int EB = DT == DT_F32 ? 4 : 2, VE = 16 / EB;
+    float m = 0.0f;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    if (vec) {
+        const int64_t vin = inner / VE;
+        const int64_t n = outer * vin;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const int64_t o = i / vin, c = (i % vin) * VE;
+            const uint4 u = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(x) + (o * ld + c) * EB);
+            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if constexpr (DT == DT_F32) {
+                    m = fmaxf(m, fabsf(__builtin_bit_cast(float, w[e])));
+                } else if constexpr (DT == DT_BF16) {
+                    m = fmaxf(m, fabsf(__builtin_bit_cast(float, w[e] << 16)));
+                    m = fmaxf(m, fabsf(__builtin_bit_cast(float, w[e] & 0xffff0000u)));
+                } else {
+                    m = fmaxf(m, fabsf(float(__builtin_bit_cast(_Float16, uint16_t(w[e])))));
+                    m = fmaxf(m, fabsf(float(__builtin_bit_cast(_Float16, uint16_t(w[e] >> 16)))));
+                }
+            }
+        }
+    } else {
+        const int64_t n = outer * inner;
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const int64_t o = i / inner, c = i % inner;
+            m = fmaxf(m, fabsf(elem<DT>(x, o * ld + c)));
+        }
+    }
+    m = block_max(m, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(kQThreads) absmax_finish(const float* partial, int n, float* scale) {
+    __shared__ float red[kQThreads / 64];
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, partial[i]);
+    m = block_max(m, red);
+    if (threadIdx.x == 0) scale[0] = m == 0.0f ? 1.0f : m / kE4M3Max;
+}
+
+// X / s rounded to FP32, clamped to the E4M3 range, rounded to E4M3 (nearest
+// even) by the hardware conversion; two codes per call.
+template <bool HI>
+__device__ __forceinline__ uint32_t to_e4m3x2(float a, float b, float s, uint32_t old) {
+    a = fminf(fmaxf(a / s, -kE4M3Max), kE4M3Max);
+    b = fminf(fmaxf(b / s, -kE4M3Max), kE4M3Max);
+    return uint32_t(__builtin_amdgcn_cvt_pk_fp8_f32(a, b, int(old), HI));
+}
+
+// One 64 x 64 tile of the logical rows x cols matrix per workgroup.  x_col /
+// q_col select column-major storage of the input / output.
+template <int DT>
+__global__ void __launch_bounds__(kQThreads) quantize_tiles(const void* x, int64_t rows, int64_t cols, int64_t ldx,
+                                                            int x_col, uint8_t* q, int64_t ldq, int q_col,
+                                                            const float* scale) {
+    __shared__ float tile[64][65];
+    const int64_t r0 = int64_t(blockIdx.y) * 64, c0 = int64_t(blockIdx.x) * 64;
+    const int t = threadIdx.x;
+    // read: consecutive threads walk the input's contiguous dimension
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int idx = t + k * kQThreads;
+        const int a = idx & 63, b = idx >> 6;      // a: contiguous index, b: strided index
+        const int rl = x_col ? a : b, cl = x_col ? b : a;
+        const int64_t r = r0 + rl, c = c0 + cl;
+        float v = 0.0f;
+        if (r < rows && c < cols) v = elem<DT>(x, x_col ? c * ldx + r : r * ldx + c);
+        tile[rl][cl] = v;
+    }
+    __syncthreads();
+    const float s = *scale;
+    // write: each thread converts four consecutive elements of the output's
+    // contiguous dimension
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int idx = t + k * kQThreads;           // 1024 groups of four
+        const int a4 = (idx & 15) * 4, b = idx >> 4;
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = q_col ? tile[a4 + e][b] : tile[b][a4 + e];
+        const int64_t outer = (q_col ? c0 : r0) + b;
+        const int64_t in0 = (q_col ? r0 : c0) + a4;
+        const int64_t n_outer = q_col ? cols : rows, n_inner = q_col ? rows : cols;
+        if (outer >= n_outer || in0 >= n_inner) continue;
+        uint32_t w = to_e4m3x2<false>(v[0], v[1], s, 0u);
+        w = to_e4m3x2<true>(v[2], v[3], s, w);
+        uint8_t* dst = q + outer * ldq + in0;
+        if (in0 + 4 <= n_inner && (reinterpret_cast<uintptr_t>(dst) & 3) == 0) {
+            *reinterpret_cast<uint32_t*>(dst) = w;
+        } else {
+            for (int e = 0; e < 4 && in0 + e < n_inner; ++e) dst[e] = uint8_t(w >> (8 * e));
+        }
+    }
+}
+
+int quant_workspace_floats() { return kAbsmaxBlocks; }
+
+int launch_quantize(int dtype, const void* x, int64_t rows, int64_t cols, int64_t ldx, bool x_col, uint8_t* q,
+                    int64_t ldq, bool q_col, float* scale, float* partial, void* stream) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t outer = x_col ? cols : rows, inner = x_col ? rows : cols;
+    const int eb = dtype == DT_F32 ? 4 : 2;
+    const bool vec = (inner * eb) % 16 == 0 && (ldx * eb) % 16 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    const int64_t work = vec ? outer * (inner / (16 / eb)) : outer * inner;
+    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(kAbsmaxBlocks, (work + kQThreads - 1) / kQThreads)));
+    const dim3 tiles(unsigned((cols + 63) / 64), unsigned((rows + 63) / 64));
+    const bool any = rows > 0 && cols > 0;
+    switch (dtype) {
+        case DT_F32:
+            absmax_partial<DT_F32><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);
+            absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);
+            if (any) quantize_tiles<DT_F32><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
+            break;
+        case DT_BF16:
+            absmax_partial<DT_BF16><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);
+            absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);
+            if (any) quantize_tiles<DT_BF16><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
+            break;
+        case DT_F16:
+            absmax_partial<DT_F16><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);
+            absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);
+            if (any) quantize_tiles<DT_F16><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
+            break;
+        default:
+            return int(hipErrorInvalidValue);
+    }
+    return int(hipGetLastError());
+}
+
+}  // namespace skg

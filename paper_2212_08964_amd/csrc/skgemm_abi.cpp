@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "skgemm.h"
 #include "skgemm_internal.h"
@@ -43,6 +44,13 @@ struct skgemm_plan_s {
     // workspace layout
     size_t ws_bytes, flags_off, partials_off;
     int max_segs;
+    // iteration space as problems (a single GEMM is one problem)
+    int G;                                  // 0 for a single-GEMM plan
+    std::vector<int32_t> pM, pN, pK, ptm, ptn, pipt;   // launched shapes
+    std::vector<int32_t> tile_base;         // G + 1 prefix of tiles
+    std::vector<int64_t> iter_base;         // G + 1 prefix of MAC-loop iterations
+    std::vector<int64_t> gM, gN, gK;        // shapes as given
+    int64_t sk_iters;
 };
 
 namespace {
@@ -111,10 +119,31 @@ int share_start(int x, int q, int r) { return x * q + std::min(x, r); }
 
 int owner_of(int i, int q, int r) { return (i < r * (q + 1)) ? i / (q + 1) : r + (i - r * (q + 1)) / q; }
 
+int find_last_le(const std::vector<int64_t>& base, int G, int64_t x) {
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+int find_last_le32(const std::vector<int32_t>& base, int G, int x) {
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Walks the schedule of workgroup x exactly as the kernel does; calls
-// emit(seq, tile, lo, hi, role, first_peer, last_peer) per segment.
+// emit(seq, global_tile, lo, hi, role, first_peer, last_peer) per segment.
 template <class F>
 int walk(const skgemm_plan_s& pl, int x, F&& emit) {
+    const int np = int(pl.pipt.size());
     int sk_it = 0, sk_end = 0;
     if (x < pl.g_sk) {
         sk_it = share_start(x, pl.sk_q, pl.sk_r);
@@ -126,10 +155,13 @@ int walk(const skgemm_plan_s& pl, int x, F&& emit) {
         const bool sk_left = sk_it < sk_end, dp_left = dp_tile < pl.t;
         if (!sk_left && !dp_left) break;
         const bool take_sk = pl.sk_first ? sk_left : !dp_left;
-        int tile, lo, hi, role, p0 = -1, p1 = -1;
+        int gtile, lo, hi, role, p0 = -1, p1 = -1;
         if (take_sk) {
-            tile = sk_it / pl.ipt;
-            const int first = tile * pl.ipt, last = first + pl.ipt;
+            const int pi = find_last_le(pl.iter_base, np, sk_it);
+            const int ipt = pl.pipt[pi];
+            const int tile = int((sk_it - pl.iter_base[pi]) / ipt);
+            const int first = int(pl.iter_base[pi]) + tile * ipt, last = first + ipt;
+            gtile = pl.tile_base[pi] + tile;
             lo = sk_it - first;
             hi = std::min(sk_end, last) - first;
             if (sk_it != first) {
@@ -143,13 +175,13 @@ int walk(const skgemm_plan_s& pl, int x, F&& emit) {
             }
             sk_it = last;
         } else {
-            tile = dp_tile;
+            gtile = dp_tile;
             lo = 0;
-            hi = pl.ipt;
+            hi = pl.pipt[find_last_le32(pl.tile_base, np, dp_tile)];
             role = ROLE_FULL;
             dp_tile += pl.grid;
         }
-        emit(seq, tile, lo, hi, role, p0, p1);
+        emit(seq, gtile, lo, hi, role, p0, p1);
         ++seq;
     }
     return seq;
@@ -198,84 +230,32 @@ void skgemm_default_options(skgemm_options_t* opt) {
     opt->hybrid_min_waves = 2;
 }
 
-skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K, skgemm_layout_t la,
-                            skgemm_layout_t lb, skgemm_layout_t lc, skgemm_dtype_t ta, skgemm_dtype_t tb,
-                            skgemm_dtype_t tc, const skgemm_options_t* opt) {
-    if (!out) return SKGEMM_ERR_INVALID_ARG;
-    *out = nullptr;
-    if (M < 0 || N < 0 || K < 0 || M > kMaxDim || N > kMaxDim || K > kMaxDim) return SKGEMM_ERR_INVALID_ARG;
-    if ((la != SKGEMM_ROW_MAJOR && la != SKGEMM_COL_MAJOR) || (lb != SKGEMM_ROW_MAJOR && lb != SKGEMM_COL_MAJOR) ||
-        (lc != SKGEMM_ROW_MAJOR && lc != SKGEMM_COL_MAJOR))
-        return SKGEMM_ERR_INVALID_ARG;
-    if (to_dt(ta) < 0 || to_dt(tb) < 0 || to_dt(tc) < 0) return SKGEMM_ERR_INVALID_ARG;
-    if (ta != tb) return SKGEMM_ERR_UNSUPPORTED;
-    if (tc == SKGEMM_F8E4M3) return SKGEMM_ERR_UNSUPPORTED;
-    if (ta != SKGEMM_F8E4M3 && ta != SKGEMM_F32 && tc != ta && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
-    if (ta == SKGEMM_F32 && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
-    skgemm_options_t o;
-    skgemm_default_options(&o);
-    if (opt) o = *opt;
-    if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
-    if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0) return SKGEMM_ERR_INVALID_ARG;
-    if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_2TILE_SK_DP) return SKGEMM_ERR_INVALID_ARG;
-
-    skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s();
-    if (!pl) return SKGEMM_ERR_HIP;
-    pl->M = M; pl->N = N; pl->K = K;
-    pl->la = la; pl->lb = lb; pl->lc = lc;
-    pl->ta = ta; pl->tc = tc;
-    pl->dtype = to_dt(ta);
-    pl->out = to_dt(tc);
-    pl->swapped = (lc == SKGEMM_COL_MAJOR);
-    const bool a_kc = (la == SKGEMM_ROW_MAJOR), b_kc = (lb == SKGEMM_COL_MAJOR);
-    pl->Ml = int32_t(pl->swapped ? N : M);
-    pl->Nl = int32_t(pl->swapped ? M : N);
-    pl->Kl = int32_t(K);
-    pl->akc = pl->swapped ? b_kc : a_kc;
-    pl->bkc = pl->swapped ? a_kc : b_kc;
-    if (!kernel_exists(pl->dtype, pl->akc, pl->bkc)) {
-        delete pl;
-        return SKGEMM_ERR_UNSUPPORTED;
-    }
-    const TileCfg tc_ = tile_for(pl->dtype);
-    if ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) || (o.tile_k && o.tile_k != tc_.bk)) {
-        delete pl;
-        return SKGEMM_ERR_UNSUPPORTED;
-    }
-    pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
-    model_for(pl->dtype, pl->model);
-    pl->hybrid_min_waves = o.hybrid_min_waves;
-
+// Common part of single and grouped planning: validate the options, resolve
+// the co-resident capacity, then the policy, Stream-K region, grid and
+// workspace for the iteration space in pl->{pipt, tile_base, iter_base}.
+static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o) {
     int cus = o.num_cus, occ = o.occupancy;
     if (cus == 0 || occ == 0) {
         int qc = 0, qo = 0;
         const skgemm_status_t st = device_capacity(pl->dtype, pl->akc, pl->bkc, &qc, &qo);
-        if (st != SKGEMM_OK) {
-            delete pl;
-            return st;
-        }
+        if (st != SKGEMM_OK) return st;
         if (cus == 0) cus = qc;
         if (occ == 0) occ = qo;
     }
     const int64_t p = int64_t(cus) * occ;
-    if (p <= 0 || p > kMaxDim) {
-        delete pl;
-        return SKGEMM_ERR_INVALID_ARG;
-    }
+    if (p <= 0 || p > kMaxDim) return SKGEMM_ERR_INVALID_ARG;
     pl->p = int(p);
-
-    const int64_t tm = cdiv(pl->Ml, pl->BM), tn = cdiv(pl->Nl, pl->BN), ipt = cdiv(K, pl->BK);
-    const int64_t t = tm * tn;
-    if (t > kMaxDim || t * ipt > kMaxDim) {
-        delete pl;
-        return SKGEMM_ERR_UNSUPPORTED;
-    }
-    pl->tm = int(tm); pl->tn = int(tn); pl->t = int(t); pl->ipt = int(ipt);
-
+    const int np = int(pl->pipt.size());
+    const int64_t t = pl->tile_base[np];
+    const int64_t total = pl->iter_base[np];
+    if (t > kMaxDim || total > kMaxDim) return SKGEMM_ERR_UNSUPPORTED;
+    pl->t = int(t);
+    // iterations per tile for the model (their mean over a grouped launch)
+    const int64_t ipt = t ? (total + t - 1) / t : 0;
     int policy = o.policy;
     pl->sk_tiles = 0; pl->g_sk = 0; pl->grid = 0; pl->sk_first = true;
     if (t > 0) {
-        if (ipt == 0) policy = SKGEMM_POLICY_DP;
+        if (total == 0) policy = SKGEMM_POLICY_DP;    // K == 0: epilogue-only tiles
         const int64_t w = t / p, r = t % p;
         if (policy == SKGEMM_POLICY_AUTO) {
             if (r == 0) policy = SKGEMM_POLICY_DP;
@@ -285,36 +265,38 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
         }
         if (policy == SKGEMM_POLICY_DP) {
             pl->grid = int(t);
-        } else if (policy == SKGEMM_POLICY_SK) {
-            pl->sk_tiles = int(t);
-            if (o.force_g) pl->g_sk = o.force_g;
-            else if (t >= p) pl->g_sk = int(p);
-            else pl->g_sk = model_best_g(t, ipt, p, pl->model);
-            pl->grid = pl->g_sk;
         } else {
-            if (policy == SKGEMM_POLICY_DP_1TILE_SK) {
+            if (policy == SKGEMM_POLICY_SK) {
+                pl->sk_tiles = int(t);
+            } else if (policy == SKGEMM_POLICY_DP_1TILE_SK) {
                 pl->sk_tiles = int(r);
                 pl->sk_first = false;
             } else {
                 pl->sk_tiles = int(w == 0 ? t : r + p);
-                pl->sk_first = true;
             }
-            if (pl->sk_tiles) pl->g_sk = o.force_g ? o.force_g : int(std::min<int64_t>(p, pl->sk_tiles * ipt));
-            pl->grid = (t - pl->sk_tiles > 0) ? int(p) : pl->g_sk;
-            pl->grid = std::max(pl->grid, pl->g_sk);
+            // iterations of the Stream-K region [0, sk_tiles)
+            const int pi = find_last_le32(pl->tile_base, np, pl->sk_tiles);
+            pl->sk_iters = pl->sk_tiles >= t ? total
+                                             : pl->iter_base[pi] + int64_t(pl->sk_tiles - pl->tile_base[pi]) * pl->pipt[pi];
+            if (policy == SKGEMM_POLICY_SK) {
+                if (o.force_g) pl->g_sk = o.force_g;
+                else if (t >= p) pl->g_sk = int(p);
+                else pl->g_sk = model_best_g(t, ipt, p, pl->model);
+                pl->grid = pl->g_sk;
+            } else {
+                if (pl->sk_tiles) pl->g_sk = o.force_g ? o.force_g : int(std::min<int64_t>(p, pl->sk_iters));
+                pl->grid = (t - pl->sk_tiles > 0) ? int(p) : pl->g_sk;
+                pl->grid = std::max(pl->grid, pl->g_sk);
+            }
         }
     }
     pl->policy = policy;
     // Owners wait on workgroups with higher indices, so every Stream-K
     // workgroup must be resident at once.
-    if (pl->g_sk > pl->p) {
-        delete pl;
-        return SKGEMM_ERR_CAPACITY;
-    }
+    if (pl->g_sk > pl->p) return SKGEMM_ERR_CAPACITY;
     if (pl->g_sk) {
-        const int64_t total = int64_t(pl->sk_tiles) * ipt;
-        pl->sk_q = int(total / pl->g_sk);
-        pl->sk_r = int(total % pl->g_sk);
+        pl->sk_q = int(pl->sk_iters / pl->g_sk);
+        pl->sk_r = int(pl->sk_iters % pl->g_sk);
     }
     pl->flags_off = kWsHeaderBytes;
     pl->partials_off = (kWsHeaderBytes + size_t(pl->g_sk) * kFlagStrideInts * 4 + 255) & ~size_t(255);
@@ -322,6 +304,122 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     int mx = 0;
     for (int x = 0; x < pl->grid; ++x) mx = std::max(mx, walk(*pl, x, [](int, int, int, int, int, int, int) {}));
     pl->max_segs = mx;
+    return SKGEMM_OK;
+}
+
+// Checks shared by single and grouped plans; fills dtype, layout and tile
+// fields of pl.
+static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc,
+                                   skgemm_dtype_t ta, skgemm_dtype_t tb, skgemm_dtype_t tc,
+                                   const skgemm_options_t& o) {
+    if ((la != SKGEMM_ROW_MAJOR && la != SKGEMM_COL_MAJOR) || (lb != SKGEMM_ROW_MAJOR && lb != SKGEMM_COL_MAJOR) ||
+        (lc != SKGEMM_ROW_MAJOR && lc != SKGEMM_COL_MAJOR))
+        return SKGEMM_ERR_INVALID_ARG;
+    if (to_dt(ta) < 0 || to_dt(tb) < 0 || to_dt(tc) < 0) return SKGEMM_ERR_INVALID_ARG;
+    if (ta != tb) return SKGEMM_ERR_UNSUPPORTED;
+    if (tc == SKGEMM_F8E4M3) return SKGEMM_ERR_UNSUPPORTED;
+    if (ta != SKGEMM_F8E4M3 && ta != SKGEMM_F32 && tc != ta && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
+    if (ta == SKGEMM_F32 && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
+    if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0) return SKGEMM_ERR_INVALID_ARG;
+    if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_2TILE_SK_DP) return SKGEMM_ERR_INVALID_ARG;
+    pl->la = la; pl->lb = lb; pl->lc = lc;
+    pl->ta = ta; pl->tc = tc;
+    pl->dtype = to_dt(ta);
+    pl->out = to_dt(tc);
+    pl->swapped = (lc == SKGEMM_COL_MAJOR);
+    const bool a_kc = (la == SKGEMM_ROW_MAJOR), b_kc = (lb == SKGEMM_COL_MAJOR);
+    pl->akc = pl->swapped ? b_kc : a_kc;
+    pl->bkc = pl->swapped ? a_kc : b_kc;
+    if (!kernel_exists(pl->dtype, pl->akc, pl->bkc)) return SKGEMM_ERR_UNSUPPORTED;
+    const TileCfg tc_ = tile_for(pl->dtype);
+    if ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) || (o.tile_k && o.tile_k != tc_.bk))
+        return SKGEMM_ERR_UNSUPPORTED;
+    pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
+    model_for(pl->dtype, pl->model);
+    pl->hybrid_min_waves = o.hybrid_min_waves;
+    return SKGEMM_OK;
+}
+
+// Appends one problem (shape as given) to the plan's iteration space.
+static void add_problem(skgemm_plan_s* pl, int64_t M, int64_t N, int64_t K) {
+    const int32_t Ml = int32_t(pl->swapped ? N : M), Nl = int32_t(pl->swapped ? M : N);
+    const int64_t tm = cdiv(Ml, pl->BM), tn = cdiv(Nl, pl->BN), ipt = cdiv(K, pl->BK);
+    if (pl->tile_base.empty()) {
+        pl->tile_base.push_back(0);
+        pl->iter_base.push_back(0);
+    }
+    pl->gM.push_back(M); pl->gN.push_back(N); pl->gK.push_back(K);
+    pl->pM.push_back(Ml); pl->pN.push_back(Nl); pl->pK.push_back(int32_t(K));
+    pl->ptm.push_back(int32_t(tm)); pl->ptn.push_back(int32_t(tn)); pl->pipt.push_back(int32_t(ipt));
+    const int64_t tb = pl->tile_base.back() + tm * tn;
+    pl->tile_base.push_back(int32_t(std::min<int64_t>(tb, kMaxDim)));
+    pl->iter_base.push_back(pl->iter_base.back() + tm * tn * ipt);
+}
+
+skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K, skgemm_layout_t la,
+                            skgemm_layout_t lb, skgemm_layout_t lc, skgemm_dtype_t ta, skgemm_dtype_t tb,
+                            skgemm_dtype_t tc, const skgemm_options_t* opt) {
+    if (!out) return SKGEMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (M < 0 || N < 0 || K < 0 || M > kMaxDim || N > kMaxDim || K > kMaxDim) return SKGEMM_ERR_INVALID_ARG;
+    skgemm_options_t o;
+    skgemm_default_options(&o);
+    if (opt) o = *opt;
+    if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
+    skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s();
+    if (!pl) return SKGEMM_ERR_HIP;
+    skgemm_status_t st = init_common(pl, la, lb, lc, ta, tb, tc, o);
+    if (st == SKGEMM_OK) {
+        pl->M = M; pl->N = N; pl->K = K;
+        pl->G = 0;
+        add_problem(pl, M, N, K);
+        pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(K);
+        pl->tm = pl->ptm[0]; pl->tn = pl->ptn[0]; pl->ipt = pl->pipt[0];
+        if (int64_t(pl->tm) * pl->tn > kMaxDim || int64_t(pl->tm) * pl->tn * pl->ipt > kMaxDim)
+            st = SKGEMM_ERR_UNSUPPORTED;
+        else
+            st = finish_plan(pl, o);
+    }
+    if (st != SKGEMM_OK) {
+        delete pl;
+        return st;
+    }
+    *out = pl;
+    return SKGEMM_OK;
+}
+
+skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t* M, const int64_t* N,
+                                    const int64_t* K, skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc,
+                                    skgemm_dtype_t ta, skgemm_dtype_t tb, skgemm_dtype_t tc,
+                                    const skgemm_options_t* opt) {
+    if (!out) return SKGEMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (G <= 0 || G > (1 << 20) || !M || !N || !K) return SKGEMM_ERR_INVALID_ARG;
+    for (int i = 0; i < G; ++i) {
+        if (M[i] < 0 || N[i] < 0 || K[i] < 0 || M[i] > kMaxDim || N[i] > kMaxDim || K[i] > kMaxDim)
+            return SKGEMM_ERR_INVALID_ARG;
+        if (K[i] == 0 && M[i] > 0 && N[i] > 0) return SKGEMM_ERR_UNSUPPORTED;   // tiles without iterations
+    }
+    skgemm_options_t o;
+    skgemm_default_options(&o);
+    if (opt) o = *opt;
+    if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
+    skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s();
+    if (!pl) return SKGEMM_ERR_HIP;
+    skgemm_status_t st = init_common(pl, la, lb, lc, ta, tb, tc, o);
+    if (st == SKGEMM_OK) {
+        pl->G = G;
+        for (int i = 0; i < G; ++i) add_problem(pl, M[i], N[i], K[i]);
+        pl->M = pl->N = pl->K = 0;
+        pl->Ml = pl->Nl = pl->Kl = 0;
+        pl->tm = pl->tn = 0;
+        pl->ipt = 0;
+        st = finish_plan(pl, o);
+    }
+    if (st != SKGEMM_OK) {
+        delete pl;
+        return st;
+    }
     *out = pl;
     return SKGEMM_OK;
 }
@@ -338,65 +436,82 @@ skgemm_status_t skgemm_trace_capacity(skgemm_plan_t plan, size_t* n_records) {
     return SKGEMM_OK;
 }
 
-static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                                int64_t ldc, float alpha, float beta, const float* scale_a, const float* scale_b,
-                                void* workspace, size_t ws_bytes, int32_t* trace, size_t trace_records,
-                                hipStream_t stream) {
-    if (!pl) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t M = pl->M, N = pl->N, K = pl->K;
-    // leading dimensions follow each operand's own layout
+// Leading-dimension, pointer and 32-bit offset checks for one problem as
+// given; fills the launched operand fields of e.
+static skgemm_status_t check_problem(const skgemm_plan_s* pl, int64_t M, int64_t N, int64_t K, const void* A,
+                                     int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, GroupEntry* e) {
     const int64_t a_min = pl->la == SKGEMM_ROW_MAJOR ? K : M;
     const int64_t b_min = pl->lb == SKGEMM_ROW_MAJOR ? N : K;
     const int64_t c_min = pl->lc == SKGEMM_ROW_MAJOR ? N : M;
     if (lda < std::max<int64_t>(1, a_min) || ldb < std::max<int64_t>(1, b_min) || ldc < std::max<int64_t>(1, c_min))
         return SKGEMM_ERR_INVALID_ARG;
-    if (M == 0 || N == 0) return SKGEMM_OK;
-    if (!C) return SKGEMM_ERR_INVALID_ARG;
-    if (K > 0 && (!A || !B)) return SKGEMM_ERR_INVALID_ARG;
+    if (M > 0 && N > 0) {
+        if (!C) return SKGEMM_ERR_INVALID_ARG;
+        if (K > 0 && (!A || !B)) return SKGEMM_ERR_INVALID_ARG;
+    }
+    const int eb = elem_bytes(pl->ta);
+    e->A = pl->swapped ? B : A;
+    e->B = pl->swapped ? A : B;
+    e->lda = pl->swapped ? ldb : lda;
+    e->ldb = pl->swapped ? lda : ldb;
+    e->C = C;
+    e->ldc = ldc;
+    // Loads use 32-bit offsets within one tile's slab of each operand.
+    const int64_t lim = (int64_t(1) << 31) - 1;
+    const int64_t span_a = pl->akc ? int64_t(pl->BM) * e->lda * eb + 128 : int64_t(pl->BK) * e->lda * eb + 512;
+    const int64_t span_b = pl->bkc ? int64_t(pl->BN) * e->ldb * eb + 128 : int64_t(pl->BK) * e->ldb * eb + 512;
+    if (span_a > lim || span_b > lim) return SKGEMM_ERR_UNSUPPORTED;
+    return SKGEMM_OK;
+}
+
+static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspace, int32_t* trace) {
+    a->t = pl->t;
+    a->sk_tiles = pl->sk_tiles; a->g_sk = pl->g_sk;
+    a->sk_iters = int32_t(pl->sk_iters);
+    a->sk_q = pl->sk_q; a->sk_r = pl->sk_r;
+    a->grid = pl->grid;
+    a->sk_first = pl->sk_first ? 1 : 0;
+    a->dp_only = pl->g_sk == 0 ? 1 : 0;
+    a->out_dtype = pl->out;
+    a->vec_a = 16;
+    a->vec_b = 16;
+    if (pl->ws_bytes) {
+        unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+        a->err = reinterpret_cast<int32_t*>(ws);
+        a->flags = reinterpret_cast<int32_t*>(ws + pl->flags_off);
+        a->partials = reinterpret_cast<float*>(ws + pl->partials_off);
+    }
+    a->trace = trace;
+    a->trace_per_wg = trace ? pl->max_segs : 0;
+    a->spin_limit = 1 << 22;
+}
+
+static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                                int64_t ldc, float alpha, float beta, const float* scale_a, const float* scale_b,
+                                void* workspace, size_t ws_bytes, int32_t* trace, size_t trace_records,
+                                hipStream_t stream) {
+    if (!pl || pl->G) return SKGEMM_ERR_INVALID_ARG;
+    GroupEntry e;
+    std::memset(&e, 0, sizeof(e));
+    skgemm_status_t st = check_problem(pl, pl->M, pl->N, pl->K, A, lda, B, ldb, C, ldc, &e);
+    if (st != SKGEMM_OK) return st;
+    if (pl->M == 0 || pl->N == 0) return SKGEMM_OK;
     if (pl->ws_bytes) {
         if (!workspace || ws_bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255))
             return SKGEMM_ERR_WORKSPACE;
     }
     if (trace && trace_records < size_t(pl->grid) * size_t(pl->max_segs)) return SKGEMM_ERR_INVALID_ARG;
-
     KArgs a;
     std::memset(&a, 0, sizeof(a));
-    const int eb = elem_bytes(pl->ta);
-    a.A = pl->swapped ? B : A;
-    a.B = pl->swapped ? A : B;
-    a.lda = pl->swapped ? ldb : lda;
-    a.ldb = pl->swapped ? lda : ldb;
+    a.A = e.A; a.B = e.B; a.C = e.C;
+    a.lda = e.lda; a.ldb = e.ldb; a.ldc = e.ldc;
     a.scale_a = pl->swapped ? scale_b : scale_a;
     a.scale_b = pl->swapped ? scale_a : scale_b;
-    // Loads use 32-bit offsets within one tile's slab of each operand.
-    const int64_t lim = (int64_t(1) << 31) - 1;
-    const int64_t span_a = pl->akc ? int64_t(pl->BM) * a.lda * eb + 128 : int64_t(pl->BK) * a.lda * eb + 512;
-    const int64_t span_b = pl->bkc ? int64_t(pl->BN) * a.ldb * eb + 128 : int64_t(pl->BK) * a.ldb * eb + 512;
-    if (span_a > lim || span_b > lim) return SKGEMM_ERR_UNSUPPORTED;
-    a.C = C;
-    a.ldc = ldc;
     a.M = pl->Ml; a.N = pl->Nl; a.K = pl->Kl;
-    a.tm = pl->tm; a.tn = pl->tn; a.t = pl->t; a.ipt = pl->ipt;
-    a.sk_tiles = pl->sk_tiles; a.g_sk = pl->g_sk;
-    a.sk_iters = pl->sk_tiles * pl->ipt;
-    a.sk_q = pl->sk_q; a.sk_r = pl->sk_r;
-    a.grid = pl->grid;
-    a.sk_first = pl->sk_first ? 1 : 0;
-    a.dp_only = pl->g_sk == 0 ? 1 : 0;
+    a.tm = pl->tm; a.tn = pl->tn; a.ipt = pl->ipt;
     a.alpha = alpha;
     a.beta = beta;
-    a.out_dtype = pl->out;
-    a.vec_a = 16;
-    a.vec_b = 16;
-    if (pl->ws_bytes) {
-        unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
-        a.err = reinterpret_cast<int32_t*>(ws);
-        a.flags = reinterpret_cast<int32_t*>(ws + pl->flags_off);
-        a.partials = reinterpret_cast<float*>(ws + pl->partials_off);
-    }
-    a.trace = trace;
-    a.trace_per_wg = trace ? pl->max_segs : 0;
-    a.spin_limit = 1 << 22;
+    fill_schedule_args(pl, &a, workspace, trace);
     if (pl->grid == 0) return SKGEMM_OK;
     const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, a, pl->grid, stream);
     return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
@@ -418,12 +533,70 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan, const void* A, int64_t lda
                     trace_records, stream);
 }
 
+skgemm_status_t skgemm_grouped_table_size(skgemm_plan_t pl, size_t* bytes) {
+    if (!pl || !bytes || !pl->G) return SKGEMM_ERR_INVALID_ARG;
+    *bytes = size_t(pl->G) * sizeof(GroupEntry);
+    return SKGEMM_OK;
+}
+
+skgemm_status_t skgemm_grouped_table(skgemm_plan_t pl, const skgemm_group_args_t* args, void* table,
+                                     size_t bytes) {
+    if (!pl || !pl->G || !args || !table || bytes < size_t(pl->G) * sizeof(GroupEntry)) return SKGEMM_ERR_INVALID_ARG;
+    GroupEntry* out = reinterpret_cast<GroupEntry*>(table);
+    for (int i = 0; i < pl->G; ++i) {
+        GroupEntry e;
+        std::memset(&e, 0, sizeof(e));
+        const skgemm_group_args_t& g = args[i];
+        const skgemm_status_t st =
+            check_problem(pl, pl->gM[i], pl->gN[i], pl->gK[i], g.A, g.lda, g.B, g.ldb, g.C, g.ldc, &e);
+        if (st != SKGEMM_OK) return st;
+        e.iter_base = pl->iter_base[i];
+        e.M = pl->pM[i]; e.N = pl->pN[i]; e.K = pl->pK[i];
+        e.tm = pl->ptm[i]; e.tn = pl->ptn[i]; e.ipt = pl->pipt[i];
+        e.tile_base = pl->tile_base[i];
+        e.alpha = g.alpha;
+        e.beta = g.beta;
+        std::memcpy(&out[i], &e, sizeof(e));
+    }
+    return SKGEMM_OK;
+}
+
+static skgemm_status_t grouped_impl(skgemm_plan_t pl, const void* table_dev, void* workspace, size_t ws_bytes,
+                                    int32_t* trace, size_t trace_records, hipStream_t stream) {
+    if (!pl || !pl->G || !table_dev) return SKGEMM_ERR_INVALID_ARG;
+    if (pl->ws_bytes) {
+        if (!workspace || ws_bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255))
+            return SKGEMM_ERR_WORKSPACE;
+    }
+    if (trace && trace_records < size_t(pl->grid) * size_t(pl->max_segs)) return SKGEMM_ERR_INVALID_ARG;
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.group = reinterpret_cast<const GroupEntry*>(table_dev);
+    a.G = pl->G;
+    fill_schedule_args(pl, &a, workspace, trace);
+    if (pl->grid == 0) return SKGEMM_OK;
+    const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, a, pl->grid, stream);
+    return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
+}
+
+skgemm_status_t skgemm_grouped_run(skgemm_plan_t plan, const void* table_dev, void* workspace, size_t ws_bytes,
+                                   hipStream_t stream) {
+    return grouped_impl(plan, table_dev, workspace, ws_bytes, nullptr, 0, stream);
+}
+
+skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_dev, void* workspace,
+                                          size_t ws_bytes, int32_t* trace, size_t trace_records,
+                                          hipStream_t stream) {
+    if (!trace) return SKGEMM_ERR_INVALID_ARG;
+    return grouped_impl(plan, table_dev, workspace, ws_bytes, trace, trace_records, stream);
+}
+
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[20] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[21] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
-                           pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0};
-    for (int i = 0; i < n && i < 20; ++i) info[i] = v[i];
+                           pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G};
+    for (int i = 0; i < n && i < 21; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 
@@ -456,6 +629,31 @@ skgemm_status_t skgemm_check_device_error(const void* workspace, hipStream_t str
         return SKGEMM_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return SKGEMM_ERR_HIP;
     return word == 0 ? SKGEMM_OK : SKGEMM_ERR_TIMEOUT;
+}
+
+skgemm_status_t skgemm_quantize_workspace_size(size_t* bytes) {
+    if (!bytes) return SKGEMM_ERR_INVALID_ARG;
+    *bytes = size_t(quant_workspace_floats()) * sizeof(float);
+    return SKGEMM_OK;
+}
+
+skgemm_status_t skgemm_quantize_e4m3(const void* X, skgemm_dtype_t tx, int64_t rows, int64_t cols,
+                                     skgemm_layout_t lx, int64_t ldx, void* Q, skgemm_layout_t lq, int64_t ldq,
+                                     float* scale, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (tx != SKGEMM_F32 && tx != SKGEMM_BF16 && tx != SKGEMM_F16) return SKGEMM_ERR_UNSUPPORTED;
+    if (rows < 0 || cols < 0 || (lx != SKGEMM_ROW_MAJOR && lx != SKGEMM_COL_MAJOR) ||
+        (lq != SKGEMM_ROW_MAJOR && lq != SKGEMM_COL_MAJOR))
+        return SKGEMM_ERR_INVALID_ARG;
+    const int64_t x_min = lx == SKGEMM_ROW_MAJOR ? cols : rows, q_min = lq == SKGEMM_ROW_MAJOR ? cols : rows;
+    if (ldx < std::max<int64_t>(1, x_min) || ldq < std::max<int64_t>(1, q_min)) return SKGEMM_ERR_INVALID_ARG;
+    if (!scale || (rows > 0 && cols > 0 && (!X || !Q))) return SKGEMM_ERR_INVALID_ARG;
+    if ((rows + 63) / 64 > 65535 || (cols + 63) / 64 > kMaxDim) return SKGEMM_ERR_UNSUPPORTED;
+    const size_t need = size_t(quant_workspace_floats()) * sizeof(float);
+    if (!workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 3)) return SKGEMM_ERR_WORKSPACE;
+    const int rc = launch_quantize(to_dt(tx), X, rows, cols, ldx, lx == SKGEMM_COL_MAJOR,
+                                   reinterpret_cast<uint8_t*>(Q), ldq, lq == SKGEMM_COL_MAJOR, scale,
+                                   reinterpret_cast<float*>(workspace), stream);
+    return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
 }
 
 skgemm_status_t skgemm_plan_destroy(skgemm_plan_t plan) {

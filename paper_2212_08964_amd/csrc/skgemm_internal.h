@@ -20,6 +20,21 @@ constexpr TileCfg kTileF32 = {128, 128, 32};
 constexpr TileCfg kTile16 = {256, 256, 64};    // bf16 and f16
 constexpr TileCfg kTileF8 = {256, 256, 128};
 
+// One problem of a grouped launch (device table entry, 128 bytes).  Shapes are
+// as launched (operands already swapped when C is column-major).
+struct GroupEntry {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    int64_t iter_base;          // global MAC-loop iteration of the problem's first tile
+    int32_t M, N, K, tm, tn, ipt;
+    int32_t tile_base;          // global index of the problem's first tile
+    float alpha, beta;
+    int32_t pad[9];
+};
+static_assert(sizeof(GroupEntry) == 128, "group table entry layout");
+
 // Kernel arguments, passed by value.  Operands are described relative to the
 // reduction: an operand is "K-contiguous" when consecutive k are adjacent in
 // memory (row-major A, column-major B).
@@ -43,6 +58,8 @@ struct KArgs {
     int32_t* trace;
     int32_t trace_per_wg;
     int32_t spin_limit;
+    const GroupEntry* group;   // grouped launch: G problem entries (else null)
+    int32_t G;
 };
 
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
@@ -53,5 +70,11 @@ int kernel_occupancy(int dtype, bool a_kcontig, bool b_kcontig);
 bool kernel_exists(int dtype, bool a_kcontig, bool b_kcontig);
 // Threads per workgroup of the dtype's kernel.
 int kernel_threads(int dtype);
+
+// Per-tensor E4M3 quantisation (three launches on `stream`).
+int launch_quantize(int dtype, const void* x, int64_t rows, int64_t cols, int64_t ldx, bool x_col, uint8_t* q,
+                    int64_t ldq, bool q_col, float* scale, float* partial, void* stream);
+// FP32 scratch values the quantiser needs.
+int quant_workspace_floats();
 
 }  // namespace skg

@@ -266,6 +266,17 @@ __device__ __forceinline__ void store_c1(void* C, int64_t off, float v) {
 
 // ------------------------------------------------------------------ the kernel
 
+// The problem a segment belongs to (the whole launch for a single GEMM, one
+// table entry for a grouped launch).
+struct Prob {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t lda, ldb, ldc;
+    int M, N, K, tn, ipt;
+    float alpha, beta;
+};
+
 template <int DT, bool AKC, bool BKC>
 struct Gemm {
     static constexpr int EB = Cfg<DT>::EB, BM = Cfg<DT>::BM, BN = Cfg<DT>::BN, BK = Cfg<DT>::BK;
@@ -393,7 +404,7 @@ struct Gemm {
     // stage `nx`, run the MFMAs of stage `cu`, then wait for the loads and
     // synchronise.  Stages are distinct LDS objects, so the compiler can see
     // that the loads in flight do not touch the stage being read.
-    static __device__ __forceinline__ bool step(const KArgs& a, const SA& sa, const SB& sb, int kk, int klo,
+    static __device__ __forceinline__ bool step(const Prob& a, const SA& sa, const SB& sb, int kk, int klo,
                                                 int khi, int m0, int n0, unsigned char* cu, unsigned char* nx,
                                                 Acc& acc, int tid) {
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
@@ -413,7 +424,7 @@ struct Gemm {
     }
 
     // MAC-loop iterations [klo, khi) of one tile into acc (zeroed first).
-    static __device__ __forceinline__ void mac_loop(const KArgs& a, unsigned char* s0, unsigned char* s1,
+    static __device__ __forceinline__ void mac_loop(const Prob& a, unsigned char* s0, unsigned char* s1,
                                                     int tile, int klo, int khi, Acc& acc, int tid) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -502,15 +513,16 @@ struct Gemm {
     static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
 
     template <int OUT>
-    static __device__ __forceinline__ void epilogue_t(const KArgs& a, int tile, const Acc& acc, int tid,
-                                                      unsigned char* s0, unsigned char* s1) {
+    static __device__ __forceinline__ void epilogue_t(const Prob& a, const float* scale_a, const float* scale_b,
+                                                      int tile, const Acc& acc, int tid, unsigned char* s0,
+                                                      unsigned char* s1) {
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const int g = lane >> 5, l32 = lane & 31;
         const int m0 = (tile / a.tn) * BM + wm * WTM, n0 = (tile % a.tn) * BN + wn * WTN;
         float* st = reinterpret_cast<float*>((w < NW / 2 ? s0 : s1) + (w % (NW / 2)) * EPI_BYTES);
         float s = a.alpha;
-        if (a.scale_a) s *= *a.scale_a;
-        if (a.scale_b) s *= *a.scale_b;
+        if (scale_a) s *= *scale_a;
+        if (scale_b) s *= *scale_b;
         constexpr int LPR = WTN / 8;          // lanes per row
         constexpr int RPP = 64 / LPR;         // rows per pass
         const int col = n0 + (lane % LPR) * 8;
@@ -582,11 +594,38 @@ struct Gemm {
         }
     }
 
-    static __device__ __forceinline__ void epilogue(const KArgs& a, int tile, const Acc& acc, int tid,
-                                                    unsigned char* s0, unsigned char* s1) {
-        if (a.out_dtype == DT_F32) epilogue_t<DT_F32>(a, tile, acc, tid, s0, s1);
-        else if (a.out_dtype == DT_BF16) epilogue_t<DT_BF16>(a, tile, acc, tid, s0, s1);
-        else epilogue_t<DT_F16>(a, tile, acc, tid, s0, s1);
+    static __device__ __forceinline__ void epilogue(const KArgs& ka, const Prob& a, int tile, const Acc& acc,
+                                                    int tid, unsigned char* s0, unsigned char* s1) {
+        if (ka.out_dtype == DT_F32) epilogue_t<DT_F32>(a, ka.scale_a, ka.scale_b, tile, acc, tid, s0, s1);
+        else if (ka.out_dtype == DT_BF16) epilogue_t<DT_BF16>(a, ka.scale_a, ka.scale_b, tile, acc, tid, s0, s1);
+        else epilogue_t<DT_F16>(a, ka.scale_a, ka.scale_b, tile, acc, tid, s0, s1);
+    }
+
+    // Grouped launches: the problem holding a global iteration / tile (the
+    // last entry whose base is <= x; empty problems share the next base and
+    // are skipped by taking the last).
+    static __device__ __forceinline__ int find_iter(const KArgs& a, int64_t x) {
+        int lo = 0, hi = a.G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.group[mid].iter_base <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+
+    static __device__ __forceinline__ int find_tile(const KArgs& a, int x) {
+        int lo = 0, hi = a.G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.group[mid].tile_base <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
+
+    static __device__ __forceinline__ Prob entry_prob(const GroupEntry& e) {
+        return Prob{e.A, e.B, e.C, e.lda, e.ldb, e.ldc, e.M, e.N, e.K, e.tn, e.ipt, e.alpha, e.beta};
     }
 
     static __device__ __forceinline__ int share_start(int x, int q, int r) { return x * q + min(x, r); }
@@ -595,6 +634,11 @@ struct Gemm {
         return (i < r * (q + 1)) ? i / (q + 1) : r + (i - r * (q + 1)) / q;
     }
 
+    // The segment walk of the basic Stream-K algorithm (with the hybrids'
+    // data-parallel tiles): a workgroup takes its contiguous share of the
+    // Stream-K iterations, cut at tile seams, before or after its whole
+    // data-parallel tiles.  Iterations and tiles are global indices; a grouped
+    // launch concatenates the problems' iteration spaces.
     static __device__ __forceinline__ void run(const KArgs& a, unsigned char* s0, unsigned char* s1) {
         const int tid = threadIdx.x;
         const int wg = blockIdx.x;
@@ -605,15 +649,28 @@ struct Gemm {
         }
         int dp_tile = a.sk_tiles + wg;
         int seq = 0;
+        const Prob single = {a.A, a.B, a.C, a.lda, a.ldb, a.ldc, a.M, a.N, a.K, a.tn, a.ipt, a.alpha, a.beta};
         Acc acc;
         for (;;) {
             const bool sk_left = sk_it < sk_end, dp_left = dp_tile < a.t;
             if (!sk_left && !dp_left) break;
             const bool take_sk = a.sk_first ? sk_left : !dp_left;
-            int tile, lo, hi, role, peer_end = -1;
+            Prob pr = single;
+            int gtile, tile, lo, hi, role, peer_end = -1;
             if (take_sk) {
-                tile = sk_it / a.ipt;
-                const int first = tile * a.ipt, last = first + a.ipt;
+                int first;
+                if (a.G) {
+                    const GroupEntry& e = a.group[find_iter(a, sk_it)];
+                    pr = entry_prob(e);
+                    tile = int((sk_it - e.iter_base) / e.ipt);
+                    first = int(e.iter_base) + tile * e.ipt;
+                    gtile = e.tile_base + tile;
+                } else {
+                    tile = sk_it / a.ipt;
+                    first = tile * a.ipt;
+                    gtile = tile;
+                }
+                const int last = first + pr.ipt;
                 lo = sk_it - first;
                 hi = min(sk_end, last) - first;
                 if (sk_it != first) {
@@ -626,21 +683,27 @@ struct Gemm {
                 }
                 sk_it = last;
             } else {
+                gtile = dp_tile;
                 tile = dp_tile;
+                if (a.G) {
+                    const GroupEntry& e = a.group[find_tile(a, dp_tile)];
+                    pr = entry_prob(e);
+                    tile = dp_tile - e.tile_base;
+                }
                 lo = 0;
-                hi = a.ipt;
+                hi = pr.ipt;
                 role = ROLE_FULL;
                 dp_tile += a.grid;
             }
             if (a.trace && tid == 0 && seq < a.trace_per_wg) {
                 int32_t* rec = a.trace + ((size_t)wg * a.trace_per_wg + seq) * kTraceFields;
-                rec[0] = wg; rec[1] = seq; rec[2] = tile; rec[3] = lo; rec[4] = hi; rec[5] = role;
+                rec[0] = wg; rec[1] = seq; rec[2] = gtile; rec[3] = lo; rec[4] = hi; rec[5] = role;
                 rec[6] = role == ROLE_OWNER ? wg + 1 : -1;
                 rec[7] = role == ROLE_OWNER ? peer_end : -1;
             }
             ++seq;
 
-            mac_loop(a, s0, s1, tile, lo, hi, acc, tid);
+            mac_loop(pr, s0, s1, tile, lo, hi, acc, tid);
 
             if (role == ROLE_PARTIAL) {
                 store_partial(a.partials + (size_t)wg * (BM * BN), acc, tid);
@@ -671,7 +734,7 @@ struct Gemm {
                         if (tid == 0) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-                epilogue(a, tile, acc, tid, s0, s1);
+                epilogue(a, pr, tile, acc, tid, s0, s1);
             }
         }
     }

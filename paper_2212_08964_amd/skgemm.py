@@ -29,16 +29,24 @@ EXPORTED = [
     "skgemm_default_options", "skgemm_plan", "skgemm_workspace_size", "skgemm_run",
     "skgemm_trace_capacity", "skgemm_run_traced", "skgemm_plan_info", "skgemm_model_constants",
     "skgemm_schedule", "skgemm_check_device_error", "skgemm_plan_destroy", "skgemm_status_string",
+    "skgemm_grouped_plan", "skgemm_grouped_table_size", "skgemm_grouped_table", "skgemm_grouped_run",
+    "skgemm_grouped_run_traced", "skgemm_quantize_workspace_size", "skgemm_quantize_e4m3",
 ]
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
-               "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig"]
+               "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G"]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int), ("force_g", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
                 ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
+
+
+class GroupArgs(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("alpha", ctypes.c_float), ("beta", ctypes.c_float)]
 
 
 class SkgemmError(RuntimeError):
@@ -79,6 +87,15 @@ def lib():
                 L.skgemm_plan_destroy.argtypes = [vp]
                 L.skgemm_status_string.argtypes = [ctypes.c_int]
                 L.skgemm_status_string.restype = ctypes.c_char_p
+                L.skgemm_grouped_plan.argtypes = [P(vp), i32, P(i64), P(i64), P(i64), ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Options)]
+                L.skgemm_grouped_table_size.argtypes = [vp, P(sz)]
+                L.skgemm_grouped_table.argtypes = [vp, P(GroupArgs), vp, sz]
+                L.skgemm_grouped_run.argtypes = [vp, vp, vp, sz, vp]
+                L.skgemm_grouped_run_traced.argtypes = [vp, vp, vp, sz, vp, sz, vp]
+                L.skgemm_quantize_workspace_size.argtypes = [P(sz)]
+                L.skgemm_quantize_e4m3.argtypes = [vp, ctypes.c_int, i64, i64, ctypes.c_int, i64, vp, ctypes.c_int,
+                                                   i64, vp, vp, sz, vp]
                 for name in EXPORTED:
                     if name not in ("skgemm_default_options", "skgemm_status_string"):
                         getattr(L, name).restype = ctypes.c_int
@@ -140,8 +157,8 @@ class Plan:
         return n.value
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 20)()
-        _check(lib().skgemm_plan_info(self._h, buf, 20), "skgemm_plan_info")
+        buf = (ctypes.c_int64 * 21)()
+        _check(lib().skgemm_plan_info(self._h, buf, 21), "skgemm_plan_info")
         d = dict(zip(INFO_FIELDS, list(buf)))
         d["policy_name"] = POLICY_NAME[d["policy"]]
         return d
@@ -171,6 +188,52 @@ class Plan:
         _check(lib().skgemm_run_traced(self._h, A, int(lda), B, int(ldb), C, int(ldc), float(alpha),
                                        float(beta), scale_a, scale_b, workspace, int(ws_bytes), trace,
                                        int(trace_records), stream), "skgemm_run_traced")
+
+
+class GroupedPlan(Plan):
+    """Owns one grouped skgemm_plan_t (several problems, one launch)."""
+
+    def __init__(self, Ms, Ns, Ks, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0):
+        self._h = ctypes.c_void_p()
+        G = len(Ms)
+        if not (len(Ns) == len(Ks) == G):
+            raise ValueError("Ms, Ns, Ks must have the same length")
+        o = default_options()
+        o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
+        o.force_g = int(force_g)
+        o.hybrid_min_waves = int(hybrid_min_waves)
+        o.num_cus = int(num_cus)
+        o.occupancy = int(occupancy)
+        tc = ta if tc is None else tc
+        arr = ctypes.c_int64 * max(G, 1)
+        _check(lib().skgemm_grouped_plan(ctypes.byref(self._h), G, arr(*Ms), arr(*Ns), arr(*Ks), la, lb, lc, ta, ta,
+                                         tc, ctypes.byref(o)), "skgemm_grouped_plan")
+        self.Ms, self.Ns, self.Ks = [int(x) for x in Ms], [int(x) for x in Ns], [int(x) for x in Ks]
+        self.la, self.lb, self.lc, self.ta, self.tc = la, lb, lc, ta, tc
+
+    def table_size(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().skgemm_grouped_table_size(self._h, ctypes.byref(n)), "skgemm_grouped_table_size")
+        return n.value
+
+    def table(self, args) -> bytes:
+        """Host table for args: list of (A, lda, B, ldb, C, ldc, alpha, beta) with device pointers."""
+        G = len(self.Ms)
+        ga = (GroupArgs * G)()
+        for i, (A, lda, B, ldb, C, ldc, alpha, beta) in enumerate(args):
+            ga[i] = GroupArgs(A, B, C, int(lda), int(ldb), int(ldc), float(alpha), float(beta))
+        n = self.table_size()
+        buf = ctypes.create_string_buffer(n)
+        _check(lib().skgemm_grouped_table(self._h, ga, buf, n), "skgemm_grouped_table")
+        return buf.raw
+
+    def grouped_run(self, table_dev, workspace=None, ws_bytes=0, stream=None):
+        _check(lib().skgemm_grouped_run(self._h, table_dev, workspace, int(ws_bytes), stream), "skgemm_grouped_run")
+
+    def grouped_run_traced(self, table_dev, workspace, ws_bytes, trace, trace_records, stream=None):
+        _check(lib().skgemm_grouped_run_traced(self._h, table_dev, workspace, int(ws_bytes), trace,
+                                               int(trace_records), stream), "skgemm_grouped_run_traced")
 
 
 def check_device_error(workspace_ptr, stream=None):
@@ -278,3 +341,122 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     else:
         plan.run_traced(*args, trace.data_ptr(), trace.numel() // 8, stream=stream)
     return out
+
+
+def _layout_of(t):
+    la = _layout(t)
+    if la is None:
+        raise ValueError("operand needs one contiguous dimension")
+    return la
+
+
+_gplan_cache = {}
+
+
+def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, policy="auto", force_g=0,
+                   hybrid_min_waves=2, trace=None, table=None):
+    """C_i = alpha * A_i @ B_i + beta * C_i for every i, in ONE persistent launch.
+
+    All A_i share a layout, all B_i share a layout, all C_i share a layout
+    and every tensor the same dtype pair.  Returns (Cs, table) where table is
+    the device tensor of the per-problem descriptors; passing it back in with
+    the same tensors skips rebuilding it (e.g. for graph capture)."""
+    import torch
+    dts = _torch_dtypes()
+    G = len(As)
+    if G == 0 or len(Bs) != G:
+        raise ValueError("need as many A as B")
+    dev = As[0].device
+    if out_dtype is None:
+        out_dtype = torch.float32 if As[0].dtype in (torch.float32, torch.float8_e4m3fn) else As[0].dtype
+    if Cs is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs Cs")
+        Cs = [torch.empty((A.shape[0], B.shape[1]), dtype=out_dtype, device=dev) for A, B in zip(As, Bs)]
+    la = {_layout_of(A)[0] for A in As}
+    lb = {_layout_of(B)[0] for B in Bs}
+    lc = {_layout_of(C)[0] for C in Cs}
+    if len(la) != 1 or len(lb) != 1 or len(lc) != 1:
+        raise ValueError("all A (B, C) of a group must share one layout")
+    la, lb, lc = la.pop(), lb.pop(), lc.pop()
+    Ms = [A.shape[0] for A in As]
+    Ns = [B.shape[1] for B in Bs]
+    Ks = [A.shape[1] for A in As]
+    key = (tuple(Ms), tuple(Ns), tuple(Ks), la, lb, lc, dts[As[0].dtype], dts[Cs[0].dtype], policy, force_g,
+           hybrid_min_waves)
+    plan = _gplan_cache.get(key)
+    if plan is None:
+        plan = GroupedPlan(Ms, Ns, Ks, la, lb, lc, dts[As[0].dtype], dts[Cs[0].dtype], policy=policy,
+                           force_g=force_g, hybrid_min_waves=hybrid_min_waves)
+        if len(_gplan_cache) > 256:
+            _gplan_cache.clear()
+        _gplan_cache[key] = plan
+    if table is None:
+        args = []
+        for A, B, C in zip(As, Bs, Cs):
+            args.append((A.data_ptr() if A.numel() else None, _layout_of(A)[1],
+                         B.data_ptr() if B.numel() else None, _layout_of(B)[1],
+                         C.data_ptr() if C.numel() else None, _layout_of(C)[1], alpha, beta))
+        host = plan.table(args)
+        table = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
+    nws = plan.workspace_size()
+    ws = workspace(nws, dev) if nws else None
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    if trace is None:
+        plan.grouped_run(table.data_ptr(), ws.data_ptr() if ws is not None else None, nws, stream)
+    else:
+        plan.grouped_run_traced(table.data_ptr(), ws.data_ptr() if ws is not None else None, nws,
+                                trace.data_ptr(), trace.numel() // 8, stream)
+    return Cs, table
+
+
+_qws = {}
+
+
+def quantize_e4m3(X, layout="row", out=None, scale=None):
+    """Per-tensor E4M3 quantisation of a 2-D FP32/BF16/FP16 tensor on the GPU.
+
+    Returns (Q, scale): Q a float8_e4m3fn tensor of X's shape stored row-major
+    (layout="row") or column-major (layout="col", a transposed view of an
+    N x M row-major buffer), scale a 1-element FP32 device tensor."""
+    import torch
+    dts = _torch_dtypes()
+    if X.dim() != 2 or X.dtype not in (torch.float32, torch.bfloat16, torch.float16):
+        raise ValueError("quantize_e4m3 needs a 2-D FP32, BF16 or FP16 tensor")
+    rows, cols = X.shape
+    lx = _layout(X)
+    if lx is None:
+        X = X.contiguous()
+        lx = _layout(X)
+    if out is None:
+        if layout == "row":
+            out = torch.empty((rows, cols), dtype=torch.float8_e4m3fn, device=X.device)
+        else:
+            out = torch.empty((cols, rows), dtype=torch.float8_e4m3fn, device=X.device).t()
+    lq = _layout(out)
+    if scale is None:
+        scale = torch.empty(1, dtype=torch.float32, device=X.device)
+    key = X.device.index
+    ws = _qws.get(key)
+    if ws is None:
+        n = ctypes.c_size_t()
+        _check(lib().skgemm_quantize_workspace_size(ctypes.byref(n)), "skgemm_quantize_workspace_size")
+        ws = torch.empty(n.value // 4, dtype=torch.float32, device=X.device)
+        _qws[key] = ws
+    stream = torch.cuda.current_stream(X.device).cuda_stream
+    _check(lib().skgemm_quantize_e4m3(X.data_ptr() if X.numel() else None, dts[X.dtype], rows, cols, lx[0], lx[1],
+                                      out.data_ptr() if out.numel() else None, lq[0], lq[1], scale.data_ptr(),
+                                      ws.data_ptr(), ws.numel() * 4, stream), "skgemm_quantize_e4m3")
+    return out, scale
+
+
+def matmul_fp8(A, B, *, out_dtype=None, alpha=1.0, policy="auto", force_g=0):
+    """FP8 GEMM of higher-precision A and B: per-tensor E4M3 quantisation of
+    A (row-major) and B (column-major), then the FP8 Stream-K GEMM with the
+    scales applied in the epilogue.  Returns (C, (qA, sA), (qB, sB))."""
+    import torch
+    qa, sa = quantize_e4m3(A, "row")
+    qb, sb = quantize_e4m3(B, "col")
+    C = matmul(qa, qb, out_dtype=out_dtype or torch.float32, alpha=alpha, scale_a=sa, scale_b=sb,
+               policy=policy, force_g=force_g)
+    return C, (qa, sa), (qb, sb)

@@ -135,3 +135,56 @@ def test_workspace_scales_with_grid_not_problem():
     assert small.workspace_size() == big.workspace_size()
     dp = sk.Plan(3000, 3000, 4096, ta=sk.BF16, policy="dp", num_cus=256, occupancy=1)
     assert dp.workspace_size() == 0
+
+
+@pytest.mark.parametrize("policy", ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
+def test_grouped_planner_matches_enumerator(policy):
+    from oracle import grouped as GR
+    import workloads as W
+    sk = _lib()
+    groups = [
+        [(m, 4096, 2048) for m in W.zipf_ms(64, seed=0)],
+        [(100, 300, 16), (0, 50, 70), (700, 900, 5000), (1, 1, 1)],
+        [(256 * 3, 256 * 5, 640)] * 7,
+    ]
+    for probs, (cus, occ) in itertools.product(groups, [(256, 1), (16, 1), (37, 2)]):
+        Ms, Ns, Ks = zip(*probs)
+        try:
+            p = sk.GroupedPlan(Ms, Ns, Ks, ta=sk.BF16, policy=policy, num_cus=cus, occupancy=occ)
+        except sk.SkgemmError as e:
+            assert e.status == sk.ERR_CAPACITY
+            continue
+        info = p.info()
+        ref = GR.make_grouped_plan(probs, info["BM"], info["BN"], info["BK"], info["p"], policy=policy,
+                                   hybrid_min_waves=2, model=p.model_constants())
+        assert (ref.policy, ref.sk_tiles, ref.g_sk, ref.grid) == (
+            POLICY_BY_ID[info["policy"]], info["sk_tiles"], info["g_sk"], info["grid"])
+        got = records_to_schedule(p.schedule(), info["grid"])
+        assert got == GR.enumerate_grouped_schedule(ref)
+        GR.check_grouped_invariants(ref, got)
+
+
+def test_grouped_and_quantize_argument_errors():
+    sk = _lib()
+    L = sk.lib()
+    h = ctypes.c_void_p()
+    arr = ctypes.c_int64 * 2
+    o = sk.default_options()
+    o.num_cus, o.occupancy = 256, 1
+    assert L.skgemm_grouped_plan(ctypes.byref(h), 0, arr(1, 1), arr(1, 1), arr(1, 1), 0, 0, 0, sk.BF16, sk.BF16,
+                                 sk.BF16, ctypes.byref(o)) == sk.ERR_INVALID_ARG
+    assert L.skgemm_grouped_plan(ctypes.byref(h), 2, arr(4, 4), arr(4, 4), arr(4, 0), 0, 0, 0, sk.BF16, sk.BF16,
+                                 sk.BF16, ctypes.byref(o)) == sk.ERR_UNSUPPORTED
+    g = sk.GroupedPlan([64, 64], [64, 64], [64, 64], ta=sk.BF16, num_cus=256, occupancy=1)
+    fake = 1 << 40
+    bad = [(fake, 63, fake, 64, fake, 64, 1.0, 0.0), (fake, 64, fake, 64, fake, 64, 1.0, 0.0)]   # lda < K
+    with pytest.raises(sk.SkgemmError):
+        g.table(bad)
+    n = ctypes.c_size_t()
+    assert L.skgemm_quantize_workspace_size(ctypes.byref(n)) == sk.OK and n.value > 0
+    assert L.skgemm_quantize_e4m3(fake, sk.F8E4M3, 4, 4, 0, 4, fake, 0, 4, fake, fake, n.value,
+                                  None) == sk.ERR_UNSUPPORTED
+    assert L.skgemm_quantize_e4m3(fake, sk.BF16, 4, 4, 0, 3, fake, 0, 4, fake, fake, n.value,
+                                  None) == sk.ERR_INVALID_ARG
+    assert L.skgemm_quantize_e4m3(fake, sk.BF16, 4, 4, 0, 4, fake, 0, 4, fake, fake, n.value - 4,
+                                  None) == sk.ERR_WORKSPACE

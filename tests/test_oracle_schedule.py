@@ -176,3 +176,38 @@ def test_planted_mistake_is_caught():
     broken[0][-1] = S.Segment(s0.tile, s0.k_lo, s0.k_hi, s0.role, (2,))
     with pytest.raises(AssertionError):
         S.check_invariants(pl, broken)
+
+
+# ------------------------------------------------------------------ grouped launches
+
+def test_grouped_single_problem_equals_single_enumerator():
+    from oracle import grouped as GR
+    for (M, N, K), p, pol in itertools.product([(384, 384, 128), (896, 384, 128), (1000, 130, 77)], [4, 9, 64],
+                                               ["auto", "sk", "dp", "dp_1tile_sk", "2tile_sk_dp"]):
+        g = GR.make_grouped_plan([(M, N, K)], 128, 128, 4, p, policy=pol, model=(0, 20, 1, 8))
+        s = S.make_plan(M, N, K, 128, 128, 4, p, policy=pol, model=(0, 20, 1, 8))
+        assert (g.policy, g.sk_tiles, g.g_sk, g.grid) == (s.policy, s.sk_tiles, s.g_sk, s.grid)
+        assert GR.enumerate_grouped_schedule(g) == S.enumerate_schedule(s)
+
+
+def test_grouped_equal_ipt_is_one_long_tile_row():
+    """Problems with equal iterations per tile concatenate into the same
+    iteration space as one GEMM whose tile count is their sum."""
+    from oracle import grouped as GR
+    probs = [(128 * 3, 128 * 2, 256), (128, 128 * 5, 256), (128 * 2, 128, 256)]   # 6 + 5 + 2 tiles, ipt 64
+    for p, pol in itertools.product([3, 4, 7, 32], ["sk", "2tile_sk_dp", "dp_1tile_sk", "auto"]):
+        g = GR.make_grouped_plan(probs, 128, 128, 4, p, policy=pol, model=(0, 20, 1, 8))
+        s = S.make_plan(128 * 13, 128, 256, 128, 128, 4, p, policy=pol, model=(0, 20, 1, 8))
+        assert GR.enumerate_grouped_schedule(g) == S.enumerate_schedule(s)
+
+
+def test_grouped_ragged_invariants():
+    from oracle import grouped as GR
+    rng = __import__("random").Random(0)
+    for _ in range(60):
+        G = rng.randint(1, 6)
+        probs = [(rng.randint(0, 9), rng.randint(1, 9), rng.randint(1, 9)) for _ in range(G)]
+        for p in (1, 2, 5, 16):
+            for pol in ("auto", "sk", "dp", "dp_1tile_sk", "2tile_sk_dp"):
+                g = GR.make_grouped_plan(probs, 2, 2, 1, p, policy=pol)
+                GR.check_grouped_invariants(g, GR.enumerate_grouped_schedule(g))
