@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-shape", action="store_true")
+    ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many Stream-K steps (for profiler runs) and print timings")
     return ap.parse_args()
@@ -223,6 +224,13 @@ def main():
                 arr[i] = e0.elapsed_time(e1) / args.reps
         ratios = t_dp / t_sk
         qb = np.array([c.t / (c.p * math.ceil(c.t / c.p)) < 0.9 for c in cases])
+        if args.dump:
+            with open(args.dump, "w") as fh:
+                for c, a_, b_ in zip(cases, t_sk, t_dp):
+                    info = c.sk.info()
+                    fh.write(json.dumps({"M": c.M, "N": c.N, "K": c.K, "t": c.t, "ipt": info["ipt"],
+                                         "policy": info["policy_name"], "g": info["g_sk"], "sk_us": a_ * 1e3,
+                                         "dp_us": b_ * 1e3, "gflop": c.flops / 1e9}) + "\n")
 
         def stats(r):
             return {"geomean": float(np.exp(np.mean(np.log(r)))), "min": float(r.min()),

@@ -254,15 +254,41 @@ def _torch_dtypes():
     return _TORCH_DT
 
 
-def _layout(t):
-    """(layout, ld) of a 2-D tensor, or None if neither dimension is contiguous."""
+def _layouts(t):
+    """Every valid (layout, ld) reading of a 2-D tensor's strides (a tensor with
+    a dimension of size <= 1 is both row- and column-major)."""
     r, c = t.shape
+    if t.numel() == 0:          # no element is addressed: any reading is valid
+        return [(ROW_MAJOR, max(c, 1)), (COL_MAJOR, max(r, 1))]
     s0, s1 = t.stride()
+    out = []
     if s1 == 1 or c <= 1:
-        return ROW_MAJOR, max(s0, c, 1)
+        out.append((ROW_MAJOR, max(s0, c, 1)))
     if s0 == 1 or r <= 1:
-        return COL_MAJOR, max(s1, r, 1)
-    return None
+        out.append((COL_MAJOR, max(s1, r, 1)))
+    return out
+
+
+def _layout(t, prefer=ROW_MAJOR):
+    """(layout, ld) of a 2-D tensor, the preferred reading when both are valid,
+    or None if neither dimension is contiguous."""
+    ls = _layouts(t)
+    for lay in ls:
+        if lay[0] == prefer:
+            return lay
+    return ls[0] if ls else None
+
+
+def _pick(tensors, prefer):
+    """One layout valid for every tensor of a group (the preferred one if
+    possible), with each tensor's leading dimension; None if there is none."""
+    common = {ROW_MAJOR, COL_MAJOR}
+    for t in tensors:
+        common &= {lay for lay, _ in _layouts(t)}
+    if not common:
+        return None
+    lay = prefer if prefer in common else common.pop()
+    return lay, [dict(_layouts(t))[lay] for t in tensors]
 
 
 _ws_cache = {}
@@ -310,11 +336,12 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
         raise ValueError("operands must live on the same GPU")
     M, K = A.shape
     N = B.shape[1]
-    la = _layout(A)
+    # where a degenerate shape allows either reading, take the K-contiguous one
+    la = _layout(A, prefer=ROW_MAJOR)
     if la is None:
         A = A.contiguous()
         la = _layout(A)
-    lb = _layout(B)
+    lb = _layout(B, prefer=COL_MAJOR)
     if lb is None:
         B = B.contiguous()
         lb = _layout(B)
@@ -373,12 +400,10 @@ def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, poli
         if beta != 0.0:
             raise ValueError("beta != 0 needs Cs")
         Cs = [torch.empty((A.shape[0], B.shape[1]), dtype=out_dtype, device=dev) for A, B in zip(As, Bs)]
-    la = {_layout_of(A)[0] for A in As}
-    lb = {_layout_of(B)[0] for B in Bs}
-    lc = {_layout_of(C)[0] for C in Cs}
-    if len(la) != 1 or len(lb) != 1 or len(lc) != 1:
+    pa, pb, pc = _pick(As, ROW_MAJOR), _pick(Bs, COL_MAJOR), _pick(Cs, ROW_MAJOR)
+    if pa is None or pb is None or pc is None:
         raise ValueError("all A (B, C) of a group must share one layout")
-    la, lb, lc = la.pop(), lb.pop(), lc.pop()
+    (la, lda), (lb, ldb), (lc, ldc) = pa, pb, pc
     Ms = [A.shape[0] for A in As]
     Ns = [B.shape[1] for B in Bs]
     Ks = [A.shape[1] for A in As]
@@ -393,10 +418,10 @@ def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, poli
         _gplan_cache[key] = plan
     if table is None:
         args = []
-        for A, B, C in zip(As, Bs, Cs):
-            args.append((A.data_ptr() if A.numel() else None, _layout_of(A)[1],
-                         B.data_ptr() if B.numel() else None, _layout_of(B)[1],
-                         C.data_ptr() if C.numel() else None, _layout_of(C)[1], alpha, beta))
+        for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+            args.append((A.data_ptr() if A.numel() else None, lda[i],
+                         B.data_ptr() if B.numel() else None, ldb[i],
+                         C.data_ptr() if C.numel() else None, ldc[i], alpha, beta))
         host = plan.table(args)
         table = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
     nws = plan.workspace_size()
@@ -433,7 +458,9 @@ def quantize_e4m3(X, layout="row", out=None, scale=None):
             out = torch.empty((rows, cols), dtype=torch.float8_e4m3fn, device=X.device)
         else:
             out = torch.empty((cols, rows), dtype=torch.float8_e4m3fn, device=X.device).t()
-    lq = _layout(out)
+    lq = _layout(out, prefer=COL_MAJOR if layout == "col" else ROW_MAJOR)
+    if lq is None:
+        raise ValueError("out needs one contiguous dimension")
     if scale is None:
         scale = torch.empty(1, dtype=torch.float32, device=X.device)
     key = X.device.index

@@ -7,9 +7,12 @@ the eager result.
 
 FP8: the quantiser's codes and scale must equal the oracle's bit for bit (the
 decision x / s is taken in FP32 on both sides); the FP8 GEMM must match the
-FP64 GEMM of the dequantised inputs within 1e-5 (FP32 accumulation error
-only) and the FP64 GEMM of the unquantised inputs within 6e-2 (total error
-including quantisation).
+FP64 GEMM of the dequantised inputs within 5e-5 and the FP64 GEMM of the
+unquantised inputs within 6e-2 (total error including quantisation).  The
+kernel-error bound is set by the hardware: gfx950's FP8 MFMA adds its
+products at about 16 significant bits before the FP32 accumulate, which
+measures as a relative error of ~1.5e-5 independent of K (FP32 accumulation
+alone would give ~1e-7).
 """
 import numpy as np
 import pytest
@@ -178,5 +181,5 @@ def test_fp8_gemm_parity(shape):
         dqb = to_f64(qb) * sb.item()
         kernel_err = og.rel_frobenius(to_f64(C), og.gemm_f64(dqa, dqb))
         total_err = og.rel_frobenius(to_f64(C), og.gemm_f64(a, b))
-        assert kernel_err <= 1e-5, (pol, kernel_err)
+        assert kernel_err <= 5e-5, (pol, kernel_err)
         assert total_err <= 6e-2, (pol, total_err)
