@@ -71,8 +71,10 @@ def build_cases(shapes, torch, sk):
         c.B = torch.randn((K, N), generator=gen, device=dev, dtype=torch.float32).to(torch.bfloat16)
         c.C = torch.empty((M, N), device=dev, dtype=torch.bfloat16)
         c.sk = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="auto")
-        c.dp = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="dp")
         info = c.sk.info()
+        # the baseline: the same kernel and tile with one workgroup per tile
+        c.dp = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="dp",
+                       tile=info["tile"])
         c.t, c.p = info["t"], info["p"]
         c.flops = 2.0 * M * N * K
         cases.append(c)
@@ -229,7 +231,8 @@ def main():
                 for c, a_, b_ in zip(cases, t_sk, t_dp):
                     info = c.sk.info()
                     fh.write(json.dumps({"M": c.M, "N": c.N, "K": c.K, "t": c.t, "ipt": info["ipt"],
-                                         "policy": info["policy_name"], "g": info["g_sk"], "sk_us": a_ * 1e3,
+                                         "tile": info["BM"], "policy": info["policy_name"], "g": info["g_sk"],
+                                         "sk_us": a_ * 1e3,
                                          "dp_us": b_ * 1e3, "gflop": c.flops / 1e9}) + "\n")
 
         def stats(r):
@@ -262,7 +265,8 @@ def main():
                                "(half multiples of 128, half +1..127), A,B iid N(0,1) bf16, FP32 accumulate, "
                                "bf16 out, row-major",
                    "n_shapes": n, "policy": "auto (DP waves + Stream-K remainder)",
-                   "baseline": "same kernel, policy=dp (one workgroup per 256x256 tile)",
+                   "baseline": "same kernel and tile, policy=dp (one workgroup per tile)",
+                   "tiles": "256x256x64, or 128x128x64 where the model predicts it faster (same tile for both)",
                    "total_gflop": round(total_flops / 1e9, 1), "parallelism": "single GPU"},
         "pct_mfma_peak": round(100.0 * value / PEAK_BF16_TFLOPS, 2),
         "dp_value": round(dp_value, 3),

@@ -9,7 +9,7 @@ times each with HIP events, and fits (a, b, c, d) by least squares.  It
 prints the constants normalised to c = 1, in the form the library's model
 table uses.
 
-Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32|f8]
+Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32] [BMxBNxBK]
 """
 from __future__ import annotations
 
@@ -23,14 +23,14 @@ def model_terms(t, ipt, g):
     return [1.0, 1.0 if peers > 1 else 0.0, float(ipc), float(peers - 1)]
 
 
-def measure(dtype="bf16", reps=20, verbose=True):
+def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     import numpy as np
     import torch
 
     from . import skgemm as sk
     tdt = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}[dtype]
     cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32}[dtype]
-    probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp").info()
+    probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
     BM, BN, BK, p = probe["BM"], probe["BN"], probe["BK"], probe["p"]
     rows, ys = [], []
     for t in (1, 2, 4, 8, 16, 32, 64, 128):
@@ -46,7 +46,7 @@ def measure(dtype="bf16", reps=20, verbose=True):
             gs = sorted({g for g in (t, 2 * t, 3 * t, 4 * t, 6 * t, 8 * t, 12 * t, 16 * t, p)
                          if t <= g <= min(p, t * ipt)})
             for g in gs:
-                sk.matmul(A, B, out=C, policy="sk", force_g=g)
+                sk.matmul(A, B, out=C, policy="sk", force_g=g, tile=(BM, BN, BK))
                 torch.cuda.synchronize()
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
@@ -54,7 +54,7 @@ def measure(dtype="bf16", reps=20, verbose=True):
                 for _ in range(3):
                     e0.record()
                     for _ in range(reps):
-                        sk.matmul(A, B, out=C, policy="sk", force_g=g)
+                        sk.matmul(A, B, out=C, policy="sk", force_g=g, tile=(BM, BN, BK))
                     e1.record()
                     e1.synchronize()
                     best = min(best, e0.elapsed_time(e1) / reps * 1e3)
@@ -71,7 +71,8 @@ def measure(dtype="bf16", reps=20, verbose=True):
 
 def main():
     dtype = sys.argv[1] if len(sys.argv) > 1 else "bf16"
-    norm, raw, X, y = measure(dtype)
+    tile = tuple(int(x) for x in sys.argv[2].split("x")) if len(sys.argv) > 2 else None
+    norm, raw, X, y = measure(dtype, tile=tile)
     a, b, c, d = raw
     pred = X @ [a, b, c, d]
     import numpy as np

@@ -4,13 +4,22 @@
 
 namespace skg {
 
-const void* kernel_fn_bf16(bool akc, bool bkc) {
-    if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true>)
-                        : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false>);
-    return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true>)
-               : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false>);
+const void* kernel_fn_bf16(bool akc, bool bkc, int v) {
+    if (v == 0) {
+        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 0>)
+                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false, 0>);
+        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 0>)
+                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 0>);
+    }
+    if (v == 1) {
+        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 1>)
+                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false, 1>);
+        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 1>)
+                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 1>);
+    }
+    return nullptr;
 }
 
-int kernel_threads_bf16() { return kThreadsOf<DT_BF16>; }
+int kernel_threads_bf16(int v) { return v == 0 ? kThreadsOf<DT_BF16, 0> : v == 1 ? kThreadsOf<DT_BF16, 1> : 0; }
 
 }  // namespace skg

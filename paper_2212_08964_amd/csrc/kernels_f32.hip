@@ -4,13 +4,16 @@
 
 namespace skg {
 
-const void* kernel_fn_f32(bool akc, bool bkc) {
-    if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, true, true>)
-                        : reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, true, false>);
-    return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, false, true>)
-               : reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, false, false>);
+const void* kernel_fn_f32(bool akc, bool bkc, int v) {
+    if (v == 0) {
+        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, true, true, 0>)
+                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, true, false, 0>);
+        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, false, true, 0>)
+                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_F32, false, false, 0>);
+    }
+    return nullptr;
 }
 
-int kernel_threads_f32() { return kThreadsOf<DT_F32>; }
+int kernel_threads_f32(int v) { return v == 0 ? kThreadsOf<DT_F32, 0> : 0; }
 
 }  // namespace skg

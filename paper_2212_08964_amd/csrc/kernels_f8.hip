@@ -4,11 +4,11 @@
 
 namespace skg {
 
-const void* kernel_fn_f8(bool akc, bool bkc) {
-    if (akc && bkc) return reinterpret_cast<const void*>(&skgemm_kernel<DT_F8, true, true>);
+const void* kernel_fn_f8(bool akc, bool bkc, int v) {
+    if (v == 0 && akc && bkc) return reinterpret_cast<const void*>(&skgemm_kernel<DT_F8, true, true, 0>);
     return nullptr;
 }
 
-int kernel_threads_f8() { return kThreadsOf<DT_F8>; }
+int kernel_threads_f8(int v) { return v == 0 ? kThreadsOf<DT_F8, 0> : 0; }
 
 }  // namespace skg

@@ -32,6 +32,7 @@ struct skgemm_plan_s {
     int32_t Ml, Nl, Kl;
     bool akc, bkc;   // K-contiguity of the launched A and B
     int dtype, out;
+    int variant;     // tile variant (0 default, 1 small 16-bit tile)
     // tiling and schedule
     int BM, BN, BK;
     int tm, tn, t, ipt;
@@ -75,23 +76,29 @@ int to_dt(skgemm_dtype_t t) {
     return -1;
 }
 
-TileCfg tile_for(int dt) {
-    switch (dt) {
-        case DT_F32: return kTileF32;
-        case DT_F8: return kTileF8;
-        default: return kTile16;
+// Tile of each (input type, variant); {0, 0, 0} where the variant does not exist.
+TileCfg tile_for(int dt, int v) {
+    if (v == 0) {
+        switch (dt) {
+            case DT_F32: return kTileF32;
+            case DT_F8: return kTileF8;
+            default: return kTile16;
+        }
     }
+    if (v == 1 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
+    return TileCfg{0, 0, 0};
 }
 
-// Grid-size model constants (a, b, c, d) per input type, in units of one
-// MAC-loop iteration (c = 1): a fixed per-workgroup cost, b the cost of
-// publishing a partial tile, d the cost of adding one peer's partial.
-void model_for(int dt, double* m) {
-    switch (dt) {
-        case DT_F32: m[0] = 3.0; m[1] = 1.0; m[2] = 1.0; m[3] = 1.0; break;
-        case DT_F8: m[0] = 8.0; m[1] = 3.0; m[2] = 1.0; m[3] = 3.0; break;
-        default: m[0] = 5.0; m[1] = 2.0; m[2] = 1.0; m[3] = 2.0; break;
-    }
+// Grid-size model constants (a, b, c, d) per input type and tile variant, in
+// microseconds measured on MI355X (paper_2212_08964_amd/calibrate.py): a the
+// fixed cost of a workgroup's tile, b the cost of publishing a partial tile,
+// c the cost of one MAC-loop iteration, d the cost of adding one peer's
+// partial.  The grid-size argmin only depends on their ratios; the absolute
+// values let the planner compare tile variants.
+void model_for(int dt, int v, double* m) {
+    if (dt == DT_F32) { m[0] = 3.0; m[1] = 0.7; m[2] = 1.0; m[3] = 0.7; return; }
+    if (v == 1) { m[0] = 2.0; m[1] = 0.7; m[2] = 0.45; m[3] = 0.7; return; }
+    m[0] = 4.0; m[1] = 2.5; m[2] = 1.6; m[3] = 2.5;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -189,13 +196,13 @@ int walk(const skgemm_plan_s& pl, int x, F&& emit) {
 
 struct DevInfo {
     int cus = 0;
-    int occ[4][2][2] = {};
-    bool have_occ[4][2][2] = {};
+    int occ[4][2][2][kVariants] = {};
+    bool have_occ[4][2][2][kVariants] = {};
 };
 std::mutex g_dev_mu;
 DevInfo g_dev[64];
 
-skgemm_status_t device_capacity(int dt, bool akc, bool bkc, int* cus, int* occ) {
+skgemm_status_t device_capacity(int dt, bool akc, bool bkc, int v, int* cus, int* occ) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SKGEMM_ERR_HIP;
     std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -206,14 +213,14 @@ skgemm_status_t device_capacity(int dt, bool akc, bool bkc, int* cus, int* occ) 
             return SKGEMM_ERR_HIP;
         d.cus = n;
     }
-    if (!d.have_occ[dt][akc][bkc]) {
-        const int o = kernel_occupancy(dt, akc, bkc);
+    if (!d.have_occ[dt][akc][bkc][v]) {
+        const int o = kernel_occupancy(dt, akc, bkc, v);
         if (o <= 0) return SKGEMM_ERR_HIP;
-        d.occ[dt][akc][bkc] = o;
-        d.have_occ[dt][akc][bkc] = true;
+        d.occ[dt][akc][bkc][v] = o;
+        d.have_occ[dt][akc][bkc][v] = true;
     }
     *cus = d.cus;
-    *occ = d.occ[dt][akc][bkc];
+    *occ = d.occ[dt][akc][bkc][v];
     return SKGEMM_OK;
 }
 
@@ -237,7 +244,7 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     int cus = o.num_cus, occ = o.occupancy;
     if (cus == 0 || occ == 0) {
         int qc = 0, qo = 0;
-        const skgemm_status_t st = device_capacity(pl->dtype, pl->akc, pl->bkc, &qc, &qo);
+        const skgemm_status_t st = device_capacity(pl->dtype, pl->akc, pl->bkc, pl->variant, &qc, &qo);
         if (st != SKGEMM_OK) return st;
         if (cus == 0) cus = qc;
         if (occ == 0) occ = qo;
@@ -330,13 +337,75 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     const bool a_kc = (la == SKGEMM_ROW_MAJOR), b_kc = (lb == SKGEMM_COL_MAJOR);
     pl->akc = pl->swapped ? b_kc : a_kc;
     pl->bkc = pl->swapped ? a_kc : b_kc;
-    if (!kernel_exists(pl->dtype, pl->akc, pl->bkc)) return SKGEMM_ERR_UNSUPPORTED;
-    const TileCfg tc_ = tile_for(pl->dtype);
-    if ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) || (o.tile_k && o.tile_k != tc_.bk))
-        return SKGEMM_ERR_UNSUPPORTED;
-    pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
-    model_for(pl->dtype, pl->model);
+    if (!kernel_exists(pl->dtype, pl->akc, pl->bkc, 0)) return SKGEMM_ERR_UNSUPPORTED;
     pl->hybrid_min_waves = o.hybrid_min_waves;
+    return SKGEMM_OK;
+}
+
+static void add_problem(skgemm_plan_s* pl, int64_t M, int64_t N, int64_t K);
+
+// Modelled runtime (microseconds) of a resolved plan, by the analytical model
+// of the Analytical Modeling subsection extended to the hybrids: a
+// workgroup's Stream-K share plus its data-parallel tiles, each tile paying
+// the fixed cost a; pure data-parallel plans run in ceil(t / p) waves.
+static double plan_estimate(const skgemm_plan_s* pl) {
+    if (pl->t == 0) return 0.0;
+    const int np = int(pl->pipt.size());
+    const double ipt = double(pl->iter_base[np]) / pl->t;
+    const double* m = pl->model;
+    if (pl->g_sk == 0) return double(cdiv(pl->t, pl->p)) * (m[0] + m[2] * ipt);
+    const int64_t ipc = cdiv(pl->sk_iters, pl->g_sk);
+    const int64_t peers = std::max<int64_t>(1, cdiv(int64_t(ipt + 0.5), ipc));
+    const int64_t dp_per_wg = cdiv(pl->t - pl->sk_tiles, pl->grid);
+    return m[0] * double(1 + dp_per_wg) + m[1] * (peers > 1 ? 1.0 : 0.0) + m[2] * (double(ipc) + dp_per_wg * ipt) +
+           m[3] * double(peers - 1);
+}
+
+// Builds the plan for every admissible tile variant (the one the options
+// name, else all that exist) and keeps the one with the smallest modelled
+// runtime (the default tile on ties).
+static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t& o, int G, const int64_t* M,
+                                     const int64_t* N, const int64_t* K, skgemm_plan_s** out) {
+    const bool named = o.tile_m || o.tile_n || o.tile_k;
+    skgemm_plan_s* best = nullptr;
+    double best_t = 0.0;
+    skgemm_status_t last = SKGEMM_ERR_UNSUPPORTED;
+    for (int v = 0; v < kVariants; ++v) {
+        const TileCfg tc_ = tile_for(base->dtype, v);
+        if (!tc_.bm || !kernel_exists(base->dtype, base->akc, base->bkc, v)) continue;
+        if (named && ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) ||
+                      (o.tile_k && o.tile_k != tc_.bk)))
+            continue;
+        skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s(*base);
+        if (!pl) return SKGEMM_ERR_HIP;
+        pl->variant = v;
+        pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
+        model_for(pl->dtype, v, pl->model);
+        for (int i = 0; i < G; ++i) add_problem(pl, M[i], N[i], K[i]);
+        skgemm_status_t st = SKGEMM_OK;
+        if (!pl->G) {
+            pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(pl->K);
+            pl->tm = pl->ptm[0]; pl->tn = pl->ptn[0]; pl->ipt = pl->pipt[0];
+            if (int64_t(pl->tm) * pl->tn > kMaxDim || int64_t(pl->tm) * pl->tn * pl->ipt > kMaxDim)
+                st = SKGEMM_ERR_UNSUPPORTED;
+        }
+        if (st == SKGEMM_OK) st = finish_plan(pl, o);
+        if (st != SKGEMM_OK) {
+            last = st;
+            delete pl;
+            continue;
+        }
+        const double t = plan_estimate(pl);
+        if (!best || t < best_t) {
+            delete best;
+            best = pl;
+            best_t = t;
+        } else {
+            delete pl;
+        }
+    }
+    if (!best) return last;
+    *out = best;
     return SKGEMM_OK;
 }
 
@@ -366,24 +435,14 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     skgemm_default_options(&o);
     if (opt) o = *opt;
     if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
-    skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s();
-    if (!pl) return SKGEMM_ERR_HIP;
-    skgemm_status_t st = init_common(pl, la, lb, lc, ta, tb, tc, o);
-    if (st == SKGEMM_OK) {
-        pl->M = M; pl->N = N; pl->K = K;
-        pl->G = 0;
-        add_problem(pl, M, N, K);
-        pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(K);
-        pl->tm = pl->ptm[0]; pl->tn = pl->ptn[0]; pl->ipt = pl->pipt[0];
-        if (int64_t(pl->tm) * pl->tn > kMaxDim || int64_t(pl->tm) * pl->tn * pl->ipt > kMaxDim)
-            st = SKGEMM_ERR_UNSUPPORTED;
-        else
-            st = finish_plan(pl, o);
-    }
-    if (st != SKGEMM_OK) {
-        delete pl;
-        return st;
-    }
+    skgemm_plan_s base{};
+    skgemm_status_t st = init_common(&base, la, lb, lc, ta, tb, tc, o);
+    if (st != SKGEMM_OK) return st;
+    base.M = M; base.N = N; base.K = K;
+    base.G = 0;
+    skgemm_plan_s* pl = nullptr;
+    st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
+    if (st != SKGEMM_OK) return st;
     *out = pl;
     return SKGEMM_OK;
 }
@@ -404,22 +463,16 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
     skgemm_default_options(&o);
     if (opt) o = *opt;
     if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
-    skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s();
-    if (!pl) return SKGEMM_ERR_HIP;
-    skgemm_status_t st = init_common(pl, la, lb, lc, ta, tb, tc, o);
-    if (st == SKGEMM_OK) {
-        pl->G = G;
-        for (int i = 0; i < G; ++i) add_problem(pl, M[i], N[i], K[i]);
-        pl->M = pl->N = pl->K = 0;
-        pl->Ml = pl->Nl = pl->Kl = 0;
-        pl->tm = pl->tn = 0;
-        pl->ipt = 0;
-        st = finish_plan(pl, o);
-    }
-    if (st != SKGEMM_OK) {
-        delete pl;
-        return st;
-    }
+    skgemm_plan_s base{};
+    skgemm_status_t st = init_common(&base, la, lb, lc, ta, tb, tc, o);
+    if (st != SKGEMM_OK) return st;
+    base.G = G;
+    base.M = base.N = base.K = 0;
+    base.Ml = base.Nl = base.Kl = 0;
+    base.tm = base.tn = base.ipt = 0;
+    skgemm_plan_s* pl = nullptr;
+    st = plan_variants(&base, o, G, M, N, K, &pl);
+    if (st != SKGEMM_OK) return st;
     *out = pl;
     return SKGEMM_OK;
 }
@@ -513,7 +566,7 @@ static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, co
     a.beta = beta;
     fill_schedule_args(pl, &a, workspace, trace);
     if (pl->grid == 0) return SKGEMM_OK;
-    const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, a, pl->grid, stream);
+    const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, pl->variant, a, pl->grid, stream);
     return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
 }
 
@@ -575,7 +628,7 @@ static skgemm_status_t grouped_impl(skgemm_plan_t pl, const void* table_dev, voi
     a.G = pl->G;
     fill_schedule_args(pl, &a, workspace, trace);
     if (pl->grid == 0) return SKGEMM_OK;
-    const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, a, pl->grid, stream);
+    const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, pl->variant, a, pl->grid, stream);
     return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
 }
 

@@ -18,6 +18,7 @@ constexpr int32_t kErrTimeout = 6;
 struct TileCfg { int bm, bn, bk; };
 constexpr TileCfg kTileF32 = {128, 128, 32};
 constexpr TileCfg kTile16 = {256, 256, 64};    // bf16 and f16
+constexpr TileCfg kTile16S = {128, 128, 64};   // bf16 and f16, small-tile variant
 constexpr TileCfg kTileF8 = {256, 256, 128};
 
 // One problem of a grouped launch (device table entry, 128 bytes).  Shapes are
@@ -62,14 +63,17 @@ struct KArgs {
     int32_t G;
 };
 
+// Tile variants: 0 = the type's default tile, 1 = the small 16-bit tile.
+constexpr int kVariants = 2;
+
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
-int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, const KArgs& args, int grid,
+int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, int variant, const KArgs& args, int grid,
                 void* stream);
 // Workgroups of the kernel that fit on one CU at once (0 on failure).
-int kernel_occupancy(int dtype, bool a_kcontig, bool b_kcontig);
-bool kernel_exists(int dtype, bool a_kcontig, bool b_kcontig);
-// Threads per workgroup of the dtype's kernel.
-int kernel_threads(int dtype);
+int kernel_occupancy(int dtype, bool a_kcontig, bool b_kcontig, int variant);
+bool kernel_exists(int dtype, bool a_kcontig, bool b_kcontig, int variant);
+// Threads per workgroup of the kernel.
+int kernel_threads(int dtype, int variant);
 
 // Per-tensor E4M3 quantisation (three launches on `stream`).
 int launch_quantize(int dtype, const void* x, int64_t rows, int64_t cols, int64_t ldx, bool x_col, uint8_t* q,

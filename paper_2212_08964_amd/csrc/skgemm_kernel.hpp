@@ -47,15 +47,24 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-// Tile per input type and the wave grid that covers it (WM x WN wavefronts).
-template <int DT> struct Cfg;
-template <> struct Cfg<DT_F32> { static constexpr int EB = 4, BM = kTileF32.bm, BN = kTileF32.bn, BK = kTileF32.bk, WM = 2, WN = 2; };
-template <> struct Cfg<DT_F16> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
-template <> struct Cfg<DT_BF16> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
-template <> struct Cfg<DT_F8> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4; };
+// Tile per input type and variant, and the wave grid that covers it (WM x WN
+// wavefronts).  Variant 1 is the small 16-bit tile (cheaper partial tiles
+// and epilogues for small, memory-bound problems; two workgroups per CU).
+template <int DT, int V> struct Cfg;
+template <> struct Cfg<DT_F32, 0> { static constexpr int EB = 4, BM = kTileF32.bm, BN = kTileF32.bn, BK = kTileF32.bk, WM = 2, WN = 2; };
+template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
+template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
+template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4; };
+template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2; };
+template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2; };
 
-template <int DT>
-constexpr int kThreadsOf = 64 * Cfg<DT>::WM * Cfg<DT>::WN;
+template <int DT, int V>
+constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
+
+// Waves per SIMD the register budget must allow: two workgroups per CU for
+// the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one).
+template <int DT, int V>
+constexpr int kWavesPerEU = 2;
 
 // Buffer descriptor word 3 for untyped buffer loads on gfx9-family targets.
 constexpr int kBufferFlags = 0x00020000;
@@ -91,7 +100,7 @@ struct Slab {
     static constexpr int BLOCKS = BYTES / 1024;
     static constexpr int PER_WAVE = BLOCKS / NW;
     static_assert(BK * EB == 128, "k slab must be 128 bytes");
-    static_assert(KC || ROWB == 512, "MN-contiguous slab rows must be 512 bytes");
+    static_assert(KC || ROWB == 512 || ROWB == 256, "MN-contiguous slab rows must be 256 or 512 bytes");
     static_assert(BLOCKS % NW == 0, "slab must split evenly over the waves");
 
     uint32_t voff[PER_WAVE];     // byte offset of the lane's chunk from the slab origin
@@ -192,11 +201,11 @@ __device__ __forceinline__ u32x4 lds_row_chunk(const unsigned char* lds, int row
     return *reinterpret_cast<const u32x4*>(lds + row * 128 + ((q ^ swz<2, true>(row)) << 4));
 }
 
-// Byte address of element (k, col) of an MN-contiguous slab.
-template <int EB>
+// Byte address of element (k, col) of an MN-contiguous slab with ROWB-byte rows.
+template <int EB, int ROWB>
 __device__ __forceinline__ int mn_addr(int k, int col) {
     constexpr int VE = 16 / EB;
-    return k * 512 + (((col / VE) ^ swz<EB, false>(k)) << 4) + (col % VE) * EB;
+    return k * ROWB + (((col / VE) ^ swz<EB, false>(k)) << 4) + (col % VE) * EB;
 }
 
 // Eight consecutive k (kb .. kb+7) of column (ob + lane % 32) of an MN-contiguous
@@ -204,13 +213,14 @@ __device__ __forceinline__ int mn_addr(int k, int col) {
 // of 16 lanes the transpose read returns, to lane i, element i mod 4 of the
 // 8-byte words fetched by lanes 4e + i / 4 (e = 0..3); so lane j of the group
 // fetches row kb + j / 4, columns 4 (j mod 4) .. +3 of its 16-column half.
+template <int ROWB>
 __device__ __forceinline__ u32x4 lds_tr16(const unsigned char* lds, int kb, int ob, int lane) {
     const int sub = lane & 15, h = lane >> 4;
     const int col = ob + 16 * (h & 1) + 4 * (sub & 3);
     const int k = kb + (sub >> 2);
     typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
-    lds_i16x4* p0 = (lds_i16x4*)(lds + mn_addr<2>(k, col));
-    lds_i16x4* p1 = (lds_i16x4*)(lds + mn_addr<2>(k + 4, col));
+    lds_i16x4* p0 = (lds_i16x4*)(lds + mn_addr<2, ROWB>(k, col));
+    lds_i16x4* p1 = (lds_i16x4*)(lds + mn_addr<2, ROWB>(k + 4, col));
     const i16x4 v0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(p0);
     const i16x4 v1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(p1);
     const u32x2 a = __builtin_bit_cast(u32x2, v0);
@@ -277,10 +287,11 @@ struct Prob {
     float alpha, beta;
 };
 
-template <int DT, bool AKC, bool BKC>
+template <int DT, bool AKC, bool BKC, int V>
 struct Gemm {
-    static constexpr int EB = Cfg<DT>::EB, BM = Cfg<DT>::BM, BN = Cfg<DT>::BN, BK = Cfg<DT>::BK;
-    static constexpr int WM = Cfg<DT>::WM, WN = Cfg<DT>::WN, THREADS = 64 * WM * WN, NW = WM * WN;
+    using C_ = Cfg<DT, V>;
+    static constexpr int EB = C_::EB, BM = C_::BM, BN = C_::BN, BK = C_::BK;
+    static constexpr int WM = C_::WM, WN = C_::WN, THREADS = 64 * WM * WN, NW = WM * WN;
     static constexpr int WTM = BM / WM, WTN = BN / WN;    // wave tile
     static constexpr int FM = WTM / 32, FN = WTN / 32;    // 32x32 MFMA blocks per wave
     using SA = Slab<EB, BM, BK, AKC, THREADS>;
@@ -304,12 +315,12 @@ struct Gemm {
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
                     if constexpr (AKC) af[buf][i] = lds_row_chunk(As, wm * WTM + i * 32 + l32, 2 * s + g);
-                    else af[buf][i] = lds_tr16(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
+                    else af[buf][i] = lds_tr16<SA::ROWB>(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
                 }
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
                     if constexpr (BKC) bf[buf][j] = lds_row_chunk(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
-                    else bf[buf][j] = lds_tr16(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
+                    else bf[buf][j] = lds_tr16<SB::ROWB>(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
                 }
             };
             constexpr int READS = FM * (AKC ? 1 : 2) + FN * (BKC ? 1 : 2);   // LDS reads per step
@@ -346,7 +357,7 @@ struct Gemm {
                     } else {
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            af[i][u] = *reinterpret_cast<const float*>(As + mn_addr<4>(8 * c + 4 * g + u, row));
+                            af[i][u] = *reinterpret_cast<const float*>(As + mn_addr<4, SA::ROWB>(8 * c + 4 * g + u, row));
                     }
                 }
 #pragma unroll
@@ -357,7 +368,7 @@ struct Gemm {
                     } else {
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            bf[j][u] = *reinterpret_cast<const float*>(Bs + mn_addr<4>(8 * c + 4 * g + u, col));
+                            bf[j][u] = *reinterpret_cast<const float*>(Bs + mn_addr<4, SB::ROWB>(8 * c + 4 * g + u, col));
                     }
                 }
 #pragma unroll
@@ -740,9 +751,10 @@ struct Gemm {
     }
 };
 
-template <int DT, bool AKC, bool BKC>
-__global__ void __launch_bounds__(kThreadsOf<DT>) skgemm_kernel(KArgs a) {
-    using G = Gemm<DT, AKC, BKC>;
+template <int DT, bool AKC, bool BKC, int V>
+__global__ void __launch_bounds__((kThreadsOf<DT, V>)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<DT, V>)))
+skgemm_kernel(KArgs a) {
+    using G = Gemm<DT, AKC, BKC, V>;
     __shared__ __attribute__((aligned(1024))) unsigned char stage0[G::STAGE];
     __shared__ __attribute__((aligned(1024))) unsigned char stage1[G::STAGE];
     G::run(a, stage0, stage1);

@@ -122,9 +122,11 @@ class Plan:
     """Owns one skgemm_plan_t."""
 
     def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
-                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0):
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None):
         self._h = ctypes.c_void_p()
         o = default_options()
+        if tile:
+            o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
@@ -161,6 +163,7 @@ class Plan:
         _check(lib().skgemm_plan_info(self._h, buf, 21), "skgemm_plan_info")
         d = dict(zip(INFO_FIELDS, list(buf)))
         d["policy_name"] = POLICY_NAME[d["policy"]]
+        d["tile"] = (d["BM"], d["BN"], d["BK"])
         return d
 
     def model_constants(self):
@@ -194,12 +197,14 @@ class GroupedPlan(Plan):
     """Owns one grouped skgemm_plan_t (several problems, one launch)."""
 
     def __init__(self, Ms, Ns, Ks, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
-                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0):
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None):
         self._h = ctypes.c_void_p()
         G = len(Ms)
         if not (len(Ns) == len(Ks) == G):
             raise ValueError("Ms, Ns, Ks must have the same length")
         o = default_options()
+        if tile:
+            o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
@@ -307,11 +312,12 @@ def workspace(nbytes: int, device):
     return buf
 
 
-def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2):
-    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves)
+def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2, tile=None):
+    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves, tuple(tile) if tile else None)
     p = _plan_cache.get(key)
     if p is None:
-        p = Plan(M, N, K, la, lb, lc, ta, tc, policy=policy, force_g=force_g, hybrid_min_waves=hybrid_min_waves)
+        p = Plan(M, N, K, la, lb, lc, ta, tc, policy=policy, force_g=force_g, hybrid_min_waves=hybrid_min_waves,
+                 tile=tile)
         if len(_plan_cache) > 4096:
             _plan_cache.clear()
         _plan_cache[key] = p
@@ -319,7 +325,7 @@ def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_w
 
 
 def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None, scale_b=None,
-           policy="auto", force_g=0, hybrid_min_waves=2, trace=None):
+           policy="auto", force_g=0, hybrid_min_waves=2, trace=None, tile=None):
     """C = alpha * s_A * s_B * A @ B + beta * C on torch tensors (2-D, on one GPU).
 
     Layouts come from the strides (a non-contiguous operand is copied).  When
@@ -354,7 +360,8 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     lc = _layout(out)
     if lc is None or out.shape != (M, N):
         raise ValueError("out must be an M x N tensor with one contiguous dimension")
-    plan = get_plan(M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy, force_g, hybrid_min_waves)
+    plan = get_plan(M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy, force_g, hybrid_min_waves,
+                    tile)
     nws = plan.workspace_size()
     ws = workspace(nws, A.device) if nws else None
     stream = torch.cuda.current_stream(A.device).cuda_stream
@@ -381,7 +388,7 @@ _gplan_cache = {}
 
 
 def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, policy="auto", force_g=0,
-                   hybrid_min_waves=2, trace=None, table=None):
+                   hybrid_min_waves=2, trace=None, table=None, tile=None):
     """C_i = alpha * A_i @ B_i + beta * C_i for every i, in ONE persistent launch.
 
     All A_i share a layout, all B_i share a layout, all C_i share a layout
@@ -408,11 +415,11 @@ def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, poli
     Ns = [B.shape[1] for B in Bs]
     Ks = [A.shape[1] for A in As]
     key = (tuple(Ms), tuple(Ns), tuple(Ks), la, lb, lc, dts[As[0].dtype], dts[Cs[0].dtype], policy, force_g,
-           hybrid_min_waves)
+           hybrid_min_waves, tuple(tile) if tile else None)
     plan = _gplan_cache.get(key)
     if plan is None:
         plan = GroupedPlan(Ms, Ns, Ks, la, lb, lc, dts[As[0].dtype], dts[Cs[0].dtype], policy=policy,
-                           force_g=force_g, hybrid_min_waves=hybrid_min_waves)
+                           force_g=force_g, hybrid_min_waves=hybrid_min_waves, tile=tile)
         if len(_gplan_cache) > 256:
             _gplan_cache.clear()
         _gplan_cache[key] = plan

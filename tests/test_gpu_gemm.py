@@ -22,6 +22,8 @@ TOL_16_OUT32 = 1e-5
 TOL_16 = 1e-2
 
 POLICIES = ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"]
+# the two 16-bit tile configurations (the planner picks one per problem; tests pin each)
+TILES16 = [(256, 256, 64), (128, 128, 64)]
 
 
 def sk():
@@ -98,12 +100,12 @@ def test_integer_f32_bit_exact_every_policy():
 
 # ------------------------------------------------------------------ schedule parity
 
-def _trace(A, B, policy, force_g=0, out_dtype=None):
+def _trace(A, B, policy, force_g=0, out_dtype=None, tile=None):
     p = sk().get_plan(A.shape[0], B.shape[1], A.shape[1], 0, 0, 0, sk()._torch_dtypes()[A.dtype],
-                      sk()._torch_dtypes()[out_dtype or A.dtype], policy, force_g, 2)
+                      sk()._torch_dtypes()[out_dtype or A.dtype], policy, force_g, 2, tile)
     cap = p.trace_capacity()
     tr = torch.full((max(cap, 1) * 8,), -7, dtype=torch.int32, device=dev())
-    mm(A, B, policy=policy, force_g=force_g, trace=tr, out_dtype=out_dtype)
+    mm(A, B, policy=policy, force_g=force_g, trace=tr, out_dtype=out_dtype, tile=tile)
     recs = tr.cpu().numpy().reshape(-1, 8)
     info = p.info()
     recs = [tuple(int(v) for v in r) for r in recs if r[0] != -7]
@@ -127,12 +129,15 @@ def test_trace_matches_enumerator_f32(shape, policy, g):
 
 
 @pytest.mark.parametrize("shape,policy", [((256 * 5 + 7, 256 * 3, 1000), "auto"), ((4096, 4096, 512), "auto"),
-                                          ((300, 3000, 2000), "sk"), ((256 * 17, 256 * 16, 256), "auto")])
-def test_trace_matches_enumerator_bf16(shape, policy):
+                                          ((300, 3000, 2000), "sk"), ((256 * 17, 256 * 16, 256), "auto"),
+                                          ((128 * 9 + 5, 128 * 7, 1000), "2tile_sk_dp")])
+@pytest.mark.parametrize("tile", TILES16)
+def test_trace_matches_enumerator_bf16(shape, policy, tile):
     M, N, K = shape
     A = torch.ones((M, K), dtype=torch.bfloat16, device=dev())
     B = torch.ones((K, N), dtype=torch.bfloat16, device=dev())
-    p, info, recs = _trace(A, B, policy, 0, out_dtype=torch.float32)
+    p, info, recs = _trace(A, B, policy, 0, out_dtype=torch.float32, tile=tile)
+    assert info["tile"] == tile
     got = records_to_schedule(recs, info["grid"])
     ref = oracle_plan_for(info, p.model_constants(), policy)
     assert got == S.enumerate_schedule(ref)
@@ -152,31 +157,41 @@ def test_16bit_parity(dtype, shape):
     A = torch.from_numpy(a).to(dtype).to(dev())
     B = torch.from_numpy(b).to(dtype).to(dev())
     ref = oracle(A, B)
-    for pol in ("auto", "dp", "sk"):
-        C32 = mm(A, B, policy=pol, out_dtype=torch.float32)
-        assert rel(C32, ref) <= TOL_16_OUT32, (pol, "f32 out")
-        C16 = mm(A, B, policy=pol)
-        assert C16.dtype == dtype
-        assert rel(C16, ref) <= TOL_16, (pol, "16-bit out")
+    for tile in [None] + TILES16:
+        for pol in ("auto", "dp", "sk"):
+            C32 = mm(A, B, policy=pol, out_dtype=torch.float32, tile=tile)
+            assert rel(C32, ref) <= TOL_16_OUT32, (tile, pol, "f32 out")
+            C16 = mm(A, B, policy=pol, tile=tile)
+            assert C16.dtype == dtype
+            assert rel(C16, ref) <= TOL_16, (tile, pol, "16-bit out")
 
 
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
-def test_16bit_integer_exact_all_policies(dtype):
+@pytest.mark.parametrize("tile", TILES16)
+def test_16bit_integer_exact_all_policies(dtype, tile):
     M, N, K = 700, 900, 1500
     g = W.rng(3)
     A = torch.from_numpy(W.integer_f32(g, (M, K))).to(dtype).to(dev())
     B = torch.from_numpy(W.integer_f32(g, (K, N))).to(dtype).to(dev())
     ref = oracle(A, B)
     for pol in POLICIES:
-        for fg in ([0] if pol != "sk" else [0, 5, 17, 200]):
-            C = mm(A, B, policy=pol, force_g=fg, out_dtype=torch.float32)
+        for fg in ([0] if pol != "sk" else [0, 5, 17, 200, 400]):
+            try:
+                C = mm(A, B, policy=pol, force_g=fg, out_dtype=torch.float32, tile=tile)
+            except sk().SkgemmError as e:
+                # a forced grid beyond the co-resident capacity of this tile is refused, never run
+                assert fg > 0 and e.status == sk().ERR_CAPACITY, (pol, fg, e)
+                continue
             assert np.array_equal(to_f64(C), ref), (pol, fg)
 
 
 @pytest.mark.parametrize("layouts", ["nn", "nt", "tn", "tt"])
 @pytest.mark.parametrize("c_col", [False, True])
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, "bf16_small"])
 def test_layouts(layouts, c_col, dtype):
+    tile = None
+    if dtype == "bf16_small":
+        dtype, tile = torch.bfloat16, (128, 128, 64)
     M, N, K = 333, 517, 290
     a, b = W.normal_pair(M, N, K, seed=11)
     A = torch.from_numpy(a).to(dtype).to(dev())
@@ -189,13 +204,16 @@ def test_layouts(layouts, c_col, dtype):
     odt = torch.float32
     out = torch.empty((N, M), dtype=odt, device=dev()).t() if c_col else torch.empty((M, N), dtype=odt, device=dev())
     for pol in ("auto", "sk", "dp"):
-        C = mm(A, B, out=out, policy=pol)
+        C = mm(A, B, out=out, policy=pol, tile=tile)
         tol = TOL_F32 if dtype == torch.float32 else TOL_16_OUT32
         assert rel(C, ref) <= tol, (layouts, c_col, pol)
 
 
-@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32, "bf16_small"])
 def test_alpha_beta_and_nan_c(dtype):
+    tile = None
+    if dtype == "bf16_small":
+        dtype, tile = torch.bfloat16, (128, 128, 64)
     M, N, K = 260, 300, 500
     a, b = W.normal_pair(M, N, K, seed=5)
     A = torch.from_numpy(a).to(dtype).to(dev())
@@ -204,11 +222,11 @@ def test_alpha_beta_and_nan_c(dtype):
     ref = oracle(A, B, alpha=0.5, beta=-2.0, C=c0)
     for pol in ("sk", "dp", "auto"):
         C = c0.clone()
-        mm(A, B, out=C, alpha=0.5, beta=-2.0, policy=pol)
+        mm(A, B, out=C, alpha=0.5, beta=-2.0, policy=pol, tile=tile)
         tol = TOL_F32 if dtype == torch.float32 else TOL_16
         assert rel(C, ref) <= tol, pol
         Cn = torch.full((M, N), float("nan"), dtype=dtype, device=dev())
-        mm(A, B, out=Cn, alpha=1.0, beta=0.0, policy=pol)
+        mm(A, B, out=Cn, alpha=1.0, beta=0.0, policy=pol, tile=tile)
         assert not torch.isnan(Cn).any(), pol
 
 
@@ -225,14 +243,15 @@ def test_k_zero_and_empty():
     assert mm(E, F).shape == (0, 5)
 
 
-def test_determinism_repeated_runs():
+@pytest.mark.parametrize("tile", TILES16)
+def test_determinism_repeated_runs(tile):
     M, N, K = 1000, 1000, 3000
     a, b = W.normal_pair(M, N, K, seed=9)
     A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
     B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
-    first = mm(A, B, policy="sk", out_dtype=torch.float32).clone()
+    first = mm(A, B, policy="sk", out_dtype=torch.float32, tile=tile).clone()
     for _ in range(20):
-        assert torch.equal(mm(A, B, policy="sk", out_dtype=torch.float32), first)
+        assert torch.equal(mm(A, B, policy="sk", out_dtype=torch.float32, tile=tile), first)
 
 
 def test_full_size_sampled_rows_bf16():

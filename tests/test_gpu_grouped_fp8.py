@@ -46,10 +46,11 @@ def _problems(seed, Ms, N, K, dtype=torch.bfloat16):
 
 
 @pytest.mark.parametrize("policy", ["auto", "sk", "dp", "2tile_sk_dp", "dp_1tile_sk"])
-def test_grouped_zipf_parity(policy):
+@pytest.mark.parametrize("tile", [None, (256, 256, 64), (128, 128, 64)])
+def test_grouped_zipf_parity(policy, tile):
     Ms = W.zipf_ms(24, lo=16, hi=1024, seed=1)
     As, Bs = _problems(2, Ms, 1024, 512)
-    Cs, _ = sk().grouped_matmul(As, Bs, out_dtype=torch.float32, policy=policy)
+    Cs, _ = sk().grouped_matmul(As, Bs, out_dtype=torch.float32, policy=policy, tile=tile)
     torch.cuda.synchronize()
     for A, B, C in zip(As, Bs, Cs):
         ref = og.gemm_f64(to_f64(A), to_f64(B))
@@ -71,29 +72,31 @@ def test_grouped_ragged_mixed_shapes_bf16_out():
             assert og.rel_frobenius(to_f64(C), ref) <= 1e-2
 
 
-def test_grouped_integer_exact_forced_grids():
+@pytest.mark.parametrize("tile", [(256, 256, 64), (128, 128, 64)])
+def test_grouped_integer_exact_forced_grids(tile):
     Ms = [37, 300, 16, 520]
     g = W.rng(4)
     As = [torch.from_numpy(W.integer_f32(g, (M, 777))).to(torch.bfloat16).to(dev()) for M in Ms]
     Bs = [torch.from_numpy(W.integer_f32(g, (777, 600))).to(torch.bfloat16).to(dev()) for _ in Ms]
     refs = [og.gemm_f64(to_f64(A), to_f64(B)) for A, B in zip(As, Bs)]
     for fg in (0, 3, 17, 64, 200):
-        Cs, _ = sk().grouped_matmul(As, Bs, out_dtype=torch.float32, policy="sk", force_g=fg)
+        Cs, _ = sk().grouped_matmul(As, Bs, out_dtype=torch.float32, policy="sk", force_g=fg, tile=tile)
         torch.cuda.synchronize()
         for C, ref in zip(Cs, refs):
             assert np.array_equal(to_f64(C), ref), fg
 
 
 @pytest.mark.parametrize("policy", ["auto", "sk", "2tile_sk_dp"])
-def test_grouped_trace_matches_enumerator(policy):
+@pytest.mark.parametrize("tile", [None, (128, 128, 64)])
+def test_grouped_trace_matches_enumerator(policy, tile):
     Ms = W.zipf_ms(64, seed=0)
     shapes = [(m, 4096, 2048) for m in Ms]
     A = [torch.ones((m, 2048), dtype=torch.bfloat16, device=dev()) for m in Ms]
     B = [torch.ones((2048, 4096), dtype=torch.bfloat16, device=dev()) for _ in Ms]
-    p = sk().GroupedPlan(Ms, [4096] * 64, [2048] * 64, ta=sk().BF16, tc=sk().F32, policy=policy)
+    p = sk().GroupedPlan(Ms, [4096] * 64, [2048] * 64, ta=sk().BF16, tc=sk().F32, policy=policy, tile=tile)
     info = p.info()
     tr = torch.full((p.trace_capacity() * 8,), -7, dtype=torch.int32, device=dev())
-    sk().grouped_matmul(A, B, out_dtype=torch.float32, policy=policy, trace=tr)
+    sk().grouped_matmul(A, B, out_dtype=torch.float32, policy=policy, trace=tr, tile=tile)
     torch.cuda.synchronize()
     recs = [tuple(int(v) for v in r) for r in tr.cpu().numpy().reshape(-1, 8) if r[0] != -7]
     got = records_to_schedule(recs, info["grid"])
