@@ -52,11 +52,14 @@ def parse():
     ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many Stream-K steps (for profiler runs) and print timings")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="with --profile-steps: then one plain device copy of this many MiB, the reference "
+                         "that scales the HBM byte counters")
     return ap.parse_args()
 
 
 class Case:
-    __slots__ = ("M", "N", "K", "A", "B", "C", "sk", "dp", "flops", "t", "p")
+    __slots__ = ("M", "N", "K", "A", "B", "C", "sk", "dp", "flops", "bytes", "t", "p")
 
 
 def build_cases(shapes, torch, sk):
@@ -77,6 +80,7 @@ def build_cases(shapes, torch, sk):
                        tile=info["tile"])
         c.t, c.p = info["t"], info["p"]
         c.flops = 2.0 * M * N * K
+        c.bytes = 2 * (M * K + K * N + M * N)       # read A and B once, write C once (bf16)
         cases.append(c)
     return cases
 
@@ -167,6 +171,16 @@ def main():
             run_pass(sk_launch)
             torch.cuda.synchronize()
             print(f"profile step {s}: {(time.perf_counter() - t1) * 1e3:.2f} ms", flush=True)
+        if args.copy_probe_mib:
+            nb = args.copy_probe_mib << 20
+            src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            print(f"copy probe: {nb} bytes read, {nb} bytes written", flush=True)
+        print(f"algorithmic bytes per step: {sum(c.bytes for c in cases)}; launches per step: {len(cases)}",
+              flush=True)
         return
 
     for _ in range(args.warmup):

@@ -72,6 +72,16 @@ typedef struct {
     int32_t hybrid_min_waves;     /* full waves needed for the two-tile hybrid (default 2) */
     int32_t num_cus;              /* >0: plan for this many CUs instead of querying */
     int32_t occupancy;            /* >0: workgroups per CU instead of querying */
+    int32_t raster_rows;          /* output tiles are numbered down groups of this many
+                                     tile rows, column by column (0 = default 8,
+                                     1 = row-major); does not change the schedule
+                                     over tile indices, only which block a tile is */
+    int32_t xcds;                 /* hardware workgroup b runs as logical workgroup
+                                     perm(b) so that each of this many XCDs (the GPU
+                                     hands workgroups to XCDs round-robin) gets a
+                                     contiguous range of logical workgroups
+                                     (0 = default 8, 1 = identity); the schedule over
+                                     logical workgroups is unchanged */
 } skgemm_options_t;
 
 /* Fills *opt with the defaults. */

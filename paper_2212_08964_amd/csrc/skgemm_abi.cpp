@@ -40,6 +40,7 @@ struct skgemm_plan_s {
     int sk_tiles, g_sk, grid;
     bool sk_first;
     int p, hybrid_min_waves;
+    int raster, xcds;  // tile raster group rows; XCD count for the workgroup permutation
     int sk_q, sk_r;
     double model[4];
     // workspace layout
@@ -225,6 +226,11 @@ skgemm_status_t device_capacity(int dt, bool akc, bool bkc, int v, int* cus, int
 }
 
 constexpr int64_t kMaxDim = (int64_t(1) << 31) - 1;
+// Tile raster groups of 8 tile rows: 8 x 4 (256-wide tiles, one workgroup per
+// CU) or 8 x 8 (128-wide, two per CU) neighbouring tiles per XCD at a time.
+constexpr int kDefaultRaster = 8, kMaxRaster = 1 << 16;
+// MI355X hands workgroups round-robin to its 8 XCDs.
+constexpr int kDefaultXcds = 8, kMaxXcds = 64;
 
 }  // namespace
 
@@ -328,6 +334,8 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     if (ta != SKGEMM_F8E4M3 && ta != SKGEMM_F32 && tc != ta && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if (ta == SKGEMM_F32 && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0) return SKGEMM_ERR_INVALID_ARG;
+    if (o.raster_rows < 0 || o.raster_rows > kMaxRaster || o.xcds < 0 || o.xcds > kMaxXcds)
+        return SKGEMM_ERR_INVALID_ARG;
     if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_2TILE_SK_DP) return SKGEMM_ERR_INVALID_ARG;
     pl->la = la; pl->lb = lb; pl->lc = lc;
     pl->ta = ta; pl->tc = tc;
@@ -339,6 +347,8 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     pl->bkc = pl->swapped ? a_kc : b_kc;
     if (!kernel_exists(pl->dtype, pl->akc, pl->bkc, 0)) return SKGEMM_ERR_UNSUPPORTED;
     pl->hybrid_min_waves = o.hybrid_min_waves;
+    pl->raster = o.raster_rows ? o.raster_rows : kDefaultRaster;
+    pl->xcds = o.xcds ? o.xcds : kDefaultXcds;
     return SKGEMM_OK;
 }
 
@@ -537,6 +547,8 @@ static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspac
     a->trace = trace;
     a->trace_per_wg = trace ? pl->max_segs : 0;
     a->spin_limit = 1 << 22;
+    a->raster = pl->raster;
+    a->xcds = pl->xcds;
 }
 
 static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,

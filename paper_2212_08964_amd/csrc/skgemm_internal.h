@@ -61,6 +61,8 @@ struct KArgs {
     int32_t spin_limit;
     const GroupEntry* group;   // grouped launch: G problem entries (else null)
     int32_t G;
+    int32_t raster;            // tile rows per raster group (1 = row-major)
+    int32_t xcds;              // XCDs the workgroups are spread over (1 = no remapping)
 };
 
 // Tile variants: 0 = the type's default tile, 1 = the small 16-bit tile.

@@ -71,6 +71,30 @@ constexpr int kBufferFlags = 0x00020000;
 
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Values that are the same in every lane but reach the compiler through
+// vector registers (a grouped launch reads its problem table with vector
+// loads) are moved to scalar registers, so that buffer descriptors built from
+// them stay scalar: a descriptor in vector registers forces a loop over the
+// distinct lane values around every buffer load.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(x))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(x) >> 32))));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* unip(T* p) { return reinterpret_cast<T*>(uni64(reinterpret_cast<int64_t>(p))); }
+__device__ __forceinline__ float unif(float x) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, x))); }
+
+// A copy of x the compiler cannot see through.  Per-lane addresses derived
+// from the thread index are re-derived from such a copy where they are used,
+// so they are not hoisted to the kernel's start and kept live (in registers
+// the MAC loop's accumulators need) across every loop in between.
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // ------------------------------------------------------------------ slab loads
 
 // Position swizzle of a row of a slab in LDS (see the layout note above).
@@ -87,10 +111,11 @@ __device__ __forceinline__ int swz(int row) {
 // its slot in the block.  Loads go through a buffer descriptor rebased at
 // every k-iteration, so a lane keeps only 32-bit offsets, and the hardware
 // returns zero for bytes past the end of the operand (rows beyond M or N of a
-// K-contiguous operand, k beyond K of an MN-contiguous one).  Chunks that
-// reach past the inner edge of a row (k beyond K, or columns beyond M or N)
-// are skipped by the wide load (offset forced out of range: zero, no memory
-// access) and, where partly inside, reloaded element by element.
+// K-contiguous operand, k beyond K of an MN-contiguous one).  In the checked
+// form (the slabs that need it, see mac_loop) chunks that reach past the
+// inner edge of a row (k beyond K, or columns beyond M or N) are skipped by
+// the wide load (offset forced out of range: zero, no memory access) and,
+// where partly inside, reloaded element by element.
 template <int EB, int R, int BK, bool KC, int THREADS>
 struct Slab {
     static constexpr int VE = 16 / EB;
@@ -104,7 +129,6 @@ struct Slab {
     static_assert(BLOCKS % NW == 0, "slab must split evenly over the waves");
 
     uint32_t voff[PER_WAVE];     // byte offset of the lane's chunk from the slab origin
-    int inner[PER_WAVE];         // its first inner-dimension element within the slab row
     const unsigned char* base;   // operand address of (outer o0, k of the first iteration)
     int64_t bytes;               // operand bytes from base to its end
     int64_t step;                // bytes between consecutive k-iterations
@@ -122,15 +146,20 @@ struct Slab {
             bytes = ((int64_t)(K - k0 - 1) * ld + (dout - o0)) * EB;
             step = (int64_t)BK * ld * EB;
         }
-        const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
-            const int pos = (w + j * NW) * 1024 + lane * 16;
-            const int row = pos / ROWB;
-            const int c = ((pos % ROWB) >> 4) ^ swz<EB, KC>(row);
-            voff[j] = uint32_t(row) * uint32_t(ld * EB) + uint32_t(c * 16);
-            inner[j] = c * VE;
+            const int row = chunk_row(j, tid);
+            voff[j] = uint32_t(row) * uint32_t(ld * EB) + uint32_t(chunk_col(j, tid) * 16);
         }
+    }
+
+    // Slab row and (unswizzled) 16-byte chunk index of the lane's chunk j.
+    static __device__ __forceinline__ int chunk_row(int j, int tid) {
+        return (((tid >> 6) + j * NW) * 1024 + (tid & 63) * 16) / ROWB;
+    }
+    static __device__ __forceinline__ int chunk_col(int j, int tid) {
+        const int pos = ((tid >> 6) + j * NW) * 1024 + (tid & 63) * 16;
+        return ((pos % ROWB) >> 4) ^ swz<EB, KC>(pos / ROWB);
     }
 
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int it) const {
@@ -142,21 +171,23 @@ struct Slab {
     }
 
     // Elements of the lane's chunk j inside the inner edge (VE when not at the edge).
-    __device__ __forceinline__ int keep(int j, bool tail, int lim) const {
-        return tail ? min(max(lim - inner[j], 0), VE) : VE;
+    __device__ __forceinline__ int keep(int j, bool tail, int lim, int tid) const {
+        return tail ? min(max(lim - chunk_col(j, tid) * VE, 0), VE) : VE;
     }
 
     // Issue the direct-to-LDS loads of iteration `it` (counted from kbeg), whose
-    // first k is k0, into the stage at `lds`.
+    // first k is k0, into the stage at `lds`.  EDGE = false: the caller knows
+    // the slab is wholly inside the inner edge (no per-chunk checks).
+    template <bool EDGE>
     __device__ __forceinline__ void issue(int it, int k0, int K, int o0, int dout, unsigned char* lds,
                                           int tid) const {
         const __amdgpu_buffer_rsrc_t rs = rsrc(it);
-        const bool tail = KC ? (k0 + BK > K) : (o0 + R > dout);
+        const bool tail = EDGE && (KC ? (k0 + BK > K) : (o0 + R > dout));
         const int lim = KC ? (K - k0) : (dout - o0);
-        const int w = tid >> 6;
+        const int w = uni(tid >> 6);
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
-            const uint32_t off = keep(j, tail, lim) == VE ? voff[j] : 0x80000000u;
+            const uint32_t off = (!EDGE || keep(j, tail, lim, tid) == VE) ? voff[j] : 0x80000000u;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + (w + j * NW) * 1024), 16, int(off), 0, 0, 0);
         }
     }
@@ -172,7 +203,7 @@ struct Slab {
         const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
-            const int kp = keep(j, tail, lim);
+            const int kp = keep(j, tail, lim, tid);
             if (kp > 0 && kp < VE) {
                 uint32_t v[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
@@ -285,7 +316,13 @@ struct Prob {
     int64_t lda, ldb, ldc;
     int M, N, K, tn, ipt;
     float alpha, beta;
+    int raster;          // tile rows per raster group (1 = plain row-major)
 };
+
+__device__ __forceinline__ Prob uniform(const Prob& p) {
+    return Prob{unip(p.A), unip(p.B), unip(p.C), uni64(p.lda), uni64(p.ldb), uni64(p.ldc), uni(p.M), uni(p.N),
+                uni(p.K), uni(p.tn), uni(p.ipt), unif(p.alpha), unif(p.beta), uni(p.raster)};
+}
 
 template <int DT, bool AKC, bool BKC, int V>
 struct Gemm {
@@ -323,26 +360,20 @@ struct Gemm {
                     else bf[buf][j] = lds_tr16<SB::ROWB>(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
                 }
             };
-            constexpr int READS = FM * (AKC ? 1 : 2) + FN * (BKC ? 1 : 2);   // LDS reads per step
             load(0, 0);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const int cur = s & 1;
+                // The reads of step s+1 are issued ahead of the MFMAs of step
+                // s, which then cover their latency; scheduling barriers keep
+                // the compiler from sinking them back next to their users.
                 if (s + 1 < KS) load(s + 1, cur ^ 1);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(af[cur][i], bf[cur][j], acc.v[i][j]);
-                if (s + 1 < KS) {
-                    constexpr int MF = FM * FN, PAIRS = READS < MF ? READS : MF;
-#pragma unroll
-                    for (int r = 0; r < PAIRS; ++r) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
-                    }
-                    if constexpr (MF > PAIRS) __builtin_amdgcn_sched_group_barrier(0x008, MF - PAIRS, 0);
-                    if constexpr (READS > PAIRS) __builtin_amdgcn_sched_group_barrier(0x100, READS - PAIRS, 0);
-                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         } else if constexpr (DT == DT_F32) {
             // Lane group g handles k = 8c + 4g + u of step (c, u).
@@ -411,30 +442,83 @@ struct Gemm {
         }
     }
 
+    // Output block of a tile index.  Tile indices run down a group of
+    // `raster` tile rows before moving to the next column, so consecutive
+    // tiles (the ones neighbouring workgroups work on at the same time) form
+    // a compact block that shares A and B slabs in the L2 cache.  A bijection
+    // of [0, tm*tn) for any raster >= 1; raster = 1 is row-major order.
+    static __device__ __forceinline__ void tile_origin(const Prob& a, int tile, int& m0, int& n0) {
+        const int tm = (a.M + BM - 1) / BM;
+        const int rows = min(a.raster, tm);     // rows * tn <= tiles: no overflow
+        const int span = rows * a.tn;
+        const int grp = tile / span;
+        const int first = grp * rows;
+        const int gm = min(tm - first, rows);
+        const int in = tile - grp * span;
+        m0 = (first + in % gm) * BM;
+        n0 = (in / gm) * BN;
+    }
+
     // One step of the MAC loop: start the loads of iteration kk+1 (if any) into
     // stage `nx`, run the MFMAs of stage `cu`, then wait for the loads and
     // synchronise.  Stages are distinct LDS objects, so the compiler can see
-    // that the loads in flight do not touch the stage being read.
-    static __device__ __forceinline__ bool step(const Prob& a, const SA& sa, const SB& sb, int kk, int klo,
+    // that the loads in flight do not touch the stage being read.  EDGE =
+    // false: every slab up to khi lies inside the operands' inner edges.
+    template <bool EDGE>
+    static __device__ __forceinline__ bool step(const Prob& a, const SA& sa, const SB& sb, int kk, int kbeg,
                                                 int khi, int m0, int n0, unsigned char* cu, unsigned char* nx,
                                                 Acc& acc, int tid) {
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const bool more = kk + 1 < khi;
         if (more) {
-            sa.issue(kk + 1 - klo, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
-            sb.issue(kk + 1 - klo, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+            sa.template issue<EDGE>(kk + 1 - kbeg, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
+            sb.template issue<EDGE>(kk + 1 - kbeg, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
         }
         compute(cu, cu + SA::BYTES, acc, wm, wn, lane);
         if (more) {
             wait_vmem();
-            sa.fix_edge(kk + 1 - klo, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
-            sb.fix_edge(kk + 1 - klo, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+            if constexpr (EDGE) {
+                sa.fix_edge(kk + 1 - kbeg, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
+                sb.fix_edge(kk + 1 - kbeg, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+            }
         }
         __syncthreads();
         return more;
     }
 
+    // Iterations [kbeg, kend) of a tile: a prologue load into stage 0, then the
+    // two-stage pipeline.
+    template <bool EDGE>
+    static __device__ __forceinline__ void loop(const Prob& a, unsigned char* s0, unsigned char* s1, int m0,
+                                                int n0, int kbeg, int kend, Acc& acc, int tid) {
+        tid = opaque(tid);
+        SA sa;
+        SB sb;
+        sa.init(a.A, a.lda, m0, a.M, kbeg, a.K, tid);
+        sb.init(a.B, a.ldb, n0, a.N, kbeg, a.K, tid);
+        __syncthreads();   // LDS may still be in use (previous epilogue or loop)
+        sa.template issue<EDGE>(0, kbeg * BK, a.K, m0, a.M, s0, tid);
+        sb.template issue<EDGE>(0, kbeg * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
+        wait_vmem();
+        if constexpr (EDGE) {
+            sa.fix_edge(0, kbeg * BK, a.K, m0, a.M, s0, tid);
+            sb.fix_edge(0, kbeg * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
+        }
+        __syncthreads();
+        for (int kk = kbeg;; kk += 2) {
+            if (!step<EDGE>(a, sa, sb, kk, kbeg, kend, m0, n0, s0, s1, acc, tid)) break;
+            if (!step<EDGE>(a, sa, sb, kk + 1, kbeg, kend, m0, n0, s1, s0, acc, tid)) break;
+        }
+    }
+
     // MAC-loop iterations [klo, khi) of one tile into acc (zeroed first).
+    // Only the tile's last k-iteration can need per-chunk checks: there a
+    // K-contiguous operand's chunks may straddle k = K (the elements past it
+    // belong to the next row and must read as zero), and an MN-contiguous
+    // operand's chunk in row K-1 may straddle the operand's end (the whole
+    // chunk would read as zero).  Every other slab is loaded with plain
+    // 16-byte chunks: chunks past the M or N edge of an MN-contiguous operand
+    // only feed rows or columns of the tile that are never written.
     static __device__ __forceinline__ void mac_loop(const Prob& a, unsigned char* s0, unsigned char* s1,
                                                     int tile, int klo, int khi, Acc& acc, int tid) {
 #pragma unroll
@@ -442,22 +526,16 @@ struct Gemm {
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc.v[i][j] = f32x16{0};
         if (klo >= khi) return;
-        const int m0 = (tile / a.tn) * BM, n0 = (tile % a.tn) * BN;
-        SA sa;
-        SB sb;
-        sa.init(a.A, a.lda, m0, a.M, klo, a.K, tid);
-        sb.init(a.B, a.ldb, n0, a.N, klo, a.K, tid);
-        __syncthreads();   // the previous segment's epilogue may still be using LDS
-        sa.issue(0, klo * BK, a.K, m0, a.M, s0, tid);
-        sb.issue(0, klo * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
-        wait_vmem();
-        sa.fix_edge(0, klo * BK, a.K, m0, a.M, s0, tid);
-        sb.fix_edge(0, klo * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
-        __syncthreads();
-        for (int kk = klo;; kk += 2) {
-            if (!step(a, sa, sb, kk, klo, khi, m0, n0, s0, s1, acc, tid)) break;
-            if (!step(a, sa, sb, kk + 1, klo, khi, m0, n0, s1, s0, acc, tid)) break;
-        }
+        int m0, n0;
+        tile_origin(a, tile, m0, n0);
+        const int klast = (a.K + BK - 1) / BK - 1;
+        const bool a_edge = !AKC && m0 + BM > a.M, b_edge = !BKC && n0 + BN > a.N;
+        const bool check_last = ((AKC || BKC) && a.K % BK != 0) || a_edge || b_edge;
+        // rows shorter than a chunk: chunks of earlier rows can reach the end too
+        const bool check_all = (a_edge && a.lda * EB < 16) || (b_edge && a.ldb * EB < 16);
+        const int kfast = check_all ? klo : (check_last && khi > klast) ? max(klo, klast) : khi;
+        if (kfast > klo) loop<false>(a, s0, s1, m0, n0, klo, kfast, acc, tid);
+        if (khi > kfast) loop<true>(a, s0, s1, m0, n0, kfast, khi, acc, tid);
     }
 
     // Partial tiles are stored in fragment order: float4 group q of thread tid
@@ -479,6 +557,7 @@ struct Gemm {
     }
 
     static __device__ __forceinline__ void store_partial(float* slot, const Acc& acc, int tid) {
+        tid = opaque(tid);
         const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot);
         int q = 0;
 #pragma unroll
@@ -495,6 +574,7 @@ struct Gemm {
     }
 
     static __device__ __forceinline__ void add_partial(const float* slot, Acc& acc, int tid) {
+        tid = opaque(tid);
         const __amdgpu_buffer_rsrc_t rs = slot_rsrc(const_cast<float*>(slot));
         int q = 0;
 #pragma unroll
@@ -527,9 +607,13 @@ struct Gemm {
     static __device__ __forceinline__ void epilogue_t(const Prob& a, const float* scale_a, const float* scale_b,
                                                       int tile, const Acc& acc, int tid, unsigned char* s0,
                                                       unsigned char* s1) {
+        tid = opaque(tid);
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const int g = lane >> 5, l32 = lane & 31;
-        const int m0 = (tile / a.tn) * BM + wm * WTM, n0 = (tile % a.tn) * BN + wn * WTN;
+        int m0, n0;
+        tile_origin(a, tile, m0, n0);
+        m0 += wm * WTM;
+        n0 += wn * WTN;
         float* st = reinterpret_cast<float*>((w < NW / 2 ? s0 : s1) + (w % (NW / 2)) * EPI_BYTES);
         float s = a.alpha;
         if (scale_a) s *= *scale_a;
@@ -635,8 +719,20 @@ struct Gemm {
         return lo;
     }
 
-    static __device__ __forceinline__ Prob entry_prob(const GroupEntry& e) {
-        return Prob{e.A, e.B, e.C, e.lda, e.ldb, e.ldc, e.M, e.N, e.K, e.tn, e.ipt, e.alpha, e.beta};
+    static __device__ __forceinline__ Prob entry_prob(const GroupEntry& e, int raster) {
+        return Prob{e.A, e.B, e.C, e.lda, e.ldb, e.ldc, e.M, e.N, e.K, e.tn, e.ipt, e.alpha, e.beta, raster};
+    }
+
+    // Logical workgroup index of hardware workgroup b.  Workgroups are handed
+    // to the XCDs round-robin (b mod xcds), and each XCD has its own L2; the
+    // permutation gives every XCD a contiguous range of logical indices, so
+    // the Stream-K shares and data-parallel tiles it runs are neighbours.
+    // A bijection of [0, grid); xcds = 1 is the identity.
+    static __device__ __forceinline__ int logical_wg(int b, int grid, int xcds) {
+        if (xcds <= 1) return b;
+        const int q = grid / xcds, r = grid % xcds;
+        const int x = b % xcds, pos = b / xcds;
+        return x < r ? x * (q + 1) + pos : r * (q + 1) + (x - r) * q + pos;
     }
 
     static __device__ __forceinline__ int share_start(int x, int q, int r) { return x * q + min(x, r); }
@@ -652,7 +748,7 @@ struct Gemm {
     // launch concatenates the problems' iteration spaces.
     static __device__ __forceinline__ void run(const KArgs& a, unsigned char* s0, unsigned char* s1) {
         const int tid = threadIdx.x;
-        const int wg = blockIdx.x;
+        const int wg = logical_wg(blockIdx.x, a.grid, a.xcds);
         int sk_it = 0, sk_end = 0;
         if (wg < a.g_sk) {
             sk_it = share_start(wg, a.sk_q, a.sk_r);
@@ -660,7 +756,8 @@ struct Gemm {
         }
         int dp_tile = a.sk_tiles + wg;
         int seq = 0;
-        const Prob single = {a.A, a.B, a.C, a.lda, a.ldb, a.ldc, a.M, a.N, a.K, a.tn, a.ipt, a.alpha, a.beta};
+        const Prob single = {a.A, a.B, a.C, a.lda, a.ldb, a.ldc, a.M, a.N, a.K, a.tn, a.ipt, a.alpha, a.beta,
+                             a.raster};
         Acc acc;
         for (;;) {
             const bool sk_left = sk_it < sk_end, dp_left = dp_tile < a.t;
@@ -672,7 +769,7 @@ struct Gemm {
                 int first;
                 if (a.G) {
                     const GroupEntry& e = a.group[find_iter(a, sk_it)];
-                    pr = entry_prob(e);
+                    pr = entry_prob(e, a.raster);
                     tile = int((sk_it - e.iter_base) / e.ipt);
                     first = int(e.iter_base) + tile * e.ipt;
                     gtile = e.tile_base + tile;
@@ -698,7 +795,7 @@ struct Gemm {
                 tile = dp_tile;
                 if (a.G) {
                     const GroupEntry& e = a.group[find_tile(a, dp_tile)];
-                    pr = entry_prob(e);
+                    pr = entry_prob(e, a.raster);
                     tile = dp_tile - e.tile_base;
                 }
                 lo = 0;
@@ -706,6 +803,10 @@ struct Gemm {
                 role = ROLE_FULL;
                 dp_tile += a.grid;
             }
+            pr = uniform(pr);
+            tile = uni(tile);
+            lo = uni(lo);
+            hi = uni(hi);
             if (a.trace && tid == 0 && seq < a.trace_per_wg) {
                 int32_t* rec = a.trace + ((size_t)wg * a.trace_per_wg + seq) * kTraceFields;
                 rec[0] = wg; rec[1] = seq; rec[2] = gtile; rec[3] = lo; rec[4] = hi; rec[5] = role;

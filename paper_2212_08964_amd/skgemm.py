@@ -40,7 +40,8 @@ INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt
 class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int), ("force_g", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
-                ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
+                ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("raster_rows", ctypes.c_int32),
+                ("xcds", ctypes.c_int32)]
 
 
 class GroupArgs(ctypes.Structure):
@@ -122,11 +123,13 @@ class Plan:
     """Owns one skgemm_plan_t."""
 
     def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
-                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None):
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
+                 raster_rows=0, xcds=0):
         self._h = ctypes.c_void_p()
         o = default_options()
         if tile:
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
+        o.raster_rows, o.xcds = int(raster_rows), int(xcds)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
@@ -197,7 +200,8 @@ class GroupedPlan(Plan):
     """Owns one grouped skgemm_plan_t (several problems, one launch)."""
 
     def __init__(self, Ms, Ns, Ks, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
-                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None):
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
+                 raster_rows=0, xcds=0):
         self._h = ctypes.c_void_p()
         G = len(Ms)
         if not (len(Ns) == len(Ks) == G):
@@ -205,6 +209,7 @@ class GroupedPlan(Plan):
         o = default_options()
         if tile:
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
+        o.raster_rows, o.xcds = int(raster_rows), int(xcds)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)

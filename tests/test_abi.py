@@ -195,3 +195,19 @@ def test_grouped_and_quantize_argument_errors():
                                   None) == sk.ERR_INVALID_ARG
     assert L.skgemm_quantize_e4m3(fake, sk.BF16, 4, 4, 0, 4, fake, 0, 4, fake, fake, n.value - 4,
                                   None) == sk.ERR_WORKSPACE
+
+
+def test_raster_and_xcd_options():
+    """Raster and XCD permutation options are validated and leave the schedule over tile indices unchanged."""
+    sk = _lib()
+    L = sk.lib()
+    h = ctypes.c_void_p()
+    for field, bad in (("raster_rows", -1), ("raster_rows", 1 << 17), ("xcds", -1), ("xcds", 65)):
+        o = sk.default_options()
+        o.num_cus, o.occupancy = 256, 1
+        setattr(o, field, bad)
+        assert L.skgemm_plan(ctypes.byref(h), 1000, 1000, 1000, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                             ctypes.byref(o)) == sk.ERR_INVALID_ARG, (field, bad)
+    scheds = [sk.Plan(3000, 2000, 1000, ta=sk.BF16, policy="sk", num_cus=256, occupancy=1, raster_rows=r,
+                      xcds=x).schedule() for r in (0, 1, 3, 8) for x in (0, 1, 8)]
+    assert all(s == scheds[0] for s in scheds)

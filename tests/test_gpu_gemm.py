@@ -146,7 +146,11 @@ def test_trace_matches_enumerator_bf16(shape, policy, tile):
 # ------------------------------------------------------------------ 16-bit inputs
 
 SHAPES16 = [(1, 1, 1), (3, 5, 7), (256, 256, 64), (257, 255, 65), (300, 500, 700), (513, 1031, 129),
-            (1000, 130, 5), (64, 3000, 2048), (640, 768, 4099)]
+            (1000, 130, 5), (64, 3000, 2048), (640, 768, 4099),
+            # rows shorter than a 16-byte chunk, and just longer, over many k-slabs
+            (300, 7, 1000), (70, 9, 1030), (7, 300, 1000),
+            # K a multiple of the k-slab (no K tail) with M and N edges
+            (129, 4100, 64), (200, 260, 640)]
 
 
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
