@@ -573,23 +573,37 @@ struct Gemm {
                 }
     }
 
+    // Loads go in groups of two accumulator blocks (32 registers in flight):
+    // issuing all of them before the adds would need a second accumulator's
+    // worth of registers and push the accumulators out to scratch memory.
     static __device__ __forceinline__ void add_partial(const float* slot, Acc& acc, int tid) {
         tid = opaque(tid);
         const __amdgpu_buffer_rsrc_t rs = slot_rsrc(const_cast<float*>(slot));
-        int q = 0;
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
+            for (int jg = 0; jg < FN; jg += 2) {
+                f32x4 v[2][4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r, ++q) {
-                    const f32x4 v = __builtin_bit_cast(
-                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent));
-                    acc.v[i][j][4 * r] += v.x;
-                    acc.v[i][j][4 * r + 1] += v.y;
-                    acc.v[i][j][4 * r + 2] += v.z;
-                    acc.v[i][j][4 * r + 3] += v.w;
-                }
+                for (int j = jg; j < jg + 2 && j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int q = (i * FN + j) * 4 + r;
+                        v[j - jg][r] = __builtin_bit_cast(
+                            f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent));
+                    }
+#pragma unroll
+                for (int j = jg; j < jg + 2 && j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        acc.v[i][j][4 * r] += v[j - jg][r].x;
+                        acc.v[i][j][4 * r + 1] += v[j - jg][r].y;
+                        acc.v[i][j][4 * r + 2] += v[j - jg][r].z;
+                        acc.v[i][j][4 * r + 3] += v[j - jg][r].w;
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
     }
 
     // C = alpha * s_A * s_B * acc + beta * C over the tile.  Each wave stages
@@ -735,6 +749,21 @@ struct Gemm {
         return x < r ? x * (q + 1) + pos : r * (q + 1) + (x - r) * q + pos;
     }
 
+    // Relaxed agent-scope polling of a ready flag: coherent loads with no
+    // cache invalidation per poll.  All lanes load the same word, so the
+    // value is wave-uniform and the loop runs as scalar branches.  Bounded:
+    // past spin_limit polls the error word is set and the wait ends.
+    static __device__ __forceinline__ void wait_flag(int32_t* flag, int spin_limit, int32_t* err) {
+        int spins = 0;
+        while (uni(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > spin_limit) {
+                __hip_atomic_store(err, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+
     static __device__ __forceinline__ int share_start(int x, int q, int r) { return x * q + min(x, r); }
 
     static __device__ __forceinline__ int owner_of(int i, int q, int r) {
@@ -826,25 +855,18 @@ struct Gemm {
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 if (role == ROLE_OWNER) {
+                    // Every wave waits for each peer's flag itself (a wave-
+                    // uniform loop: no divergent region around the
+                    // accumulators), then adds that peer's partial.
                     for (int peer = wg + 1; peer <= peer_end; ++peer) {
-                        int32_t* flag = a.flags + (size_t)peer * kFlagStrideInts;
-                        if (tid == 0) {
-                            // Relaxed agent-scope polling: coherent loads of the
-                            // flag, with no cache invalidation per poll.
-                            int spins = 0;
-                            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                                __builtin_amdgcn_s_sleep(2);
-                                if (++spins > a.spin_limit) {
-                                    __hip_atomic_store(a.err, kErrTimeout, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                                    break;
-                                }
-                            }
-                        }
-                        __syncthreads();
+                        wait_flag(a.flags + (size_t)peer * kFlagStrideInts, a.spin_limit, a.err);
                         add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);   // coherent loads
-                        if (tid == 0) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
+                    __syncthreads();   // every wave has seen every flag: clear them for the next launch
+                    if (tid == 0)
+                        for (int peer = wg + 1; peer <= peer_end; ++peer)
+                            __hip_atomic_store(a.flags + (size_t)peer * kFlagStrideInts, 0, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                 }
                 epilogue(a, pr, tile, acc, tid, s0, s1);
             }
