@@ -56,8 +56,13 @@ typedef enum {
 /* Work decomposition (Work Decomposition Strategies section and
  * Data-parallel Hybridization subsection). */
 typedef enum {
-    SKGEMM_POLICY_AUTO = 0,       /* DP when tiles fill whole waves, basic SK with the
-                                     model's grid when tiles < workgroups, else a hybrid */
+    SKGEMM_POLICY_AUTO = 0,       /* DP when tiles fill whole waves; otherwise the
+                                     remainder tiles (all tiles when there are fewer
+                                     than workgroups) are split into s equal parts
+                                     each, s from the grid-size model over
+                                     1 .. p / tiles: s = 1 is DP, else basic SK
+                                     (no full wave) or DP + one-tile SK with
+                                     g = s * tiles */
     SKGEMM_POLICY_DP = 1,         /* one workgroup per output tile */
     SKGEMM_POLICY_SK = 2,         /* basic Stream-K over all tiles */
     SKGEMM_POLICY_DP_1TILE_SK = 3,/* full DP waves, Stream-K over the remainder tiles */
@@ -82,7 +87,17 @@ typedef struct {
                                      contiguous range of logical workgroups
                                      (0 = default 8, 1 = identity); the schedule over
                                      logical workgroups is unchanged */
+    int32_t share;                /* even share of the Stream-K iterations (each
+                                     workgroup gets floor(T/g) or ceil(T/g)):
+                                     SKGEMM_SHARE_PROPORTIONAL (default) starts
+                                     workgroup x at floor(x*T/g), so when g is a
+                                     multiple s of the Stream-K tile count every tile
+                                     is cut into s parts at the same k-offsets;
+                                     SKGEMM_SHARE_LEADING gives the T mod g extra
+                                     iterations to the first workgroups */
 } skgemm_options_t;
+
+typedef enum { SKGEMM_SHARE_PROPORTIONAL = 0, SKGEMM_SHARE_LEADING = 1 } skgemm_share_t;
 
 /* Fills *opt with the defaults. */
 void skgemm_default_options(skgemm_options_t* opt);
@@ -143,8 +158,8 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
  *   15 sk_first (0/1), 16 p (co-resident workgroups), 17 hybrid_min_waves,
  *   18 A K-contiguous (0/1), 19 B K-contiguous (0/1), 20 G (problems of a
  *   grouped plan, 0 for one GEMM; fields 0-2, 7, 8 and 10 are 0 then and
- *   field 9 is the total tile count).
- * n is the capacity of info; up to 21 values are written. */
+ *   field 9 is the total tile count), 21 share (skgemm_share_t).
+ * n is the capacity of info; up to 22 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)

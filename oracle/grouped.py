@@ -20,7 +20,8 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
-from .schedule import FULL, OWNER, PARTIAL, Segment, cdiv, model_best_g, owner_of, share_start
+from .schedule import (FULL, OWNER, PARTIAL, Segment, cdiv, model_best_g, model_best_split, owner_of,
+                       share_start)
 
 
 @dataclass
@@ -40,11 +41,12 @@ class GroupedPlan:
     g_sk: int = 0
     grid: int = 0
     sk_first: bool = True
+    share: str = "proportional"
 
 
 def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_min_waves=2,
-                      model=(0.0, 0.0, 1.0, 0.0)) -> GroupedPlan:
-    pl = GroupedPlan(list(problems), BM, BN, BK, p)
+                      model=(0.0, 0.0, 1.0, 0.0), share="proportional") -> GroupedPlan:
+    pl = GroupedPlan(list(problems), BM, BN, BK, p, share=share)
     it = 0
     for pi, (M, N, K) in enumerate(problems):
         tm, tn, ipt = cdiv(M, BM), cdiv(N, BN), cdiv(K, BK)
@@ -59,9 +61,21 @@ def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_
     if it == 0:
         policy = "dp"
     w, r = divmod(t, p)
+    ipts = {ipt for (_, _, ipt) in pl.tiles}
+    auto_g = 0
     if policy == "auto":
         if r == 0:
             policy = "dp"
+        elif len(ipts) == 1:
+            # every tile has the same iterations: the tile-aligned split of the
+            # single-GEMM automatic policy applies to the concatenated tiles
+            count = t if w == 0 else r
+            s = model_best_split(count, next(iter(ipts)), p, model)
+            if s == 1:
+                policy = "dp"
+            else:
+                policy = "sk" if w == 0 else "dp_1tile_sk"
+                auto_g = s * count
         elif w == 0:
             policy = "sk"
         elif w >= hybrid_min_waves:
@@ -82,14 +96,18 @@ def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_
     if policy == "sk":
         if force_g:
             pl.g_sk = force_g
+        elif auto_g:
+            pl.g_sk = auto_g
         elif t >= p:
             pl.g_sk = p
         else:
             pl.g_sk = model_best_g(t, cdiv(pl.total_iters, t), p, model)
+        pl.g_sk = min(pl.g_sk, pl.sk_iters)     # at most one workgroup per iteration
         pl.grid = pl.g_sk
     else:
         if pl.sk_tiles:
-            pl.g_sk = force_g if force_g else min(p, pl.sk_iters)
+            pl.g_sk = force_g if force_g else auto_g if auto_g else min(p, pl.sk_iters)
+            pl.g_sk = min(pl.g_sk, pl.sk_iters)
         pl.grid = max(p if t - pl.sk_tiles > 0 else pl.g_sk, pl.g_sk)
     return pl
 
@@ -107,7 +125,7 @@ def enumerate_grouped_schedule(pl: GroupedPlan) -> List[List[Segment]]:
     for x in range(pl.grid):
         sk = []
         if x < pl.g_sk:
-            it, end = share_start(x, pl.sk_iters, pl.g_sk), share_start(x + 1, pl.sk_iters, pl.g_sk)
+            it, end = share_start(x, pl.sk_iters, pl.g_sk, pl.share), share_start(x + 1, pl.sk_iters, pl.g_sk, pl.share)
             while it < end:
                 gt = _tile_of_iter(pl, it)
                 first, last = pl.first_iter[gt], pl.first_iter[gt] + pl.tiles[gt][2]
@@ -115,7 +133,7 @@ def enumerate_grouped_schedule(pl: GroupedPlan) -> List[List[Segment]]:
                 if it != first:
                     sk.append(Segment(gt, lo, hi, PARTIAL))
                 elif end < last:
-                    peers = tuple(range(x + 1, owner_of(last - 1, pl.sk_iters, pl.g_sk) + 1))
+                    peers = tuple(range(x + 1, owner_of(last - 1, pl.sk_iters, pl.g_sk, pl.share) + 1))
                     sk.append(Segment(gt, lo, hi, OWNER, peers))
                 else:
                     sk.append(Segment(gt, lo, hi, FULL))

@@ -17,10 +17,15 @@ reason in the design notes):
   column block = idx % tn), with k innermost.  The printed MacLoop divides by
   ceil(m / BLK_M) for both coordinates, which is only consistent for square
   tile grids; the prose's m -> n -> k linearisation is followed instead.
-* Even share "within one": with q, r = divmod(total, g), workgroup x owns
-  iterations [x*q + min(x, r), (x+1)*q + min(x+1, r)).  The printed
-  ceil(total / g) split overruns on the last CTA; the within-one split is
-  the one that reproduces the 132/133 iterations per CTA of the model figure.
+* Even share "within one": every workgroup gets floor(total / g) or
+  ceil(total / g) contiguous iterations.  The printed ceil(total / g) split
+  overruns on the last CTA; a within-one split is the one that reproduces the
+  132/133 iterations per CTA of the model figure.  Which workgroups get the
+  extra iteration the paper does not say; two rules are provided:
+  proportional (workgroup x starts at floor(x * total / g), the default) and
+  leading (q, r = divmod(total, g); workgroup x starts at x*q + min(x, r)).
+  Under the proportional rule a grid g = s * t cuts every tile into s parts
+  at the same k-offsets.
 * The accumulating workgroup of a tile (the one that ran its k = 0 iteration)
   receives partials from workgroups x+1 .. owner_of(last iteration of the
   tile), in ascending order; the printed "cta_end" expression is a tile index
@@ -29,11 +34,15 @@ reason in the design notes):
   data-parallel tiles follow and workgroup x takes sk_tiles + x + i * grid.
   "Two-tile SK + DP" runs its Stream-K share first, "DP + one-tile SK" its
   data-parallel tiles first.
-* The automatic policy: no remainder tiles (t mod p == 0) -> data-parallel;
-  fewer tiles than workgroups (t < p) -> basic Stream-K with g from the model
-  over [t, p]; at least ``hybrid_min_waves`` (2) full waves -> two-tile SK + DP
-  with sk_tiles = (t mod p) + p and g = p; otherwise DP + one-tile SK with
-  sk_tiles = t mod p and g = min(p, sk_tiles * ipt).
+* The automatic policy (a choice for the target GPU, not the paper's): no
+  remainder tiles (t mod p == 0) -> data-parallel; otherwise the remainder
+  tiles (all t when t < p) are split s ways with g = s * (their count), s
+  from the grid-size model over 1 .. min(p / count, ipt): s = 1 is
+  data-parallel, else basic Stream-K (t < p) or DP + one-tile SK.  The
+  paper's own selection (basic Stream-K with g from the model over [t, p];
+  two-tile SK + DP from ``hybrid_min_waves`` full waves on; DP + one-tile SK
+  with g = min(p, sk_tiles * ipt)) is what the explicit policies give, and
+  what a grouped launch whose problems differ in iterations per tile uses.
 * K = 0 gives zero iterations per tile; every policy then degenerates to
   data-parallel tiles that only apply the epilogue (C = beta * C).
 * Model ties are broken toward the smallest g (fewer partial tiles).
@@ -82,6 +91,7 @@ class Plan:
     grid: int = 0             # workgroups launched
     sk_first: bool = True     # per-workgroup order: Stream-K share before DP tiles
     model: Tuple[float, float, float, float] = (0.0, 0.0, 1.0, 0.0)
+    share: str = "proportional"   # even-share rule: "proportional" or "leading"
 
     @property
     def total_iters(self) -> int:
@@ -112,18 +122,25 @@ def tile_origin(tile: int, tn: int, BM: int, BN: int) -> Tuple[int, int]:
     return BM * (tile // tn), BN * (tile % tn)
 
 
-def share_start(x: int, total: int, g: int) -> int:
+def share_start(x: int, total: int, g: int, share: str = "proportional") -> int:
     """First iteration of workgroup x under the within-one even share."""
+    if share == "proportional":
+        return x * total // g
     q, r = divmod(total, g)
     return x * q + min(x, r)
 
 
-def owner_of(i: int, total: int, g: int) -> int:
-    """Workgroup whose within-one share contains iteration i."""
-    q, r = divmod(total, g)
-    if i < r * (q + 1):
-        return i // (q + 1)
-    return r + (i - r * (q + 1)) // q
+def owner_of(i: int, total: int, g: int, share: str = "proportional") -> int:
+    """Workgroup whose within-one share contains iteration i (found by
+    walking the share boundaries, not by inverting their formula)."""
+    lo, hi = 0, g - 1
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if share_start(mid, total, g, share) <= i:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
 
 
 # ---------------------------------------------------------------- analytical model
@@ -144,6 +161,18 @@ def model_time(g: int, t: int, ipt: int, a: float, b: float, c: float, d: float)
     return a + b * (1 if peers > 1 else 0) + c * model_iters_per_cta(g, t, ipt) + d * (peers - 1)
 
 
+def model_best_split(t: int, ipt: int, p: int, consts) -> int:
+    """Split factor s in [1, min(p // t, ipt)] whose grid g = s * t has the
+    smallest modelled time (smallest s on ties)."""
+    a, b, c, d = consts
+    best_s, best = 1, None
+    for s in range(1, max(1, min(p // max(t, 1), ipt)) + 1):
+        v = model_time(s * t, t, ipt, a, b, c, d)
+        if best is None or v < best:
+            best, best_s = v, s
+    return best_s
+
+
 def model_best_g(t: int, ipt: int, p: int, consts) -> int:
     """Grid size in [t, p] with the smallest modelled time (smallest g on ties)."""
     a, b, c, d = consts
@@ -160,27 +189,30 @@ def model_best_g(t: int, ipt: int, p: int, consts) -> int:
 
 def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
               policy: str = "auto", force_g: int = 0, hybrid_min_waves: int = 2,
-              model=(0.0, 0.0, 1.0, 0.0)) -> Plan:
+              model=(0.0, 0.0, 1.0, 0.0), share: str = "proportional") -> Plan:
     """Resolve a policy into the Stream-K region and the launch grid."""
     if policy not in POLICIES:
         raise ValueError(policy)
     tm, tn, t, ipt, T = iteration_space(M, N, K, BM, BN, BK)
-    pl = Plan(M, N, K, BM, BN, BK, p, tm, tn, t, ipt, model=tuple(model))
+    pl = Plan(M, N, K, BM, BN, BK, p, tm, tn, t, ipt, model=tuple(model), share=share)
     if t == 0:
         pl.policy, pl.grid = "dp", 0
         return pl
     if ipt == 0:
         policy = "dp"
     w, r = divmod(t, p)
+    auto_g = 0
     if policy == "auto":
         if r == 0:
             policy = "dp"
-        elif w == 0:
-            policy = "sk"
-        elif w >= hybrid_min_waves:
-            policy = "2tile_sk_dp"
         else:
-            policy = "dp_1tile_sk"
+            count = t if w == 0 else r
+            s = model_best_split(count, ipt, p, model)
+            if s == 1:
+                policy = "dp"
+            else:
+                policy = "sk" if w == 0 else "dp_1tile_sk"
+                auto_g = s * count
     pl.policy = policy
     if policy == "dp":
         pl.sk_tiles, pl.g_sk, pl.grid = 0, 0, t
@@ -189,10 +221,13 @@ def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
         pl.sk_tiles = t
         if force_g:
             pl.g_sk = force_g
+        elif auto_g:
+            pl.g_sk = auto_g
         elif t >= p:
             pl.g_sk = p
         else:
             pl.g_sk = model_best_g(t, ipt, p, model)
+        pl.g_sk = min(pl.g_sk, pl.sk_iters)     # at most one workgroup per iteration
         pl.grid = pl.g_sk
         return pl
     if policy == "dp_1tile_sk":
@@ -202,7 +237,8 @@ def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
         pl.sk_tiles = t if w == 0 else r + p
         pl.sk_first = True
     if pl.sk_tiles:
-        pl.g_sk = force_g if force_g else min(p, pl.sk_tiles * ipt)
+        pl.g_sk = force_g if force_g else auto_g if auto_g else min(p, pl.sk_tiles * ipt)
+        pl.g_sk = min(pl.g_sk, pl.sk_iters)
     pl.grid = p if pl.dp_tiles > 0 else pl.g_sk
     pl.grid = max(pl.grid, pl.g_sk)
     return pl
@@ -216,7 +252,7 @@ def streamk_share(x: int, pl: Plan) -> List[Segment]:
     if x >= pl.g_sk or pl.sk_tiles == 0:
         return []
     total, g, ipt = pl.sk_iters, pl.g_sk, pl.ipt
-    it, it_end = share_start(x, total, g), share_start(x + 1, total, g)
+    it, it_end = share_start(x, total, g, pl.share), share_start(x + 1, total, g, pl.share)
     segs = []
     while it < it_end:
         tile = it // ipt
@@ -225,7 +261,7 @@ def streamk_share(x: int, pl: Plan) -> List[Segment]:
         if it != first:
             segs.append(Segment(tile, lo, hi, PARTIAL))
         elif it_end < last:
-            end_wg = owner_of(last - 1, total, g)
+            end_wg = owner_of(last - 1, total, g, pl.share)
             segs.append(Segment(tile, lo, hi, OWNER, tuple(range(x + 1, end_wg + 1))))
         else:
             segs.append(Segment(tile, lo, hi, FULL))

@@ -7,6 +7,7 @@ then linked into paper_2212_08964_amd/libskgemm.so.
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -44,10 +45,33 @@ def _compile(src: str) -> str:
     cmd = [hipcc(), *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
+    elif src.startswith("kernels_"):
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{res.stderr}")
+    if src.startswith("kernels_"):
+        check_no_scratch(src, res.stderr)
     return obj
+
+
+def check_no_scratch(src: str, remarks: str) -> None:
+    """Fail the build if a GEMM kernel spills to scratch memory.
+
+    On MI355X a kernel that uses scratch pays a fixed cost of about 20 us per
+    launch (measured with two otherwise identical trivial kernels), more than
+    the whole runtime of a small GEMM, so a spill is a build error here."""
+    name = None
+    bad = []
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            bad.append(f"{name}: {m.group(1)} bytes/lane")
+    if bad:
+        raise RuntimeError(f"{src}: kernels use scratch memory:\n  " + "\n  ".join(bad))
 
 
 def build(verbose: bool = True) -> str:

@@ -4,8 +4,9 @@ The Analytical Modeling subsection models the runtime of one tile-producing
 workgroup as a + b*[peers > 1] + c*iters_per_cta + d*(peers - 1), with the
 constants found by microbenchmarks once per blocking factor, data type and
 GPU.  This script runs basic Stream-K with forced grid sizes over synthetic
-problems (tile counts t, iterations per tile ipt, grid sizes g in [t, p]),
-times each with HIP events, and fits (a, b, c, d) by least squares.  It
+problems (tile counts t, iterations per tile ipt, grid sizes g = s*t that
+split each tile into s equal parts), times back-to-back launches with HIP
+events, and fits (a, b, c, d) by least squares.  It
 prints the constants normalised to c = 1, in the form the library's model
 table uses.
 
@@ -62,8 +63,10 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
             A = torch.randn(M, K, device="cuda").to(tdt)
             B = torch.randn(K, N, device="cuda").to(tdt)
             C = torch.empty(M, N, device="cuda", dtype=tdt)
-            gs = sorted({g for g in (t, 2 * t, 3 * t, 4 * t, 6 * t, 8 * t, 12 * t, 16 * t, (t + p) // 2, p)
-                         if t <= g <= min(p, t * ipt)})
+            # grids that split every tile into s equal parts (s divides ipt): the
+            # shares then start at the same k-offset in every tile, the form the
+            # planner's automatic policy launches
+            gs = [t * s for s in range(1, ipt + 1) if ipt % s == 0 and t * s <= p]
             for g in gs:
                 plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="sk", force_g=g, tile=(BM, BN, BK))
                 nws = plan.workspace_size()

@@ -41,6 +41,7 @@ struct skgemm_plan_s {
     bool sk_first;
     int p, hybrid_min_waves;
     int raster, xcds;  // tile raster group rows; XCD count for the workgroup permutation
+    bool share_prop;   // proportional (else leading) even share
     int sk_q, sk_r;
     double model[4];
     // workspace layout
@@ -97,9 +98,11 @@ TileCfg tile_for(int dt, int v) {
 // partial.  The grid-size argmin only depends on their ratios; the absolute
 // values let the planner compare tile variants.
 void model_for(int dt, int v, double* m) {
-    if (dt == DT_F32) { m[0] = 3.0; m[1] = 0.7; m[2] = 1.0; m[3] = 0.7; return; }
-    if (v == 1) { m[0] = 2.0; m[1] = 0.7; m[2] = 0.45; m[3] = 0.7; return; }
-    m[0] = 4.0; m[1] = 2.5; m[2] = 1.6; m[3] = 2.5;
+    // least-squares fits over tile-aligned grids (FP8 shares the 16-bit
+    // 256x256 constants: its kernel has the same tile and wave layout)
+    if (dt == DT_F32) { m[0] = 4.6; m[1] = 5.4; m[2] = 2.09; m[3] = 1.46; return; }
+    if (v == 1) { m[0] = 6.4; m[1] = 2.8; m[2] = 0.59; m[3] = 1.49; return; }
+    m[0] = 7.0; m[1] = 9.0; m[2] = 1.33; m[3] = 2.69;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -123,9 +126,37 @@ int model_best_g(int64_t t, int64_t ipt, int64_t p, const double* m) {
     return int(best_g);
 }
 
-int share_start(int x, int q, int r) { return x * q + std::min(x, r); }
+// Split factor s in [1, min(p / t, ipt)] that minimises the modelled time of
+// basic Stream-K over t tiles with g = s * t (the smallest s on ties).
+int model_best_split(int64_t t, int64_t ipt, int64_t p, const double* m) {
+    const int64_t smax = std::max<int64_t>(1, std::min(p / std::max<int64_t>(t, 1), ipt));
+    int best_s = 1;
+    double best = model_time(t, t, ipt, m);
+    for (int64_t sp = 2; sp <= smax; ++sp) {
+        const double v = model_time(t * sp, t, ipt, m);
+        if (v < best) {
+            best = v;
+            best_s = int(sp);
+        }
+    }
+    return best_s;
+}
 
-int owner_of(int i, int q, int r) { return (i < r * (q + 1)) ? i / (q + 1) : r + (i - r * (q + 1)) / q; }
+// First iteration of workgroup x's even share of `total` iterations over g
+// workgroups: proportional (floor(x * total / g)) or leading (the first
+// total mod g workgroups get one iteration more).
+int share_start(int x, int64_t total, int g, bool prop) {
+    if (prop) return int(int64_t(x) * total / g);
+    const int64_t q = total / g, r = total % g;
+    return int(x * q + std::min<int64_t>(x, r));
+}
+
+// Workgroup whose share holds iteration i.
+int owner_of(int i, int64_t total, int g, bool prop) {
+    if (prop) return int((int64_t(i + 1) * g - 1) / total);
+    const int64_t q = total / g, r = total % g;
+    return int((i < r * (q + 1)) ? i / (q + 1) : r + (i - r * (q + 1)) / q);
+}
 
 int find_last_le(const std::vector<int64_t>& base, int G, int64_t x) {
     int lo = 0, hi = G - 1;
@@ -154,8 +185,8 @@ int walk(const skgemm_plan_s& pl, int x, F&& emit) {
     const int np = int(pl.pipt.size());
     int sk_it = 0, sk_end = 0;
     if (x < pl.g_sk) {
-        sk_it = share_start(x, pl.sk_q, pl.sk_r);
-        sk_end = share_start(x + 1, pl.sk_q, pl.sk_r);
+        sk_it = share_start(x, pl.sk_iters, pl.g_sk, pl.share_prop);
+        sk_end = share_start(x + 1, pl.sk_iters, pl.g_sk, pl.share_prop);
     }
     int dp_tile = pl.sk_tiles + x;
     int seq = 0;
@@ -177,7 +208,7 @@ int walk(const skgemm_plan_s& pl, int x, F&& emit) {
             } else if (sk_end < last) {
                 role = ROLE_OWNER;
                 p0 = x + 1;
-                p1 = owner_of(last - 1, pl.sk_q, pl.sk_r);
+                p1 = owner_of(last - 1, pl.sk_iters, pl.g_sk, pl.share_prop);
             } else {
                 role = ROLE_FULL;
             }
@@ -246,6 +277,18 @@ void skgemm_default_options(skgemm_options_t* opt) {
 // Common part of single and grouped planning: validate the options, resolve
 // the co-resident capacity, then the policy, Stream-K region, grid and
 // workspace for the iteration space in pl->{pipt, tile_base, iter_base}.
+// Every problem with tiles has the same iterations per tile (a single GEMM
+// always does), so shares can line up with tile seams.
+static bool uniform_ipt(const skgemm_plan_s& pl) {
+    int ipt = -1;
+    for (size_t i = 0; i < pl.pipt.size(); ++i) {
+        if (pl.tile_base[i + 1] == pl.tile_base[i]) continue;
+        if (ipt < 0) ipt = pl.pipt[i];
+        else if (pl.pipt[i] != ipt) return false;
+    }
+    return true;
+}
+
 static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o) {
     int cus = o.num_cus, occ = o.occupancy;
     if (cus == 0 || occ == 0) {
@@ -266,15 +309,35 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     // iterations per tile for the model (their mean over a grouped launch)
     const int64_t ipt = t ? (total + t - 1) / t : 0;
     int policy = o.policy;
+    int auto_g = 0;
     pl->sk_tiles = 0; pl->g_sk = 0; pl->grid = 0; pl->sk_first = true;
     if (t > 0) {
         if (total == 0) policy = SKGEMM_POLICY_DP;    // K == 0: epilogue-only tiles
         const int64_t w = t / p, r = t % p;
         if (policy == SKGEMM_POLICY_AUTO) {
-            if (r == 0) policy = SKGEMM_POLICY_DP;
-            else if (w == 0) policy = SKGEMM_POLICY_SK;
-            else if (w >= pl->hybrid_min_waves) policy = SKGEMM_POLICY_2TILE_SK_DP;
-            else policy = SKGEMM_POLICY_DP_1TILE_SK;
+            if (r == 0) {
+                policy = SKGEMM_POLICY_DP;
+            } else if (uniform_ipt(*pl)) {
+                // Tile-aligned split of the remainder: with g = s * (its tile
+                // count) and proportional shares, every tile is cut into s
+                // parts at the same k-offsets, so the workgroups of an XCD
+                // stream the same k-slabs at the same time and share them in
+                // L2.  Unaligned shares start each workgroup at its own
+                // k-offset, which on MI355X's per-XCD L2 costs up to 2x.
+                const int64_t sk_t = w == 0 ? t : r;
+                const int s_best = model_best_split(sk_t, ipt, p, pl->model);
+                if (s_best == 1) policy = SKGEMM_POLICY_DP;
+                else {
+                    policy = w == 0 ? SKGEMM_POLICY_SK : SKGEMM_POLICY_DP_1TILE_SK;
+                    auto_g = int(sk_t * s_best);
+                }
+            } else if (w == 0) {
+                policy = SKGEMM_POLICY_SK;
+            } else if (w >= pl->hybrid_min_waves) {
+                policy = SKGEMM_POLICY_2TILE_SK_DP;
+            } else {
+                policy = SKGEMM_POLICY_DP_1TILE_SK;
+            }
         }
         if (policy == SKGEMM_POLICY_DP) {
             pl->grid = int(t);
@@ -293,17 +356,25 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
                                              : pl->iter_base[pi] + int64_t(pl->sk_tiles - pl->tile_base[pi]) * pl->pipt[pi];
             if (policy == SKGEMM_POLICY_SK) {
                 if (o.force_g) pl->g_sk = o.force_g;
+                else if (auto_g) pl->g_sk = auto_g;
                 else if (t >= p) pl->g_sk = int(p);
                 else pl->g_sk = model_best_g(t, ipt, p, pl->model);
                 pl->grid = pl->g_sk;
             } else {
-                if (pl->sk_tiles) pl->g_sk = o.force_g ? o.force_g : int(std::min<int64_t>(p, pl->sk_iters));
+                if (pl->sk_tiles)
+                    pl->g_sk = o.force_g ? o.force_g : auto_g ? auto_g : int(std::min<int64_t>(p, pl->sk_iters));
                 pl->grid = (t - pl->sk_tiles > 0) ? int(p) : pl->g_sk;
                 pl->grid = std::max(pl->grid, pl->g_sk);
             }
         }
     }
     pl->policy = policy;
+    // A forced grid beyond the Stream-K iterations would leave workgroups
+    // with empty shares (between peers, under the proportional share): use
+    // one workgroup per iteration at most.
+    if (pl->g_sk > pl->sk_iters) pl->g_sk = int(pl->sk_iters);
+    if (pl->policy == SKGEMM_POLICY_SK) pl->grid = pl->g_sk;
+    else if (pl->g_sk) pl->grid = std::max(pl->grid, pl->g_sk);
     // Owners wait on workgroups with higher indices, so every Stream-K
     // workgroup must be resident at once.
     if (pl->g_sk > pl->p) return SKGEMM_ERR_CAPACITY;
@@ -347,6 +418,8 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     pl->bkc = pl->swapped ? a_kc : b_kc;
     if (!kernel_exists(pl->dtype, pl->akc, pl->bkc, 0)) return SKGEMM_ERR_UNSUPPORTED;
     pl->hybrid_min_waves = o.hybrid_min_waves;
+    if (o.share != SKGEMM_SHARE_PROPORTIONAL && o.share != SKGEMM_SHARE_LEADING) return SKGEMM_ERR_INVALID_ARG;
+    pl->share_prop = o.share == SKGEMM_SHARE_PROPORTIONAL;
     pl->raster = o.raster_rows ? o.raster_rows : kDefaultRaster;
     pl->xcds = o.xcds ? o.xcds : kDefaultXcds;
     return SKGEMM_OK;
@@ -547,6 +620,7 @@ static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspac
     a->trace = trace;
     a->trace_per_wg = trace ? pl->max_segs : 0;
     a->spin_limit = 1 << 22;
+    a->sk_prop = pl->share_prop ? 1 : 0;
     a->raster = pl->raster;
     a->xcds = pl->xcds;
 }
@@ -658,10 +732,11 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[21] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[22] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
-                           pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G};
-    for (int i = 0; i < n && i < 21; ++i) info[i] = v[i];
+                           pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
+                           pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING};
+    for (int i = 0; i < n && i < 22; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 

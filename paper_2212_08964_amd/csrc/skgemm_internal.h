@@ -61,6 +61,7 @@ struct KArgs {
     int32_t spin_limit;
     const GroupEntry* group;   // grouped launch: G problem entries (else null)
     int32_t G;
+    int32_t sk_prop;           // proportional even share (else leading: first sk_r get sk_q + 1)
     int32_t raster;            // tile rows per raster group (1 = row-major)
     int32_t xcds;              // XCDs the workgroups are spread over (1 = no remapping)
 };

@@ -198,6 +198,7 @@ struct Slab {
                                              int tid) const {
         const bool tail = KC ? (k0 + BK > K) : (o0 + R > dout);
         if (!tail) return;
+        tid = opaque(tid);   // recompute the chunk positions here rather than keep issue()'s live
         const int lim = KC ? (K - k0) : (dout - o0);
         const __amdgpu_buffer_rsrc_t rs = rsrc(it);
         const int lane = tid & 63, w = tid >> 6;
@@ -205,21 +206,26 @@ struct Slab {
         for (int j = 0; j < PER_WAVE; ++j) {
             const int kp = keep(j, tail, lim, tid);
             if (kp > 0 && kp < VE) {
-                uint32_t v[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
+                // Element by element, in a loop that is not unrolled: this
+                // runs once per tile at most, and an unrolled form needs
+                // enough registers to push the accumulators out to scratch.
+                // Elements past the edge are loaded too (inside the operand's
+                // buffer range, or zero past it) and replaced by zero.
+                unsigned char* dst = lds + (w + j * NW) * 1024 + lane * 16;
+                const int off = int(voff[j]);
+#pragma unroll 1
                 for (int e = 0; e < VE; ++e) {
-                    if (e < kp) {
-                        const int off = int(voff[j]) + e * EB;
-                        if constexpr (EB == 4) {
-                            v[e] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-                        } else if constexpr (EB == 2) {
-                            v[e >> 1] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0)) << (16 * (e & 1));
-                        } else {
-                            v[e >> 2] |= uint32_t(__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0)) << (8 * (e & 3));
-                        }
+                    if constexpr (EB == 4) {
+                        const float x = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * e, 0, 0);
+                        *reinterpret_cast<float*>(dst + 4 * e) = e < kp ? x : 0.0f;
+                    } else if constexpr (EB == 2) {
+                        const uint16_t x = __builtin_amdgcn_raw_buffer_load_b16(rs, off + 2 * e, 0, 0);
+                        *reinterpret_cast<uint16_t*>(dst + 2 * e) = e < kp ? x : uint16_t(0);
+                    } else {
+                        const uint8_t x = __builtin_amdgcn_raw_buffer_load_b8(rs, off + e, 0, 0);
+                        dst[e] = e < kp ? x : uint8_t(0);
                     }
                 }
-                *reinterpret_cast<u32x4*>(lds + (w + j * NW) * 1024 + lane * 16) = u32x4{v[0], v[1], v[2], v[3]};
             }
         }
     }
@@ -414,16 +420,13 @@ struct Gemm {
         } else {
             static_assert(AKC && BKC, "FP8 operands must be K-contiguous");
             // Lane group g handles k = 64s + 32g .. +31 of step s (two chunks).
-#pragma unroll
+            // Not unrolled, and B fragments for the step, then one A
+            // fragment at a time: the fewest registers in flight.  Any spill
+            // would make the kernel use scratch memory, and a kernel with
+            // scratch pays a fixed cost of about 20 us per launch on this GPU.
+#pragma unroll 1
             for (int s = 0; s < BK / 64; ++s) {
-                i32x8 af[FM], bf[FN];
-#pragma unroll
-                for (int i = 0; i < FM; ++i) {
-                    const int row = wm * WTM + i * 32 + l32;
-                    const u32x4 lo = lds_row_chunk(As, row, 4 * s + 2 * g);
-                    const u32x4 hi = lds_row_chunk(As, row, 4 * s + 2 * g + 1);
-                    af[i] = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
-                }
+                i32x8 bf[FN];
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
                     const int row = wn * WTN + j * 32 + l32;
@@ -432,11 +435,17 @@ struct Gemm {
                     bf[j] = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
                 }
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                for (int i = 0; i < FM; ++i) {
+                    const int row = wm * WTM + i * 32 + l32;
+                    const u32x4 lo = lds_row_chunk(As, row, 4 * s + 2 * g);
+                    const u32x4 hi = lds_row_chunk(As, row, 4 * s + 2 * g + 1);
+                    const i32x8 af = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y),
+                                           int(hi.z), int(hi.w)};
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
                         acc.v[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            af[i], bf[j], acc.v[i][j], 0, 0, 0, 127, 0, 127);
+                            af, bf[j], acc.v[i][j], 0, 0, 0, 127, 0, 127);
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -556,23 +565,6 @@ struct Gemm {
         return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, BM * BN * 4, kBufferFlags);
     }
 
-    static __device__ __forceinline__ void store_partial(float* slot, const Acc& acc, int tid) {
-        tid = opaque(tid);
-        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot);
-        int q = 0;
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r, ++q) {
-                    const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
-                                     acc.v[i][j][4 * r + 3]};
-                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs,
-                                                           (q * THREADS + tid) * 16, 0, kCoherent);
-                }
-    }
-
     // Loads go in groups of two accumulator blocks (32 registers in flight):
     // issuing all of them before the adds would need a second accumulator's
     // worth of registers and push the accumulators out to scratch memory.
@@ -606,21 +598,82 @@ struct Gemm {
         }
     }
 
-    // C = alpha * s_A * s_B * acc + beta * C over the tile.  Each wave stages
-    // one 32-row band of its block at a time in its own LDS area (FP32, rows
-    // padded by 8 floats; waves of the first half use stage 0, the others
-    // stage 1), then every lane converts eight consecutive columns of one row
-    // and writes them with one store, predicated at the M and N edges.  The
-    // caller guarantees all waves have left the MAC loop's LDS.
+    // Output of one 32-row band of the wave's block, staged in `st` (FP32,
+    // rows of EPI_LD floats): each lane converts eight consecutive columns of
+    // one row and writes them with one store, predicated at the M and N edges.
+    template <int OUT>
+    static __device__ __forceinline__ void write_band(const Prob& a, float s, const float* st, int row0, int col,
+                                                      int ncol, int lane) {
+        constexpr int LPR = WTN / 8;          // lanes per row
+        constexpr int RPP = 64 / LPR;         // rows per pass
+#pragma unroll
+        for (int pass = 0; pass < 32 / RPP; ++pass) {
+            const int rl = pass * RPP + lane / LPR;
+            const int row = row0 + rl;
+            const f32x4 lo = *reinterpret_cast<const f32x4*>(st + rl * EPI_LD + (lane % LPR) * 8);
+            const f32x4 hi = *reinterpret_cast<const f32x4*>(st + rl * EPI_LD + (lane % LPR) * 8 + 4);
+            const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            if (row < a.M && ncol > 0) {
+                const int64_t off = (int64_t)row * a.ldc + col;
+                if (ncol == 8) {
+                    if constexpr (OUT == DT_F32) {
+                        f32x4* cp = reinterpret_cast<f32x4*>(reinterpret_cast<float*>(a.C) + off);
+                        f32x4 o0 = {v[0], v[1], v[2], v[3]}, o1 = {v[4], v[5], v[6], v[7]};
+                        o0 *= s;
+                        o1 *= s;
+                        if (a.beta != 0.0f) {
+                            o0 += a.beta * cp[0];
+                            o1 += a.beta * cp[1];
+                        }
+                        cp[0] = o0;
+                        cp[1] = o1;
+                    } else {
+                        u32x4* cp = reinterpret_cast<u32x4*>(reinterpret_cast<uint16_t*>(a.C) + off);
+                        float cin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                        if (a.beta != 0.0f) {
+                            const u32x4 cv = *cp;
+#pragma unroll
+                            for (int e = 0; e < 8; ++e)
+                                cin[e] = half_to_f32<OUT>(uint16_t(cv[e >> 1] >> (16 * (e & 1))));
+                        }
+                        u32x4 o;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const float x0 = s * v[2 * e] + a.beta * cin[2 * e];
+                            const float x1 = s * v[2 * e + 1] + a.beta * cin[2 * e + 1];
+                            o[e] = uint32_t(f32_to_half<OUT>(x0)) | (uint32_t(f32_to_half<OUT>(x1)) << 16);
+                        }
+                        *cp = o;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        if (e < ncol) {
+                            float x = s * v[e];
+                            if (a.beta != 0.0f) x += a.beta * load_c1<OUT>(a.C, off + e);
+                            store_c1<OUT>(a.C, off + e, x);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // The accumulators leave the registers band by band (FM bands of 32 rows
+    // per wave), either as a partial tile (coherent stores to `slot`, in the
+    // fragment order add_partial reads) or through the epilogue: C = alpha *
+    // s_A * s_B * acc + beta * C, each band staged in the wave's own LDS area
+    // (waves of the first half use stage 0, the others stage 1).  One band
+    // loop serves both, so the accumulators have a single way out of the
+    // registers (two separate consumers made the register allocator spill
+    // them).  The caller guarantees all waves have left the MAC loop's LDS.
     static constexpr int EPI_LD = WTN + 8;
     static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
     static_assert(EPI_BYTES * (NW / 2) <= STAGE, "epilogue staging must fit in one stage");
     static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
 
-    template <int OUT>
-    static __device__ __forceinline__ void epilogue_t(const Prob& a, const float* scale_a, const float* scale_b,
-                                                      int tile, const Acc& acc, int tid, unsigned char* s0,
-                                                      unsigned char* s1) {
+    static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, const Acc& acc,
+                                                  int tid, unsigned char* s0, unsigned char* s1, float* slot) {
         tid = opaque(tid);
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const int g = lane >> 5, l32 = lane & 31;
@@ -630,84 +683,44 @@ struct Gemm {
         n0 += wn * WTN;
         float* st = reinterpret_cast<float*>((w < NW / 2 ? s0 : s1) + (w % (NW / 2)) * EPI_BYTES);
         float s = a.alpha;
-        if (scale_a) s *= *scale_a;
-        if (scale_b) s *= *scale_b;
-        constexpr int LPR = WTN / 8;          // lanes per row
-        constexpr int RPP = 64 / LPR;         // rows per pass
+        if (!slot) {
+            if (ka.scale_a) s *= *ka.scale_a;
+            if (ka.scale_b) s *= *ka.scale_b;
+        }
+        constexpr int LPR = WTN / 8;
         const int col = n0 + (lane % LPR) * 8;
         const int ncol = min(max(a.N - col, 0), 8);
+        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot);
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
+            if (slot) {
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
+                for (int j = 0; j < FN; ++j)
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-            for (int pass = 0; pass < 32 / RPP; ++pass) {
-                const int rl = pass * RPP + lane / LPR;
-                const int row = m0 + i * 32 + rl;
-                const f32x4 lo = *reinterpret_cast<const f32x4*>(st + rl * EPI_LD + (lane % LPR) * 8);
-                const f32x4 hi = *reinterpret_cast<const f32x4*>(st + rl * EPI_LD + (lane % LPR) * 8 + 4);
-                const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-                if (row < a.M && ncol > 0) {
-                    const int64_t off = (int64_t)row * a.ldc + col;
-                    if (ncol == 8) {
-                        if constexpr (OUT == DT_F32) {
-                            f32x4* cp = reinterpret_cast<f32x4*>(reinterpret_cast<float*>(a.C) + off);
-                            f32x4 o0 = {v[0], v[1], v[2], v[3]}, o1 = {v[4], v[5], v[6], v[7]};
-                            o0 *= s;
-                            o1 *= s;
-                            if (a.beta != 0.0f) {
-                                o0 += a.beta * cp[0];
-                                o1 += a.beta * cp[1];
-                            }
-                            cp[0] = o0;
-                            cp[1] = o1;
-                        } else {
-                            u32x4* cp = reinterpret_cast<u32x4*>(reinterpret_cast<uint16_t*>(a.C) + off);
-                            float cin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                            if (a.beta != 0.0f) {
-                                const u32x4 cv = *cp;
-#pragma unroll
-                                for (int e = 0; e < 8; ++e)
-                                    cin[e] = half_to_f32<OUT>(uint16_t(cv[e >> 1] >> (16 * (e & 1))));
-                            }
-                            u32x4 o;
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const float x0 = s * v[2 * e] + a.beta * cin[2 * e];
-                                const float x1 = s * v[2 * e + 1] + a.beta * cin[2 * e + 1];
-                                o[e] = uint32_t(f32_to_half<OUT>(x0)) | (uint32_t(f32_to_half<OUT>(x1)) << 16);
-                            }
-                            *cp = o;
-                        }
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            if (e < ncol) {
-                                float x = s * v[e];
-                                if (a.beta != 0.0f) x += a.beta * load_c1<OUT>(a.C, off + e);
-                                store_c1<OUT>(a.C, off + e, x);
-                            }
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        const int q = (i * FN + j) * 4 + r;
+                        const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
+                                         acc.v[i][j][4 * r + 3]};
+                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs,
+                                                               (q * THREADS + tid) * 16, 0, kCoherent);
                     }
-                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (ka.out_dtype == DT_F32) write_band<DT_F32>(a, s, st, m0 + i * 32, col, ncol, lane);
+                else if (ka.out_dtype == DT_BF16) write_band<DT_BF16>(a, s, st, m0 + i * 32, col, ncol, lane);
+                else write_band<DT_F16>(a, s, st, m0 + i * 32, col, ncol, lane);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-    }
-
-    static __device__ __forceinline__ void epilogue(const KArgs& ka, const Prob& a, int tile, const Acc& acc,
-                                                    int tid, unsigned char* s0, unsigned char* s1) {
-        if (ka.out_dtype == DT_F32) epilogue_t<DT_F32>(a, ka.scale_a, ka.scale_b, tile, acc, tid, s0, s1);
-        else if (ka.out_dtype == DT_BF16) epilogue_t<DT_BF16>(a, ka.scale_a, ka.scale_b, tile, acc, tid, s0, s1);
-        else epilogue_t<DT_F16>(a, ka.scale_a, ka.scale_b, tile, acc, tid, s0, s1);
     }
 
     // Grouped launches: the problem holding a global iteration / tile (the
@@ -764,9 +777,17 @@ struct Gemm {
         }
     }
 
-    static __device__ __forceinline__ int share_start(int x, int q, int r) { return x * q + min(x, r); }
+    // Even share of the Stream-K iterations: proportional (workgroup x starts
+    // at floor(x * T / g)) or leading (the first T mod g workgroups get q + 1).
+    static __device__ __forceinline__ int share_start(const KArgs& a, int x) {
+        if (a.sk_prop) return int(int64_t(x) * a.sk_iters / a.g_sk);
+        return x * a.sk_q + min(x, a.sk_r);
+    }
 
-    static __device__ __forceinline__ int owner_of(int i, int q, int r) {
+    // The workgroup whose share holds iteration i.
+    static __device__ __forceinline__ int owner_of(const KArgs& a, int i) {
+        if (a.sk_prop) return int((int64_t(i + 1) * a.g_sk - 1) / a.sk_iters);
+        const int q = a.sk_q, r = a.sk_r;
         return (i < r * (q + 1)) ? i / (q + 1) : r + (i - r * (q + 1)) / q;
     }
 
@@ -780,8 +801,8 @@ struct Gemm {
         const int wg = logical_wg(blockIdx.x, a.grid, a.xcds);
         int sk_it = 0, sk_end = 0;
         if (wg < a.g_sk) {
-            sk_it = share_start(wg, a.sk_q, a.sk_r);
-            sk_end = share_start(wg + 1, a.sk_q, a.sk_r);
+            sk_it = share_start(a, wg);
+            sk_end = share_start(a, wg + 1);
         }
         int dp_tile = a.sk_tiles + wg;
         int seq = 0;
@@ -814,7 +835,7 @@ struct Gemm {
                     role = ROLE_PARTIAL;
                 } else if (sk_end < last) {
                     role = ROLE_OWNER;
-                    peer_end = owner_of(last - 1, a.sk_q, a.sk_r);
+                    peer_end = owner_of(a, last - 1);
                 } else {
                     role = ROLE_FULL;
                 }
@@ -846,29 +867,28 @@ struct Gemm {
 
             mac_loop(pr, s0, s1, tile, lo, hi, acc, tid);
 
-            if (role == ROLE_PARTIAL) {
-                store_partial(a.partials + (size_t)wg * (BM * BN), acc, tid);
+            if (role == ROLE_OWNER) {
+                // Every wave waits for each peer's flag itself (a wave-uniform
+                // loop: no divergent region around the accumulators), then
+                // adds that peer's partial.
+                for (int peer = wg + 1; peer <= peer_end; ++peer) {
+                    wait_flag(a.flags + (size_t)peer * kFlagStrideInts, a.spin_limit, a.err);
+                    add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);   // coherent loads
+                }
+                __syncthreads();   // every wave has seen every flag: clear them for the next launch
+                if (tid == 0)
+                    for (int peer = wg + 1; peer <= peer_end; ++peer)
+                        __hip_atomic_store(a.flags + (size_t)peer * kFlagStrideInts, 0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const bool partial = role == ROLE_PARTIAL;
+            finish(a, pr, tile, acc, tid, s0, s1, partial ? a.partials + (size_t)wg * (BM * BN) : nullptr);
+            if (partial) {
                 wait_vmem();              // this wave's coherent partial stores have completed
                 __syncthreads();          // ... and so have every other wave's
                 if (tid == 0)
                     __hip_atomic_store(a.flags + (size_t)wg * kFlagStrideInts, 1, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                if (role == ROLE_OWNER) {
-                    // Every wave waits for each peer's flag itself (a wave-
-                    // uniform loop: no divergent region around the
-                    // accumulators), then adds that peer's partial.
-                    for (int peer = wg + 1; peer <= peer_end; ++peer) {
-                        wait_flag(a.flags + (size_t)peer * kFlagStrideInts, a.spin_limit, a.err);
-                        add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);   // coherent loads
-                    }
-                    __syncthreads();   // every wave has seen every flag: clear them for the next launch
-                    if (tid == 0)
-                        for (int peer = wg + 1; peer <= peer_end; ++peer)
-                            __hip_atomic_store(a.flags + (size_t)peer * kFlagStrideInts, 0, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                }
-                epilogue(a, pr, tile, acc, tid, s0, s1);
             }
         }
     }

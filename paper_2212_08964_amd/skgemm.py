@@ -34,14 +34,17 @@ EXPORTED = [
 ]
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
-               "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G"]
+               "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
+               "share"]
+SHARE = {"proportional": 0, "leading": 1}
+SHARE_NAME = {v: k for k, v in SHARE.items()}
 
 
 class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int), ("force_g", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
                 ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("raster_rows", ctypes.c_int32),
-                ("xcds", ctypes.c_int32)]
+                ("xcds", ctypes.c_int32), ("share", ctypes.c_int32)]
 
 
 class GroupArgs(ctypes.Structure):
@@ -124,12 +127,13 @@ class Plan:
 
     def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0):
+                 raster_rows=0, xcds=0, share="proportional"):
         self._h = ctypes.c_void_p()
         o = default_options()
         if tile:
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
         o.raster_rows, o.xcds = int(raster_rows), int(xcds)
+        o.share = SHARE[share] if isinstance(share, str) else int(share)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
@@ -162,11 +166,12 @@ class Plan:
         return n.value
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 21)()
-        _check(lib().skgemm_plan_info(self._h, buf, 21), "skgemm_plan_info")
+        buf = (ctypes.c_int64 * 22)()
+        _check(lib().skgemm_plan_info(self._h, buf, 22), "skgemm_plan_info")
         d = dict(zip(INFO_FIELDS, list(buf)))
         d["policy_name"] = POLICY_NAME[d["policy"]]
         d["tile"] = (d["BM"], d["BN"], d["BK"])
+        d["share_name"] = SHARE_NAME[d["share"]]
         return d
 
     def model_constants(self):
@@ -201,7 +206,7 @@ class GroupedPlan(Plan):
 
     def __init__(self, Ms, Ns, Ks, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0):
+                 raster_rows=0, xcds=0, share="proportional"):
         self._h = ctypes.c_void_p()
         G = len(Ms)
         if not (len(Ns) == len(Ks) == G):
@@ -210,6 +215,7 @@ class GroupedPlan(Plan):
         if tile:
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
         o.raster_rows, o.xcds = int(raster_rows), int(xcds)
+        o.share = SHARE[share] if isinstance(share, str) else int(share)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)

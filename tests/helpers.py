@@ -23,11 +23,15 @@ def records_to_schedule(records, grid):
     return out
 
 
+SHARE_BY_ID = {0: "proportional", 1: "leading"}
+
+
 def oracle_plan_for(info, model, policy, force_g=0):
     """The oracle's plan for the problem a library plan launches."""
     return S.make_plan(int(info["M"]), int(info["N"]), int(info["K"]), int(info["BM"]), int(info["BN"]),
                        int(info["BK"]), int(info["p"]), policy=policy, force_g=force_g,
-                       hybrid_min_waves=int(info["hybrid_min_waves"]), model=model)
+                       hybrid_min_waves=int(info["hybrid_min_waves"]), model=model,
+                       share=SHARE_BY_ID[int(info.get("share", 0))])
 
 
 def bits_u16(t):

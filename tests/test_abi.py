@@ -54,8 +54,16 @@ def test_plan_argument_errors():
     assert L.skgemm_plan(None, 4, 4, 4, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16, None) == sk.ERR_INVALID_ARG
     # a Stream-K grid beyond the co-resident capacity is refused
     o.policy, o.force_g = sk.POLICY["sk"], 300
-    assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+    assert L.skgemm_plan(ctypes.byref(h), 512, 512, 8192, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
                          ctypes.byref(o)) == sk.ERR_CAPACITY
+    # ... while one beyond the iterations is reduced to one workgroup per iteration
+    o.force_g = 40
+    pl = sk.Plan(64, 64, 640, ta=sk.BF16, policy="sk", force_g=40, num_cus=256, occupancy=1)
+    assert pl.info()["g_sk"] == pl.info()["grid"] == 10
+    o.share = 2
+    assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                         ctypes.byref(o)) == sk.ERR_INVALID_ARG
+    o.share = 0
     o.tile_m = 64
     o.force_g = 0
     assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
@@ -95,13 +103,14 @@ SHAPES = [(384, 384, 1024), (896, 384, 128), (1, 1, 1), (300, 500, 700), (4096, 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("policy", ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
-def test_planner_schedule_matches_enumerator(dtype, policy):
+@pytest.mark.parametrize("share", ["proportional", "leading"])
+def test_planner_schedule_matches_enumerator(dtype, policy, share):
     sk = _lib()
     ta = {"f32": sk.F32, "bf16": sk.BF16}[dtype]
     for (M, N, K), (cus, occ), lc in itertools.product(SHAPES, [(256, 1), (256, 2), (4, 1), (37, 3)],
                                                        [sk.ROW_MAJOR, sk.COL_MAJOR]):
         try:
-            p = sk.Plan(M, N, K, ta=ta, lc=lc, policy=policy, num_cus=cus, occupancy=occ)
+            p = sk.Plan(M, N, K, ta=ta, lc=lc, policy=policy, num_cus=cus, occupancy=occ, share=share)
         except sk.SkgemmError as e:
             assert e.status == sk.ERR_CAPACITY
             continue
@@ -118,9 +127,10 @@ def test_planner_schedule_matches_enumerator(dtype, policy):
 
 
 @pytest.mark.parametrize("g", [1, 2, 3, 5, 9, 16, 36, 100, 288, 300])
-def test_planner_forced_grid_matches_enumerator(g):
+@pytest.mark.parametrize("share", ["proportional", "leading"])
+def test_planner_forced_grid_matches_enumerator(g, share):
     sk = _lib()
-    p = sk.Plan(384, 384, 1024, ta=sk.F32, policy="sk", force_g=g, num_cus=256, occupancy=2)
+    p = sk.Plan(384, 384, 1024, ta=sk.F32, policy="sk", force_g=g, num_cus=256, occupancy=2, share=share)
     info = p.info()
     ref = oracle_plan_for(info, p.model_constants(), "sk", force_g=g)
     got = records_to_schedule(p.schedule(), info["grid"])

@@ -16,6 +16,7 @@ import os
 
 import pytest
 
+from oracle import grouped as GR
 from oracle import schedule as S
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "streamk_worked_examples.json")))
@@ -61,8 +62,10 @@ def test_hybrid_examples_peer_counts():
     # exactly one peer; DP + one-tile SK puts three peers on one owner.
     two = S.make_plan(896, 384, 128, 128, 128, 4, p=4, policy="2tile_sk_dp")
     one = S.make_plan(896, 384, 128, 128, 128, 4, p=4, policy="dp_1tile_sk")
-    auto = S.make_plan(896, 384, 128, 128, 128, 4, p=4)
-    assert auto.policy == "2tile_sk_dp"
+    # the paper's automatic choice for two or more full waves (kept for grouped
+    # launches whose problems differ in iterations per tile)
+    paper = GR.make_grouped_plan([(896, 384, 128), (128, 128, 8)], 128, 128, 4, p=4)
+    assert paper.policy == "2tile_sk_dp"
     owners2 = [s for segs in S.enumerate_schedule(two) for s in segs if s.role == S.OWNER]
     owners1 = [s for segs in S.enumerate_schedule(one) for s in segs if s.role == S.OWNER]
     assert owners2 and all(len(s.peers) == 1 for s in owners2)
@@ -149,17 +152,53 @@ def test_sk_with_g_multiple_of_t_is_fixed_split(s):
 
 def test_auto_policy_regimes():
     p = 256
+    m = (0, 20, 1, 8)
     # full waves only -> data-parallel
     assert S.make_plan(8192, 8192, 8192, 256, 256, 64, p).policy == "dp"
-    # fewer tiles than workgroups -> basic Stream-K, g within [t, p]
-    pl = S.make_plan(384, 384, 1024, 128, 128, 32, p, model=(0, 20, 1, 8))
-    assert pl.policy == "sk" and pl.t <= pl.g_sk <= p
-    # one full wave plus a remainder -> DP + one-tile SK
-    pl = S.make_plan(256 * 17, 256 * 16, 1024, 256, 256, 64, p)
-    assert pl.policy == "dp_1tile_sk" and pl.sk_tiles == 16
-    # two or more waves plus a remainder -> two-tile SK + DP with one fewer DP wave
-    pl = S.make_plan(256 * 33, 256 * 16, 1024, 256, 256, 64, p)
-    assert pl.policy == "2tile_sk_dp" and pl.sk_tiles == 16 + 256 and pl.g_sk == 256
+    # fewer tiles than workgroups -> basic Stream-K with g a multiple of t (each tile cut into
+    # s parts), or data-parallel when the model prefers s = 1
+    pl = S.make_plan(384, 384, 8192, 128, 128, 32, p, model=m)
+    assert pl.policy == "sk" and pl.g_sk % pl.t == 0 and pl.t < pl.g_sk <= p
+    assert pl.g_sk // pl.t == S.model_best_split(pl.t, pl.ipt, p, m)
+    pl = S.make_plan(384, 384, 64, 128, 128, 32, p, model=m)      # two iterations per tile
+    assert pl.policy == "dp" and pl.grid == pl.t
+    # full waves plus a remainder -> DP + one-tile SK over the remainder with g = s * r
+    for waves in (1, 2, 3):
+        pl = S.make_plan(256 * (16 * waves + 1), 256 * 16, 4096, 256, 256, 64, p, model=m)
+        assert pl.policy == "dp_1tile_sk" and pl.sk_tiles == 16 and pl.g_sk % 16 == 0
+        assert pl.g_sk // 16 == S.model_best_split(16, pl.ipt, p, m) and pl.grid == p
+
+
+@pytest.mark.parametrize("t,ipt,s", [(3, 10, 4), (7, 9, 2), (5, 64, 8), (12, 88, 10), (1, 7, 7)])
+def test_proportional_share_cuts_every_tile_alike(t, ipt, s):
+    """With g = s * t the proportional share cuts every tile at the same k-offsets (the
+    offsets of the within-one split of ipt into s parts), whether or not s divides ipt;
+    the leading rule does not when s does not divide ipt."""
+    M, N, K = 128 * t, 128, 8 * ipt
+    prop = S.make_plan(M, N, K, 128, 128, 8, p=4096, policy="sk", force_g=s * t)
+    sched = S.enumerate_schedule(prop)
+    S.check_invariants(prop, sched)
+    cuts = [sorted(seg.k_lo for segs in sched for seg in segs if seg.tile == x) for x in range(t)]
+    assert all(c == cuts[0] for c in cuts) and len(cuts[0]) == s
+    sizes = [seg.k_hi - seg.k_lo for segs in sched for seg in segs]
+    assert max(sizes) - min(sizes) <= 1
+    lead = S.make_plan(M, N, K, 128, 128, 8, p=4096, policy="sk", force_g=s * t, share="leading")
+    lcuts = [sorted(seg.k_lo for segs in S.enumerate_schedule(lead) for seg in segs if seg.tile == x)
+             for x in range(t)]
+    assert (all(c == lcuts[0] for c in lcuts)) == (ipt % s == 0 or t == 1)
+
+
+def test_share_rules_are_within_one():
+    for total in (1, 7, 100, 288, 1000):
+        for g in (1, 2, 3, 7, 64, total):
+            for share in ("proportional", "leading"):
+                starts = [S.share_start(x, total, g, share) for x in range(g + 1)]
+                sizes = [b - a for a, b in zip(starts, starts[1:])]
+                assert starts[0] == 0 and starts[-1] == total
+                assert set(sizes) <= {total // g, -(-total // g)}
+                for i in range(total):
+                    x = S.owner_of(i, total, g, share)
+                    assert starts[x] <= i < starts[x + 1]
 
 
 def test_planted_mistake_is_caught():
