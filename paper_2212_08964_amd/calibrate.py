@@ -92,18 +92,47 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     y = np.array(ys)
     coef, *_ = np.linalg.lstsq(X, y, rcond=None)
     a, b, c, d = (float(v) for v in coef)
-    return (a / c, b / c, 1.0, d / c), (a, b, c, d), X, y
+    # e: per-iteration time with all p slots busy, from a data-parallel problem
+    # of four full waves (four tiles per slot) at two depths
+    tw = []
+    for ipt in (16, 64):
+        t = 4 * p
+        tm = 1
+        while tm * tm < t:
+            tm *= 2
+        tn = t // tm
+        M, N, K = BM * tm, BN * tn, BK * ipt
+        A = torch.randn(M, K, device="cuda").to(tdt)
+        B = torch.randn(K, N, device="cuda").to(tdt)
+        C = torch.empty(M, N, device="cuda", dtype=tdt)
+        plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="dp", tile=(BM, BN, BK))
+        launch = _launcher(sk, plan, A, B, C, None, 0)
+        launch()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            launch()
+        e1.record()
+        e1.synchronize()
+        tw.append(e0.elapsed_time(e1) / 5 * 1e3 / 4)      # microseconds per wave
+        if verbose:
+            print(f"full waves: t={t} ipt={ipt}: {tw[-1]:.2f} us per wave", flush=True)
+    e = (tw[1] - tw[0]) / (64 - 16)
+    return (a / c, b / c, 1.0, d / c), (a, b, c, d, e), X, y
 
 
 def main():
     dtype = sys.argv[1] if len(sys.argv) > 1 else "bf16"
     tile = tuple(int(x) for x in sys.argv[2].split("x")) if len(sys.argv) > 2 else None
     norm, raw, X, y = measure(dtype, tile=tile)
-    a, b, c, d = raw
+    a, b, c, d, e = raw
     pred = X @ [a, b, c, d]
     import numpy as np
     err = float(np.sqrt(np.mean((pred - y) ** 2)))
     print(f"raw (us): a={a:.3f} b={b:.3f} c={c:.3f} d={d:.3f}  rms residual {err:.2f} us over {len(y)} runs")
+    print(f"full occupancy (us per iteration): e={e:.3f}")
     print(f"normalised (c=1): a={norm[0]:.3f} b={norm[1]:.3f} c=1 d={norm[3]:.3f}")
 
 

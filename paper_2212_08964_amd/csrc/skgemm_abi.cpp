@@ -43,7 +43,7 @@ struct skgemm_plan_s {
     int raster, xcds;  // tile raster group rows; XCD count for the workgroup permutation
     bool share_prop;   // proportional (else leading) even share
     int sk_q, sk_r;
-    double model[4];
+    double model[5];   // a, b, c, d of the grid-size model; e: c with every workgroup slot busy
     // workspace layout
     size_t ws_bytes, flags_off, partials_off;
     int max_segs;
@@ -98,11 +98,15 @@ TileCfg tile_for(int dt, int v) {
 // partial.  The grid-size argmin only depends on their ratios; the absolute
 // values let the planner compare tile variants.
 void model_for(int dt, int v, double* m) {
-    // least-squares fits over tile-aligned grids (FP8 shares the 16-bit
-    // 256x256 constants: its kernel has the same tile and wave layout)
-    if (dt == DT_F32) { m[0] = 4.6; m[1] = 5.4; m[2] = 2.09; m[3] = 1.46; return; }
-    if (v == 1) { m[0] = 6.4; m[1] = 2.8; m[2] = 0.59; m[3] = 1.49; return; }
-    m[0] = 7.0; m[1] = 9.0; m[2] = 1.33; m[3] = 2.69;
+    // a-d: least-squares fits over tile-aligned grids (calibrate.py); e: the
+    // per-iteration time of one workgroup when all p co-resident workgroups
+    // run (a data-parallel problem of several full waves), which only the
+    // comparison of tile variants uses.  FP8 shares the 16-bit 256x256
+    // constants: same tile, same wave layout, twice the k per iteration at
+    // twice the MFMA rate.
+    if (dt == DT_F32) { m[0] = 4.6; m[1] = 5.4; m[2] = 2.09; m[3] = 1.46; m[4] = 4.2; return; }
+    if (v == 1) { m[0] = 6.4; m[1] = 2.8; m[2] = 0.59; m[3] = 1.49; m[4] = 1.04; return; }
+    m[0] = 13.3; m[1] = 5.2; m[2] = 1.36; m[3] = 2.98; m[4] = 1.89;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -436,12 +440,18 @@ static double plan_estimate(const skgemm_plan_s* pl) {
     const int np = int(pl->pipt.size());
     const double ipt = double(pl->iter_base[np]) / pl->t;
     const double* m = pl->model;
-    if (pl->g_sk == 0) return double(cdiv(pl->t, pl->p)) * (m[0] + m[2] * ipt);
+    const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4];
+    // per-iteration time with `active` of the p workgroup slots busy
+    auto c_at = [&](int64_t active) { return c + (e - c) * std::min(1.0, double(active) / pl->p); };
+    if (pl->g_sk == 0) {
+        const int64_t full = pl->t / pl->p, rem = pl->t % pl->p;
+        return double(full) * (a + e * ipt) + (rem ? a + c_at(rem) * ipt : 0.0);
+    }
     const int64_t ipc = cdiv(pl->sk_iters, pl->g_sk);
     const int64_t peers = std::max<int64_t>(1, cdiv(int64_t(ipt + 0.5), ipc));
     const int64_t dp_per_wg = cdiv(pl->t - pl->sk_tiles, pl->grid);
-    return m[0] * double(1 + dp_per_wg) + m[1] * (peers > 1 ? 1.0 : 0.0) + m[2] * (double(ipc) + dp_per_wg * ipt) +
-           m[3] * double(peers - 1);
+    return a + double(dp_per_wg) * (a + e * ipt) + b * (peers > 1 ? 1.0 : 0.0) + c_at(pl->g_sk) * double(ipc) +
+           d * double(peers - 1);
 }
 
 // Builds the plan for every admissible tile variant (the one the options

@@ -215,9 +215,10 @@ struct Slab {
                 const int off = int(voff[j]);
 #pragma unroll 1
                 for (int e = 0; e < VE; ++e) {
+                    // the loads return raw bits (unsigned integers of the element's width)
                     if constexpr (EB == 4) {
-                        const float x = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * e, 0, 0);
-                        *reinterpret_cast<float*>(dst + 4 * e) = e < kp ? x : 0.0f;
+                        const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * e, 0, 0);
+                        *reinterpret_cast<uint32_t*>(dst + 4 * e) = e < kp ? x : 0u;
                     } else if constexpr (EB == 2) {
                         const uint16_t x = __builtin_amdgcn_raw_buffer_load_b16(rs, off + 2 * e, 0, 0);
                         *reinterpret_cast<uint16_t*>(dst + 2 * e) = e < kp ? x : uint16_t(0);

@@ -70,8 +70,8 @@ def _capacity(M, N, K, ta):
 
 @pytest.mark.parametrize("g", [1, 2, 9, 16, 36, 64, 100, 200, 256, 288, 500])
 def test_integer_f32_bit_exact_every_grid(g):
-    """g up to the co-resident capacity p; g > 288 (= total iterations) leaves
-    some workgroups without work."""
+    """g up to the co-resident capacity p; a g above the 288 iterations is
+    reduced to one workgroup per iteration."""
     if g > _capacity(384, 384, 1024, sk().F32):
         pytest.skip("grid larger than the co-resident capacity of this GPU")
     a, b = W.plain_f32(seed=0, integer=True)
@@ -83,9 +83,9 @@ def test_integer_f32_bit_exact_every_grid(g):
 
 
 def test_capacity_refused_beyond_resident():
-    p = _capacity(384, 384, 1024, sk().F32)
+    p = _capacity(384, 384, 8192, sk().F32)
     with pytest.raises(sk().SkgemmError) as e:
-        sk().Plan(384, 384, 1024, ta=sk().F32, policy="sk", force_g=p + 1)
+        sk().Plan(384, 384, 8192, ta=sk().F32, policy="sk", force_g=p + 1)   # 2304 iterations > p + 1
     assert e.value.status == sk().ERR_CAPACITY
 
 
