@@ -33,6 +33,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "skgemm_internal.h"
 
 namespace skg {
@@ -42,6 +44,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
@@ -51,12 +54,14 @@ typedef __attribute__((address_space(3))) void lds_void;
 // wavefronts).  Variant 1 is the small 16-bit tile (cheaper partial tiles
 // and epilogues for small, memory-bound problems; two workgroups per CU).
 template <int DT, int V> struct Cfg;
-template <> struct Cfg<DT_F32, 0> { static constexpr int EB = 4, BM = kTileF32.bm, BN = kTileF32.bn, BK = kTileF32.bk, WM = 2, WN = 2; };
-template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
-template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4; };
-template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4; };
-template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2; };
-template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2; };
+// NS is the number of LDS stages of the MAC-loop pipeline (NS - 1 k-slabs in
+// flight while one is consumed).
+template <> struct Cfg<DT_F32, 0> { static constexpr int EB = 4, BM = kTileF32.bm, BN = kTileF32.bn, BK = kTileF32.bk, WM = 2, WN = 2, NS = kTileF32.ns; };
+template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
+template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
+template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4, NS = kTileF8.ns; };
+template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
+template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 
 template <int DT, int V>
 constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
@@ -70,6 +75,32 @@ constexpr int kWavesPerEU = 2;
 constexpr int kBufferFlags = 0x00020000;
 
 __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// 32-bit LDS address of an LDS location (wave-uniform here).
+__device__ __forceinline__ uint32_t lds_addr(unsigned char* p) {
+    lds_void* q = (lds_void*)p;      // generic -> LDS address space (a C-style cast is required)
+    return uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(size_t(q)))));
+}
+
+// One 16-byte-per-lane buffer load that writes LDS directly: lane i's chunk
+// lands at LDS address m0 + 16 i; out-of-range offsets read as zero.  Issued
+// as inline assembly so that the compiler's own wait-count bookkeeping does
+// not see it: across the pipeline loop's back edge it cannot tell which LDS
+// stage a load in flight targets and would drain all of them; the pipeline
+// waits for its slabs itself (vmcnt, oldest first).  m0 is set here and used
+// by nothing else in these kernels.
+__device__ __forceinline__ void dma16(const i32x4& desc, uint32_t voff, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds"
+                 :
+                 : "v"(voff), "s"(desc), "s"(lds)
+                 : "memory");
+}
+
+// Workgroup barrier between pipeline steps, without the memory fence of
+// __syncthreads (which would also wait for the slab loads still in flight to
+// the other stages).  Each wave's LDS accesses have completed (its fragment
+// reads, and the slab loads it waited for explicitly) before it arrives.
+__device__ __forceinline__ void step_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Values that are the same in every lane but reach the compiler through
 // vector registers (a grouped launch reads its problem table with vector
@@ -98,9 +129,10 @@ __device__ __forceinline__ int opaque(int x) {
 // ------------------------------------------------------------------ slab loads
 
 // Position swizzle of a row of a slab in LDS (see the layout note above).
-template <int EB, bool KC>
+template <int EB, bool KC, int ROWB>
 __device__ __forceinline__ int swz(int row) {
-    if constexpr (KC) return (row & 7) ^ ((row >> 3) & 1);
+    if constexpr (KC && ROWB == 128) return (row & 7) ^ ((row >> 3) & 1);
+    else if constexpr (KC) return (row >> 2) & 3;          // 64-byte rows: 4 chunks
     else if constexpr (EB == 4) return 8 * ((row >> 2) & 1);
     else return 4 * (row & 3);
 }
@@ -124,7 +156,7 @@ struct Slab {
     static constexpr int NW = THREADS / 64;
     static constexpr int BLOCKS = BYTES / 1024;
     static constexpr int PER_WAVE = BLOCKS / NW;
-    static_assert(BK * EB == 128, "k slab must be 128 bytes");
+    static_assert(!KC || BK * EB == 128 || BK * EB == 64, "K-contiguous slab rows must be 64 or 128 bytes");
     static_assert(KC || ROWB == 512 || ROWB == 256, "MN-contiguous slab rows must be 256 or 512 bytes");
     static_assert(BLOCKS % NW == 0, "slab must split evenly over the waves");
 
@@ -159,15 +191,24 @@ struct Slab {
     }
     static __device__ __forceinline__ int chunk_col(int j, int tid) {
         const int pos = ((tid >> 6) + j * NW) * 1024 + (tid & 63) * 16;
-        return ((pos % ROWB) >> 4) ^ swz<EB, KC>(pos / ROWB);
+        return ((pos % ROWB) >> 4) ^ swz<EB, KC, ROWB>(pos / ROWB);
+    }
+
+    __device__ __forceinline__ int nrec(int it) const {
+        const int64_t left = bytes - (int64_t)it * step;
+        return left <= 0 ? 0 : (left > 0x7fffffff ? 0x7fffffff : int(left));
     }
 
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int it) const {
-        const int64_t skip = (int64_t)it * step;
-        const int64_t left = bytes - skip;
-        const int nrec = left <= 0 ? 0 : (left > 0x7fffffff ? 0x7fffffff : int(left));
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(base + skip), (short)0, nrec,
-                                                 kBufferFlags);
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(base + (int64_t)it * step), (short)0,
+                                                 nrec(it), kBufferFlags);
+    }
+
+    // The same descriptor as four scalar words (base, stride 0, records, flags).
+    __device__ __forceinline__ i32x4 desc(int it) const {
+        const uint64_t addr = reinterpret_cast<uint64_t>(base + (int64_t)it * step);
+        return i32x4{uni(int(uint32_t(addr))), uni(int(uint32_t(addr >> 32) & 0xffffu)), uni(nrec(it)),
+                     kBufferFlags};
     }
 
     // Elements of the lane's chunk j inside the inner edge (VE when not at the edge).
@@ -181,14 +222,14 @@ struct Slab {
     template <bool EDGE>
     __device__ __forceinline__ void issue(int it, int k0, int K, int o0, int dout, unsigned char* lds,
                                           int tid) const {
-        const __amdgpu_buffer_rsrc_t rs = rsrc(it);
+        const i32x4 d = desc(it);
         const bool tail = EDGE && (KC ? (k0 + BK > K) : (o0 + R > dout));
         const int lim = KC ? (K - k0) : (dout - o0);
         const int w = uni(tid >> 6);
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
             const uint32_t off = (!EDGE || keep(j, tail, lim, tid) == VE) ? voff[j] : 0x80000000u;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + (w + j * NW) * 1024), 16, int(off), 0, 0, 0);
+            dma16(d, off, lds_addr(lds + (w + j * NW) * 1024));
         }
     }
 
@@ -235,15 +276,16 @@ struct Slab {
 // ------------------------------------------------------------------ LDS fragment reads
 
 // 16 bytes = 8 k-values of one row of a K-contiguous slab, chunk q (0..7).
+template <int ROWB>
 __device__ __forceinline__ u32x4 lds_row_chunk(const unsigned char* lds, int row, int q) {
-    return *reinterpret_cast<const u32x4*>(lds + row * 128 + ((q ^ swz<2, true>(row)) << 4));
+    return *reinterpret_cast<const u32x4*>(lds + row * ROWB + ((q ^ swz<2, true, ROWB>(row)) << 4));
 }
 
 // Byte address of element (k, col) of an MN-contiguous slab with ROWB-byte rows.
 template <int EB, int ROWB>
 __device__ __forceinline__ int mn_addr(int k, int col) {
     constexpr int VE = 16 / EB;
-    return k * ROWB + (((col / VE) ^ swz<EB, false>(k)) << 4) + (col % VE) * EB;
+    return k * ROWB + (((col / VE) ^ swz<EB, false, ROWB>(k)) << 4) + (col % VE) * EB;
 }
 
 // Eight consecutive k (kb .. kb+7) of column (ob + lane % 32) of an MN-contiguous
@@ -341,7 +383,27 @@ struct Gemm {
     using SA = Slab<EB, BM, BK, AKC, THREADS>;
     using SB = Slab<EB, BN, BK, BKC, THREADS>;
     static constexpr int STAGE = SA::BYTES + SB::BYTES;
-    static_assert(2 * STAGE <= 160 * 1024, "LDS budget");
+    static constexpr int NS = C_::NS;
+    static_assert(NS >= 2 && NS * STAGE <= 160 * 1024, "LDS budget");
+    // direct-to-LDS loads each thread issues per k-iteration
+    static constexpr int LOADS = SA::PER_WAVE + SB::PER_WAVE;
+
+    // The pipeline's LDS stages: NS separate objects, so that the compiler
+    // can tell the stage being read from the stages being filled.  Named
+    // members picked by compile-time index: a pointer array indexed in a loop
+    // would be moved to LDS per thread by the compiler.
+    struct Stages {
+        unsigned char *s0, *s1, *s2, *s3, *s4;
+        template <int J>
+        __device__ __forceinline__ unsigned char* at() const {
+            static_assert(J >= 0 && J < NS, "stage index");
+            if constexpr (J == 0) return s0;
+            else if constexpr (J == 1) return s1;
+            else if constexpr (J == 2) return s2;
+            else if constexpr (J == 3) return s3;
+            else return s4;
+        }
+    };
 
     struct Acc { f32x16 v[FM][FN]; };
 
@@ -358,12 +420,12 @@ struct Gemm {
             auto load = [&](int s, int buf) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
-                    if constexpr (AKC) af[buf][i] = lds_row_chunk(As, wm * WTM + i * 32 + l32, 2 * s + g);
+                    if constexpr (AKC) af[buf][i] = lds_row_chunk<SA::ROWB>(As, wm * WTM + i * 32 + l32, 2 * s + g);
                     else af[buf][i] = lds_tr16<SA::ROWB>(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
                 }
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    if constexpr (BKC) bf[buf][j] = lds_row_chunk(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
+                    if constexpr (BKC) bf[buf][j] = lds_row_chunk<SB::ROWB>(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
                     else bf[buf][j] = lds_tr16<SB::ROWB>(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
                 }
             };
@@ -391,7 +453,7 @@ struct Gemm {
                 for (int i = 0; i < FM; ++i) {
                     const int row = wm * WTM + i * 32 + l32;
                     if constexpr (AKC) {
-                        af[i] = __builtin_bit_cast(f32x4, lds_row_chunk(As, row, 2 * c + g));
+                        af[i] = __builtin_bit_cast(f32x4, lds_row_chunk<SA::ROWB>(As, row, 2 * c + g));
                     } else {
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
@@ -402,7 +464,7 @@ struct Gemm {
                 for (int j = 0; j < FN; ++j) {
                     const int col = wn * WTN + j * 32 + l32;
                     if constexpr (BKC) {
-                        bf[j] = __builtin_bit_cast(f32x4, lds_row_chunk(Bs, col, 2 * c + g));
+                        bf[j] = __builtin_bit_cast(f32x4, lds_row_chunk<SB::ROWB>(Bs, col, 2 * c + g));
                     } else {
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
@@ -431,15 +493,15 @@ struct Gemm {
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
                     const int row = wn * WTN + j * 32 + l32;
-                    const u32x4 lo = lds_row_chunk(Bs, row, 4 * s + 2 * g);
-                    const u32x4 hi = lds_row_chunk(Bs, row, 4 * s + 2 * g + 1);
+                    const u32x4 lo = lds_row_chunk<SB::ROWB>(Bs, row, 4 * s + 2 * g);
+                    const u32x4 hi = lds_row_chunk<SB::ROWB>(Bs, row, 4 * s + 2 * g + 1);
                     bf[j] = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y), int(hi.z), int(hi.w)};
                 }
 #pragma unroll
                 for (int i = 0; i < FM; ++i) {
                     const int row = wm * WTM + i * 32 + l32;
-                    const u32x4 lo = lds_row_chunk(As, row, 4 * s + 2 * g);
-                    const u32x4 hi = lds_row_chunk(As, row, 4 * s + 2 * g + 1);
+                    const u32x4 lo = lds_row_chunk<SA::ROWB>(As, row, 4 * s + 2 * g);
+                    const u32x4 hi = lds_row_chunk<SA::ROWB>(As, row, 4 * s + 2 * g + 1);
                     const i32x8 af = i32x8{int(lo.x), int(lo.y), int(lo.z), int(lo.w), int(hi.x), int(hi.y),
                                            int(hi.z), int(hi.w)};
 #pragma unroll
@@ -469,56 +531,101 @@ struct Gemm {
         n0 = (in / gm) * BN;
     }
 
-    // One step of the MAC loop: start the loads of iteration kk+1 (if any) into
-    // stage `nx`, run the MFMAs of stage `cu`, then wait for the loads and
-    // synchronise.  Stages are distinct LDS objects, so the compiler can see
-    // that the loads in flight do not touch the stage being read.  EDGE =
-    // false: every slab up to khi lies inside the operands' inner edges.
+    // Wait until the k-slab after the current one has landed: at most `newer`
+    // iterations' loads (issued after it) may still be in flight.
+    template <int N>
+    static __device__ __forceinline__ void wait_vmem_le() {
+        static_assert(N >= 0 && N < 64, "vmcnt range");
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+    }
+    static __device__ __forceinline__ void wait_slab(int newer) {
+        if constexpr (NS >= 5)
+            if (newer >= 3) return wait_vmem_le<LOADS * 3>();
+        if constexpr (NS >= 4)
+            if (newer >= 2) return wait_vmem_le<LOADS * 2>();
+        if constexpr (NS >= 3)
+            if (newer >= 1) return wait_vmem_le<LOADS>();
+        wait_vmem();
+    }
+
+    // One step of the MAC loop, iteration it (stage `cur`): start the loads of
+    // iteration it + NS - 1 into stage `nxt` (freed by iteration it - 1, which
+    // every wave finished before the last barrier), run the MFMAs of `cur`,
+    // wait for the slab of iteration it + 1 (stage `fix`) and synchronise.
+    // EDGE = false: every slab of [kbeg, kend) lies inside the operands'
+    // inner edges.
     template <bool EDGE>
-    static __device__ __forceinline__ bool step(const Prob& a, const SA& sa, const SB& sb, int kk, int kbeg,
-                                                int khi, int m0, int n0, unsigned char* cu, unsigned char* nx,
-                                                Acc& acc, int tid) {
+    static __device__ __forceinline__ bool step(const Prob& a, const SA& sa, const SB& sb, int it, int kbeg,
+                                                int kend, int m0, int n0, unsigned char* cur, unsigned char* nxt,
+                                                unsigned char* fix, Acc& acc, int tid) {
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
-        const bool more = kk + 1 < khi;
-        if (more) {
-            sa.template issue<EDGE>(kk + 1 - kbeg, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
-            sb.template issue<EDGE>(kk + 1 - kbeg, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+        const int ahead = it + NS - 1;
+        if (ahead < kend) {
+            sa.template issue<EDGE>(ahead - kbeg, ahead * BK, a.K, m0, a.M, nxt, tid);
+            sb.template issue<EDGE>(ahead - kbeg, ahead * BK, a.K, n0, a.N, nxt + SA::BYTES, tid);
         }
-        compute(cu, cu + SA::BYTES, acc, wm, wn, lane);
+        compute(cur, cur + SA::BYTES, acc, wm, wn, lane);
+        const bool more = it + 1 < kend;
         if (more) {
-            wait_vmem();
             if constexpr (EDGE) {
-                sa.fix_edge(kk + 1 - kbeg, (kk + 1) * BK, a.K, m0, a.M, nx, tid);
-                sb.fix_edge(kk + 1 - kbeg, (kk + 1) * BK, a.K, n0, a.N, nx + SA::BYTES, tid);
+                wait_vmem();
+                sa.fix_edge(it + 1 - kbeg, (it + 1) * BK, a.K, m0, a.M, fix, tid);
+                sb.fix_edge(it + 1 - kbeg, (it + 1) * BK, a.K, n0, a.N, fix + SA::BYTES, tid);
+            } else {
+                wait_slab(min(NS - 2, kend - 2 - it));
             }
         }
-        __syncthreads();
+        step_barrier();
         return more;
     }
 
-    // Iterations [kbeg, kend) of a tile: a prologue load into stage 0, then the
-    // two-stage pipeline.
+    // Iterations kk + U (U = 0 .. NS-1) of the pipeline, each on its own
+    // stage; false once the last iteration has been consumed.
+    template <bool EDGE, int... U>
+    static __device__ __forceinline__ bool steps(const Prob& a, const SA& sa, const SB& sb, int kk, int kbeg,
+                                                 int kend, int m0, int n0, const Stages& st, Acc& acc, int tid,
+                                                 std::integer_sequence<int, U...>) {
+        return (step<EDGE>(a, sa, sb, kk + U, kbeg, kend, m0, n0, st.template at<U>(),
+                           st.template at<(U + NS - 1) % NS>(), st.template at<(U + 1) % NS>(), acc, tid) &&
+                ...);
+    }
+
+    // Prologue: slab kbeg + J into stage J (J = 0 .. NS-2).
+    template <bool EDGE, int... J>
+    static __device__ __forceinline__ void prologue(const Prob& a, const SA& sa, const SB& sb, int kbeg, int kend,
+                                                    int m0, int n0, const Stages& st, int tid,
+                                                    std::integer_sequence<int, J...>) {
+        (((kbeg + J < kend)
+              ? (sa.template issue<EDGE>(J, (kbeg + J) * BK, a.K, m0, a.M, st.template at<J>(), tid),
+                 sb.template issue<EDGE>(J, (kbeg + J) * BK, a.K, n0, a.N, st.template at<J>() + SA::BYTES, tid))
+              : void()),
+         ...);
+    }
+
+    // Iterations [kbeg, kend) of a tile: the first NS - 1 slabs are loaded
+    // up front, then each step consumes one stage and refills the stage the
+    // previous step consumed.  Iteration it uses stage (it - kbeg) mod NS.
     template <bool EDGE>
-    static __device__ __forceinline__ void loop(const Prob& a, unsigned char* s0, unsigned char* s1, int m0,
-                                                int n0, int kbeg, int kend, Acc& acc, int tid) {
+    static __device__ __forceinline__ void loop(const Prob& a, const Stages& st, int m0, int n0, int kbeg, int kend,
+                                                Acc& acc, int tid) {
         tid = opaque(tid);
         SA sa;
         SB sb;
         sa.init(a.A, a.lda, m0, a.M, kbeg, a.K, tid);
         sb.init(a.B, a.ldb, n0, a.N, kbeg, a.K, tid);
         __syncthreads();   // LDS may still be in use (previous epilogue or loop)
-        sa.template issue<EDGE>(0, kbeg * BK, a.K, m0, a.M, s0, tid);
-        sb.template issue<EDGE>(0, kbeg * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
-        wait_vmem();
+        prologue<EDGE>(a, sa, sb, kbeg, kend, m0, n0, st, tid, std::make_integer_sequence<int, NS - 1>{});
         if constexpr (EDGE) {
-            sa.fix_edge(0, kbeg * BK, a.K, m0, a.M, s0, tid);
-            sb.fix_edge(0, kbeg * BK, a.K, n0, a.N, s0 + SA::BYTES, tid);
+            wait_vmem();
+            sa.fix_edge(0, kbeg * BK, a.K, m0, a.M, st.template at<0>(), tid);
+            sb.fix_edge(0, kbeg * BK, a.K, n0, a.N, st.template at<0>() + SA::BYTES, tid);
+        } else {
+            wait_slab(min(NS - 2, kend - 1 - kbeg));
         }
-        __syncthreads();
-        for (int kk = kbeg;; kk += 2) {
-            if (!step<EDGE>(a, sa, sb, kk, kbeg, kend, m0, n0, s0, s1, acc, tid)) break;
-            if (!step<EDGE>(a, sa, sb, kk + 1, kbeg, kend, m0, n0, s1, s0, acc, tid)) break;
-        }
+        step_barrier();
+        for (int kk = kbeg;; kk += NS)
+            if (!steps<EDGE>(a, sa, sb, kk, kbeg, kend, m0, n0, st, acc, tid, std::make_integer_sequence<int, NS>{}))
+                return;
     }
 
     // MAC-loop iterations [klo, khi) of one tile into acc (zeroed first).
@@ -529,8 +636,8 @@ struct Gemm {
     // chunk would read as zero).  Every other slab is loaded with plain
     // 16-byte chunks: chunks past the M or N edge of an MN-contiguous operand
     // only feed rows or columns of the tile that are never written.
-    static __device__ __forceinline__ void mac_loop(const Prob& a, unsigned char* s0, unsigned char* s1,
-                                                    int tile, int klo, int khi, Acc& acc, int tid) {
+    static __device__ __forceinline__ void mac_loop(const Prob& a, const Stages& st, int tile, int klo, int khi,
+                                                    Acc& acc, int tid) {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -544,8 +651,8 @@ struct Gemm {
         // rows shorter than a chunk: chunks of earlier rows can reach the end too
         const bool check_all = (a_edge && a.lda * EB < 16) || (b_edge && a.ldb * EB < 16);
         const int kfast = check_all ? klo : (check_last && khi > klast) ? max(klo, klast) : khi;
-        if (kfast > klo) loop<false>(a, s0, s1, m0, n0, klo, kfast, acc, tid);
-        if (khi > kfast) loop<true>(a, s0, s1, m0, n0, kfast, khi, acc, tid);
+        if (kfast > klo) loop<false>(a, st, m0, n0, klo, kfast, acc, tid);
+        if (khi > kfast) loop<true>(a, st, m0, n0, kfast, khi, acc, tid);
     }
 
     // Partial tiles are stored in fragment order: float4 group q of thread tid
@@ -670,11 +777,12 @@ struct Gemm {
     // them).  The caller guarantees all waves have left the MAC loop's LDS.
     static constexpr int EPI_LD = WTN + 8;
     static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
-    static_assert(EPI_BYTES * (NW / 2) <= STAGE, "epilogue staging must fit in one stage");
+    static constexpr int EPI_PER_STAGE = STAGE / EPI_BYTES;    // waves staging in one LDS stage
+    static_assert(EPI_PER_STAGE >= 1 && NW <= EPI_PER_STAGE * NS, "epilogue staging must fit in the stages");
     static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
 
     static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, const Acc& acc,
-                                                  int tid, unsigned char* s0, unsigned char* s1, float* slot) {
+                                                  int tid, const Stages& sts, float* slot) {
         tid = opaque(tid);
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const int g = lane >> 5, l32 = lane & 31;
@@ -682,7 +790,13 @@ struct Gemm {
         tile_origin(a, tile, m0, n0);
         m0 += wm * WTM;
         n0 += wn * WTN;
-        float* st = reinterpret_cast<float*>((w < NW / 2 ? s0 : s1) + (w % (NW / 2)) * EPI_BYTES);
+        const int sj = w / EPI_PER_STAGE;
+        unsigned char* base = sts.template at<0>();
+        if (sj == 1) base = sts.template at<1 % NS>();
+        if constexpr (NS > 2) if (sj == 2) base = sts.template at<2 % NS>();
+        if constexpr (NS > 3) if (sj == 3) base = sts.template at<3 % NS>();
+        if constexpr (NS > 4) if (sj == 4) base = sts.template at<4 % NS>();
+        float* st = reinterpret_cast<float*>(base + (w % EPI_PER_STAGE) * EPI_BYTES);
         float s = a.alpha;
         if (!slot) {
             if (ka.scale_a) s *= *ka.scale_a;
@@ -797,7 +911,7 @@ struct Gemm {
     // Stream-K iterations, cut at tile seams, before or after its whole
     // data-parallel tiles.  Iterations and tiles are global indices; a grouped
     // launch concatenates the problems' iteration spaces.
-    static __device__ __forceinline__ void run(const KArgs& a, unsigned char* s0, unsigned char* s1) {
+    static __device__ __forceinline__ void run(const KArgs& a, const Stages& st) {
         const int tid = threadIdx.x;
         const int wg = logical_wg(blockIdx.x, a.grid, a.xcds);
         int sk_it = 0, sk_end = 0;
@@ -866,7 +980,7 @@ struct Gemm {
             }
             ++seq;
 
-            mac_loop(pr, s0, s1, tile, lo, hi, acc, tid);
+            mac_loop(pr, st, tile, lo, hi, acc, tid);
 
             if (role == ROLE_OWNER) {
                 // Every wave waits for each peer's flag itself (a wave-uniform
@@ -883,7 +997,7 @@ struct Gemm {
                                            __HIP_MEMORY_SCOPE_AGENT);
             }
             const bool partial = role == ROLE_PARTIAL;
-            finish(a, pr, tile, acc, tid, s0, s1, partial ? a.partials + (size_t)wg * (BM * BN) : nullptr);
+            finish(a, pr, tile, acc, tid, st, partial ? a.partials + (size_t)wg * (BM * BN) : nullptr);
             if (partial) {
                 wait_vmem();              // this wave's coherent partial stores have completed
                 __syncthreads();          // ... and so have every other wave's
@@ -899,9 +1013,32 @@ template <int DT, bool AKC, bool BKC, int V>
 __global__ void __launch_bounds__((kThreadsOf<DT, V>)) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<DT, V>)))
 skgemm_kernel(KArgs a) {
     using G = Gemm<DT, AKC, BKC, V>;
-    __shared__ __attribute__((aligned(1024))) unsigned char stage0[G::STAGE];
-    __shared__ __attribute__((aligned(1024))) unsigned char stage1[G::STAGE];
-    G::run(a, stage0, stage1);
+    constexpr int S = G::STAGE;
+    __shared__ __attribute__((aligned(1024))) unsigned char st0[S];
+    __shared__ __attribute__((aligned(1024))) unsigned char st1[S];
+    typename G::Stages sts{st0, st1, nullptr, nullptr, nullptr};
+    if constexpr (G::NS == 2) {
+        G::run(a, sts);
+    } else if constexpr (G::NS == 3) {
+        __shared__ __attribute__((aligned(1024))) unsigned char st2[S];
+        sts.s2 = st2;
+        G::run(a, sts);
+    } else if constexpr (G::NS == 4) {
+        __shared__ __attribute__((aligned(1024))) unsigned char st2[S];
+        __shared__ __attribute__((aligned(1024))) unsigned char st3[S];
+        sts.s2 = st2;
+        sts.s3 = st3;
+        G::run(a, sts);
+    } else {
+        static_assert(G::NS == 5, "2 to 5 pipeline stages");
+        __shared__ __attribute__((aligned(1024))) unsigned char st2[S];
+        __shared__ __attribute__((aligned(1024))) unsigned char st3[S];
+        __shared__ __attribute__((aligned(1024))) unsigned char st4[S];
+        sts.s2 = st2;
+        sts.s3 = st3;
+        sts.s4 = st4;
+        G::run(a, sts);
+    }
 }
 
 }  // namespace skg

@@ -58,8 +58,9 @@ def test_plan_argument_errors():
                          ctypes.byref(o)) == sk.ERR_CAPACITY
     # ... while one beyond the iterations is reduced to one workgroup per iteration
     o.force_g = 40
-    pl = sk.Plan(64, 64, 640, ta=sk.BF16, policy="sk", force_g=40, num_cus=256, occupancy=1)
-    assert pl.info()["g_sk"] == pl.info()["grid"] == 10
+    pl = sk.Plan(64, 64, 640, ta=sk.BF16, policy="sk", force_g=100, num_cus=256, occupancy=1)
+    info = pl.info()
+    assert info["t"] * info["ipt"] < 100 and info["g_sk"] == info["grid"] == info["t"] * info["ipt"]
     o.share = 2
     assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
                          ctypes.byref(o)) == sk.ERR_INVALID_ARG
@@ -140,7 +141,7 @@ def test_planner_forced_grid_matches_enumerator(g, share):
 
 def test_workspace_scales_with_grid_not_problem():
     sk = _lib()
-    for tile in [(256, 256, 64), (128, 128, 64)]:
+    for tile in [(256, 256, 32), (128, 128, 32)]:
         small = sk.Plan(300, 300, 4096, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1, tile=tile)
         big = sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
                       tile=tile)
@@ -148,8 +149,8 @@ def test_workspace_scales_with_grid_not_problem():
         assert small.workspace_size() == big.workspace_size()
     # one FP32 partial tile per workgroup: the small tile needs a quarter of the partial storage
     w = {t: sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
-                    tile=t).workspace_size() for t in [(256, 256, 64), (128, 128, 64)]}
-    assert w[(256, 256, 64)] - w[(128, 128, 64)] == 64 * (256 * 256 - 128 * 128) * 4
+                    tile=t).workspace_size() for t in [(256, 256, 32), (128, 128, 32)]}
+    assert w[(256, 256, 32)] - w[(128, 128, 32)] == 64 * (256 * 256 - 128 * 128) * 4
     dp = sk.Plan(3000, 3000, 4096, ta=sk.BF16, policy="dp", num_cus=256, occupancy=1)
     assert dp.workspace_size() == 0
 

@@ -23,7 +23,7 @@ TOL_16 = 1e-2
 
 POLICIES = ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"]
 # the two 16-bit tile configurations (the planner picks one per problem; tests pin each)
-TILES16 = [(256, 256, 64), (128, 128, 64)]
+TILES16 = [(256, 256, 32), (128, 128, 32)]
 
 
 def sk():
@@ -145,7 +145,7 @@ def test_trace_matches_enumerator_bf16(shape, policy, tile):
 
 # ------------------------------------------------------------------ 16-bit inputs
 
-SHAPES16 = [(1, 1, 1), (3, 5, 7), (256, 256, 64), (257, 255, 65), (300, 500, 700), (513, 1031, 129),
+SHAPES16 = [(1, 1, 1), (3, 5, 7), (256, 256, 32), (256, 256, 64), (257, 255, 65), (300, 500, 700), (513, 1031, 129),
             (1000, 130, 5), (64, 3000, 2048), (640, 768, 4099),
             # rows shorter than a 16-byte chunk, and just longer, over many k-slabs
             (300, 7, 1000), (70, 9, 1030), (7, 300, 1000),
@@ -195,7 +195,7 @@ def test_16bit_integer_exact_all_policies(dtype, tile):
 def test_layouts(layouts, c_col, dtype):
     tile = None
     if dtype == "bf16_small":
-        dtype, tile = torch.bfloat16, (128, 128, 64)
+        dtype, tile = torch.bfloat16, (128, 128, 32)
     M, N, K = 333, 517, 290
     a, b = W.normal_pair(M, N, K, seed=11)
     A = torch.from_numpy(a).to(dtype).to(dev())
@@ -217,7 +217,7 @@ def test_layouts(layouts, c_col, dtype):
 def test_alpha_beta_and_nan_c(dtype):
     tile = None
     if dtype == "bf16_small":
-        dtype, tile = torch.bfloat16, (128, 128, 64)
+        dtype, tile = torch.bfloat16, (128, 128, 32)
     M, N, K = 260, 300, 500
     a, b = W.normal_pair(M, N, K, seed=5)
     A = torch.from_numpy(a).to(dtype).to(dev())
