@@ -279,7 +279,7 @@ def main():
                                "bf16 out, row-major",
                    "n_shapes": n, "policy": "auto (DP waves + Stream-K remainder)",
                    "baseline": "same kernel and tile, policy=dp (one workgroup per tile)",
-                   "tiles": "256x256x32, or 128x128x32 where the model predicts it faster (same tile for both)",
+                   "tiles": "256x256x64, or 128x128x64 where the model predicts it faster (same tile for both)",
                    "total_gflop": round(total_flops / 1e9, 1), "parallelism": "single GPU"},
         "pct_mfma_peak": round(100.0 * value / PEAK_BF16_TFLOPS, 2),
         "dp_value": round(dp_value, 3),

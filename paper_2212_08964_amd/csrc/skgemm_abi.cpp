@@ -104,9 +104,9 @@ void model_for(int dt, int v, double* m) {
     // comparison of tile variants uses.  FP8 shares the 16-bit 256x256
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
-    if (dt == DT_F32) { m[0] = 4.6; m[1] = 5.4; m[2] = 2.09; m[3] = 1.46; m[4] = 4.2; return; }
-    if (v == 1) { m[0] = 6.4; m[1] = 2.8; m[2] = 0.59; m[3] = 1.49; m[4] = 1.04; return; }
-    m[0] = 13.3; m[1] = 5.2; m[2] = 1.36; m[3] = 2.98; m[4] = 1.89;
+    if (dt == DT_F32) { m[0] = 4.77; m[1] = 5.27; m[2] = 2.08; m[3] = 1.46; m[4] = 3.80; return; }
+    if (v == 1) { m[0] = 6.60; m[1] = 2.78; m[2] = 0.607; m[3] = 1.52; m[4] = 0.873; return; }
+    m[0] = 13.2; m[1] = 5.31; m[2] = 1.360; m[3] = 2.98; m[4] = 1.629;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -18,8 +18,8 @@ constexpr int32_t kErrTimeout = 6;
 // Tile (bm x bn, k-slab bk) and LDS pipeline stages per input type / variant.
 struct TileCfg { int bm, bn, bk, ns; };
 constexpr TileCfg kTileF32 = {128, 128, 32, 2};
-constexpr TileCfg kTile16 = {256, 256, 32, 4};    // bf16 and f16
-constexpr TileCfg kTile16S = {128, 128, 32, 4};   // bf16 and f16, small-tile variant
+constexpr TileCfg kTile16 = {256, 256, 64, 2};    // bf16 and f16
+constexpr TileCfg kTile16S = {128, 128, 64, 2};   // bf16 and f16, small-tile variant
 constexpr TileCfg kTileF8 = {256, 256, 128, 2};
 
 // One problem of a grouped launch (device table entry, 128 bytes).  Shapes are

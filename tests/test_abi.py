@@ -141,7 +141,7 @@ def test_planner_forced_grid_matches_enumerator(g, share):
 
 def test_workspace_scales_with_grid_not_problem():
     sk = _lib()
-    for tile in [(256, 256, 32), (128, 128, 32)]:
+    for tile in [(256, 256, 64), (128, 128, 64)]:
         small = sk.Plan(300, 300, 4096, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1, tile=tile)
         big = sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
                       tile=tile)
@@ -149,8 +149,8 @@ def test_workspace_scales_with_grid_not_problem():
         assert small.workspace_size() == big.workspace_size()
     # one FP32 partial tile per workgroup: the small tile needs a quarter of the partial storage
     w = {t: sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
-                    tile=t).workspace_size() for t in [(256, 256, 32), (128, 128, 32)]}
-    assert w[(256, 256, 32)] - w[(128, 128, 32)] == 64 * (256 * 256 - 128 * 128) * 4
+                    tile=t).workspace_size() for t in [(256, 256, 64), (128, 128, 64)]}
+    assert w[(256, 256, 64)] - w[(128, 128, 64)] == 64 * (256 * 256 - 128 * 128) * 4
     dp = sk.Plan(3000, 3000, 4096, ta=sk.BF16, policy="dp", num_cus=256, occupancy=1)
     assert dp.workspace_size() == 0
 

@@ -23,7 +23,7 @@ TOL_16 = 1e-2
 
 POLICIES = ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"]
 # the two 16-bit tile configurations (the planner picks one per problem; tests pin each)
-TILES16 = [(256, 256, 32), (128, 128, 32)]
+TILES16 = [(256, 256, 64), (128, 128, 64)]
 
 
 def sk():
@@ -195,7 +195,7 @@ def test_16bit_integer_exact_all_policies(dtype, tile):
 def test_layouts(layouts, c_col, dtype):
     tile = None
     if dtype == "bf16_small":
-        dtype, tile = torch.bfloat16, (128, 128, 32)
+        dtype, tile = torch.bfloat16, (128, 128, 64)
     M, N, K = 333, 517, 290
     a, b = W.normal_pair(M, N, K, seed=11)
     A = torch.from_numpy(a).to(dtype).to(dev())
@@ -217,7 +217,7 @@ def test_layouts(layouts, c_col, dtype):
 def test_alpha_beta_and_nan_c(dtype):
     tile = None
     if dtype == "bf16_small":
-        dtype, tile = torch.bfloat16, (128, 128, 32)
+        dtype, tile = torch.bfloat16, (128, 128, 64)
     M, N, K = 260, 300, 500
     a, b = W.normal_pair(M, N, K, seed=5)
     A = torch.from_numpy(a).to(dtype).to(dev())

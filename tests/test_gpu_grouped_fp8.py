@@ -46,7 +46,7 @@ def _problems(seed, Ms, N, K, dtype=torch.bfloat16):
 
 
 @pytest.mark.parametrize("policy", ["auto", "sk", "dp", "2tile_sk_dp", "dp_1tile_sk"])
-@pytest.mark.parametrize("tile", [None, (256, 256, 32), (128, 128, 32)])
+@pytest.mark.parametrize("tile", [None, (256, 256, 64), (128, 128, 64)])
 def test_grouped_zipf_parity(policy, tile):
     Ms = W.zipf_ms(24, lo=16, hi=1024, seed=1)
     As, Bs = _problems(2, Ms, 1024, 512)
@@ -72,7 +72,7 @@ def test_grouped_ragged_mixed_shapes_bf16_out():
             assert og.rel_frobenius(to_f64(C), ref) <= 1e-2
 
 
-@pytest.mark.parametrize("tile", [(256, 256, 32), (128, 128, 32)])
+@pytest.mark.parametrize("tile", [(256, 256, 64), (128, 128, 64)])
 def test_grouped_integer_exact_forced_grids(tile):
     Ms = [37, 300, 16, 520]
     g = W.rng(4)
@@ -87,7 +87,7 @@ def test_grouped_integer_exact_forced_grids(tile):
 
 
 @pytest.mark.parametrize("policy", ["auto", "sk", "2tile_sk_dp"])
-@pytest.mark.parametrize("tile", [None, (128, 128, 32)])
+@pytest.mark.parametrize("tile", [None, (128, 128, 64)])
 def test_grouped_trace_matches_enumerator(policy, tile):
     Ms = W.zipf_ms(64, seed=0)
     shapes = [(m, 4096, 2048) for m in Ms]
