@@ -35,6 +35,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "TFLOP/s & % MFMA peak, Stream-K vs data-parallel tiles, bf16 shape sweep"
+
+# HBM bytes per launch of the sweep, from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE,
+# each scaled by its reading for a plain 256 MiB copy); valid only for the kernel sources
+# they were taken on, identified by the hash below (see profiles/skgemm_bf16_sweep_hbm_traffic.md).
+TRAFFIC_BYTES_PER_LAUNCH = 63.04e6
+TRAFFIC_SOURCES_SHA256 = "1d37a0dc78d82111"
+
+
+def kernel_sources_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2212_08964_amd", "csrc", "*"))):
+        if f.endswith((".hpp", ".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
 PEAK_BF16_TFLOPS = 2516.6      # MI355X dense BF16 MFMA, 256 CU x 4096 flop/clk x 2.4 GHz
 HBM_GBS = 8000.0
 
@@ -289,7 +307,10 @@ def main():
         "plan_us_per_gemm": round(plan_us, 2),
         "setup_s": round(plan_s, 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_BF16_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                     "traffic": TRAFFIC_BYTES_PER_LAUNCH if kernel_sources_hash() == TRAFFIC_SOURCES_SHA256 else None,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": round(sum(c.bytes for c in cases) / n),
                      "kernel": "skgemm_kernel<BF16, A K-contiguous, B N-contiguous>",
                      "avg_launch_us": round(avg_launch_us, 3),
                      "flops_per_launch": round(total_flops / n, 1)},
