@@ -104,9 +104,9 @@ void model_for(int dt, int v, double* m) {
     // comparison of tile variants uses.  FP8 shares the 16-bit 256x256
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
-    if (dt == DT_F32) { m[0] = 4.77; m[1] = 5.27; m[2] = 2.08; m[3] = 1.46; m[4] = 3.80; return; }
-    if (v == 1) { m[0] = 6.60; m[1] = 2.78; m[2] = 0.607; m[3] = 1.52; m[4] = 0.873; return; }
-    m[0] = 13.2; m[1] = 5.31; m[2] = 1.360; m[3] = 2.98; m[4] = 1.629;
+    if (dt == DT_F32) { m[0] = 4.21; m[1] = 5.37; m[2] = 2.12; m[3] = 1.46; m[4] = 3.94; return; }
+    if (v == 1) { m[0] = 5.29; m[1] = 2.95; m[2] = 0.610; m[3] = 1.48; m[4] = 0.920; return; }
+    m[0] = 9.19; m[1] = 5.22; m[2] = 1.356; m[3] = 2.99; m[4] = 1.744;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -323,17 +323,26 @@ __device__ __forceinline__ f32x16 mfma16(const u32x4& a, const u32x4& b, const f
 
 // ------------------------------------------------------------------ output conversion
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);   // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
-}
-
+// Round to nearest even with the hardware conversions (v_cvt_pk_bf16_f32 for
+// bfloat16; NaN stays NaN).  A software rounding with a NaN branch made every
+// element a divergent branch in the epilogue.
 template <int OUT>
 __device__ __forceinline__ uint16_t f32_to_half(float x) {
-    if constexpr (OUT == DT_BF16) return f32_to_bf16_rne(x);
+    if constexpr (OUT == DT_BF16) return __builtin_bit_cast(uint16_t, __bf16(x));
     else return __builtin_bit_cast(uint16_t, _Float16(x));
+}
+
+// Two values, packed low then high.
+template <int OUT>
+__device__ __forceinline__ uint32_t f32x2_to_half2(float x0, float x1) {
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    if constexpr (OUT == DT_BF16) {
+        typedef __bf16 h2_t __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x0, x1}, h2_t));
+    } else {
+        typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{x0, x1}, h2_t));
+    }
 }
 
 template <int OUT>
@@ -342,16 +351,25 @@ __device__ __forceinline__ float half_to_f32(uint16_t h) {
     else return float(__builtin_bit_cast(_Float16, h));
 }
 
+// C is reached through global-address-space pointers: generic (flat) memory
+// instructions also count against the LDS wait counter, so every LDS read of
+// the epilogue would wait for the previous band's C stores to complete.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> global(void* p) { return (gptr<T>)p; }
+
 template <int OUT>
-__device__ __forceinline__ float load_c1(const void* C, int64_t off) {
-    if constexpr (OUT == DT_F32) return reinterpret_cast<const float*>(C)[off];
-    else return half_to_f32<OUT>(reinterpret_cast<const uint16_t*>(C)[off]);
+__device__ __forceinline__ float load_c1(void* C, int64_t off) {
+    if constexpr (OUT == DT_F32) return global<float>(C)[off];
+    else return half_to_f32<OUT>(global<uint16_t>(C)[off]);
 }
 
 template <int OUT>
 __device__ __forceinline__ void store_c1(void* C, int64_t off, float v) {
-    if constexpr (OUT == DT_F32) reinterpret_cast<float*>(C)[off] = v;
-    else reinterpret_cast<uint16_t*>(C)[off] = f32_to_half<OUT>(v);
+    if constexpr (OUT == DT_F32) global<float>(C)[off] = v;
+    else global<uint16_t>(C)[off] = f32_to_half<OUT>(v);
 }
 
 // ------------------------------------------------------------------ the kernel
@@ -725,7 +743,7 @@ struct Gemm {
                 const int64_t off = (int64_t)row * a.ldc + col;
                 if (ncol == 8) {
                     if constexpr (OUT == DT_F32) {
-                        f32x4* cp = reinterpret_cast<f32x4*>(reinterpret_cast<float*>(a.C) + off);
+                        gptr<f32x4> cp = (gptr<f32x4>)(global<float>(a.C) + off);
                         f32x4 o0 = {v[0], v[1], v[2], v[3]}, o1 = {v[4], v[5], v[6], v[7]};
                         o0 *= s;
                         o1 *= s;
@@ -736,7 +754,7 @@ struct Gemm {
                         cp[0] = o0;
                         cp[1] = o1;
                     } else {
-                        u32x4* cp = reinterpret_cast<u32x4*>(reinterpret_cast<uint16_t*>(a.C) + off);
+                        gptr<u32x4> cp = (gptr<u32x4>)(global<uint16_t>(a.C) + off);
                         float cin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                         if (a.beta != 0.0f) {
                             const u32x4 cv = *cp;
@@ -749,7 +767,7 @@ struct Gemm {
                         for (int e = 0; e < 4; ++e) {
                             const float x0 = s * v[2 * e] + a.beta * cin[2 * e];
                             const float x1 = s * v[2 * e + 1] + a.beta * cin[2 * e + 1];
-                            o[e] = uint32_t(f32_to_half<OUT>(x0)) | (uint32_t(f32_to_half<OUT>(x1)) << 16);
+                            o[e] = f32x2_to_half2<OUT>(x0, x1);
                         }
                         *cp = o;
                     }
