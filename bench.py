@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many Stream-K steps (for profiler runs) and print timings")
+    ap.add_argument("--suite", action="store_true",
+                    help="instead of the sweep: time the other workloads (FP32 plain GEMM, precision ladder, "
+                         "grouped launch under a graph, autograd forward+backward), one JSON line each")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="with --profile-steps: then one plain device copy of this many MiB, the reference "
                          "that scales the HBM byte counters")
@@ -151,11 +154,156 @@ def cpu_baseline(shapes, budget_s):
                       f"{flops / 1e9:.1f} GFLOP in {secs:.1f} s, FP64 triple loop with OpenMP over rows"}
 
 
+PEAKS = {"f32": 157.3, "bf16": PEAK_BF16_TFLOPS, "f16": PEAK_BF16_TFLOPS, "fp8": 5033.2}
+
+
+def _best_us(fn, reps, rounds=3):
+    """Best-of-rounds mean launch time (us) of `reps` back-to-back calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(rounds):
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e3 / reps)
+    return best
+
+
+def suite(args):
+    """The non-sweep workloads, timed on one GPU (inputs resident, plans built beforehand)."""
+    import torch
+    import workloads as W
+    from paper_2212_08964_amd import skgemm as sk
+    from paper_2212_08964_amd import autotune
+    from paper_2212_08964_amd.autograd import skgemm_matmul
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    def reps_for(flops):
+        return int(min(200, max(5, 2e12 / max(flops, 1.0))))
+
+    # FP32 plain GEMM, 384 x 384 x 1024 (nine 128 x 128 tiles)
+    a, b = W.plain_f32(seed=0)
+    A = torch.from_numpy(a).to(dev)
+    B = torch.from_numpy(b).to(dev)
+    C = torch.empty((384, 384), device=dev)
+    fl = 2.0 * 384 * 384 * 1024
+    row = {"workload": "fp32 384x384x1024", "dtype": "f32"}
+    for pol in ("auto", "dp"):
+        us = _best_us(lambda: sk.matmul(A, B, out=C, policy=pol), 200)
+        row[pol + "_us"] = round(us, 2)
+        row[pol + "_tflops"] = round(fl / us / 1e6, 3)
+    info = sk.get_plan(384, 384, 1024, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.F32, sk.F32).info()
+    row["auto_plan"] = {k: info[k] for k in ("policy_name", "g_sk", "BM", "BN", "BK")}
+    emit(row)
+
+    # precision ladder: bf16, fp16 and fp8 (per-tensor scales) at M=N=K in {1024, 4096, 8192}
+    # and the skinny 128 x 8192 x 8192
+    for (M, N, K) in [(1024, 1024, 1024), (4096, 4096, 4096), (8192, 8192, 8192), (128, 8192, 8192)]:
+        A32 = torch.randn((M, K), generator=gen, device=dev)
+        B32 = torch.randn((K, N), generator=gen, device=dev)
+        fl = 2.0 * M * N * K
+        for name in ("bf16", "f16", "fp8"):
+            if name == "fp8":
+                qa, sa = sk.quantize_e4m3(A32, "row")
+                qb, sb = sk.quantize_e4m3(B32, "col")
+                C = torch.empty((M, N), device=dev, dtype=torch.float32)
+                ops = {pol: (lambda pol=pol: sk.matmul(qa, qb, out=C, scale_a=sa, scale_b=sb, policy=pol))
+                       for pol in ("auto", "dp")}
+                in_bytes, out_bytes = M * K + K * N, 4 * M * N
+            else:
+                dt = torch.bfloat16 if name == "bf16" else torch.float16
+                Ai, Bi = A32.to(dt), B32.to(dt)
+                C = torch.empty((M, N), device=dev, dtype=dt)
+                ops = {pol: (lambda pol=pol: sk.matmul(Ai, Bi, out=C, policy=pol)) for pol in ("auto", "dp")}
+                in_bytes, out_bytes = 2 * (M * K + K * N), 2 * M * N
+            row = {"workload": f"{name} {M}x{N}x{K}", "dtype": name}
+            for pol, fn in ops.items():
+                us = _best_us(fn, reps_for(fl))
+                tf = fl / us / 1e6
+                row[pol + "_us"] = round(us, 2)
+                row[pol + "_tflops"] = round(tf, 1)
+                row[pol + "_pct_peak"] = round(100 * tf / PEAKS[name], 2)
+                row[pol + "_hbm_gbs"] = round((in_bytes + out_bytes) / us / 1e3, 1)
+            if name == "fp8":
+                us_q = _best_us(lambda: (sk.quantize_e4m3(A32, "row", out=qa, scale=sa),
+                                         sk.quantize_e4m3(B32, "col", out=qb, scale=sb)), 20)
+                qbytes = 4 * (M * K + K * N) * 2 + (M * K + K * N)   # two FP32 passes (absmax, cast) + fp8 out
+                row["quantize_us"] = round(us_q, 2)
+                row["quantize_hbm_gbs"] = round(qbytes / us_q / 1e3, 1)
+            if name == "bf16":
+                # context: the vendor library GEMM (hipBLASLt through torch) on the same operands
+                us_t = _best_us(lambda: torch.matmul(Ai, Bi, out=C), reps_for(fl))
+                row["torch_matmul_us"] = round(us_t, 2)
+                row["torch_matmul_tflops"] = round(fl / us_t / 1e6, 1)
+            emit(row)
+            del C
+        del A32, B32
+        torch.cuda.empty_cache()
+
+    # grouped: 64 problems, N=4096, K=2048, M ~ Zipf(1.2) on [16, 4096], one launch under a graph
+    Ms = W.zipf_ms(64, seed=0)
+    N, K = 4096, 2048
+    As = [torch.randn((m, K), generator=gen, device=dev).to(torch.bfloat16) for m in Ms]
+    Bs = [torch.randn((K, N), generator=gen, device=dev).to(torch.bfloat16) for _ in Ms]
+    Cs = [torch.empty((m, N), device=dev, dtype=torch.bfloat16) for m in Ms]
+    fl = sum(2.0 * m * N * K for m in Ms)
+    best, tried = autotune.tune_grouped(As, Bs, Cs, reps=10)
+    _, table = sk.grouped_matmul(As, Bs, Cs, **best)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        sk.grouped_matmul(As, Bs, Cs, table=table, **best)
+    torch.cuda.synchronize()
+    us_graph = _best_us(graph.replay, 20)
+    _, tdp = sk.grouped_matmul(As, Bs, Cs, policy="dp")
+    us_gdp = _best_us(lambda: sk.grouped_matmul(As, Bs, Cs, table=tdp, policy="dp"), 20)
+    us_seq = _best_us(lambda: [sk.matmul(a_, b_, out=c_, policy="dp") for a_, b_, c_ in zip(As, Bs, Cs)], 5)
+    emit({"workload": "grouped bf16: 64 problems N=4096 K=2048 M~Zipf(1.2) on [16,4096]", "dtype": "bf16",
+          "gflop": round(fl / 1e9, 1), "autotuned": best,
+          "candidates_us": {k: round(v, 1) for k, v in tried.items()},
+          "graph_replay_us": round(us_graph, 1), "graph_replay_tflops": round(fl / us_graph / 1e6, 1),
+          "grouped_dp_us": round(us_gdp, 1), "grouped_dp_tflops": round(fl / us_gdp / 1e6, 1),
+          "sequential_dp_us": round(us_seq, 1), "sequential_dp_tflops": round(fl / us_seq / 1e6, 1)})
+    del As, Bs, Cs
+    torch.cuda.empty_cache()
+
+    # autograd forward + backward (dA = dC B^T, dB = A^T dC) in bf16
+    for (M, N, K) in [(2048, 2048, 8192), (256, 4096, 4096)]:
+        A = torch.randn((M, K), generator=gen, device=dev).to(torch.bfloat16).requires_grad_()
+        B = torch.randn((K, N), generator=gen, device=dev).to(torch.bfloat16).requires_grad_()
+        dC = torch.randn((M, N), generator=gen, device=dev).to(torch.bfloat16)
+        fl = 3 * 2.0 * M * N * K
+
+        def step():
+            A.grad = B.grad = None
+            skgemm_matmul(A, B).backward(dC)
+        us = _best_us(step, 20)
+        emit({"workload": f"autograd bf16 {M}x{N}x{K} forward+backward", "dtype": "bf16",
+              "ms": round(us / 1e3, 4), "tflops": round(fl / us / 1e6, 1),
+              "pct_peak": round(100 * fl / us / 1e6 / PEAK_BF16_TFLOPS, 2)})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (single-GPU build); --gpus must be 1"}))
         sys.exit(2)
+    if args.suite:
+        suite(args)
+        return
     import numpy as np
     import torch
     import workloads as W

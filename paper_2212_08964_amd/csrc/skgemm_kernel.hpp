@@ -691,36 +691,37 @@ struct Gemm {
         return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, BM * BN * 4, kBufferFlags);
     }
 
-    // Loads go in groups of two accumulator blocks (32 registers in flight):
-    // issuing all of them before the adds would need a second accumulator's
-    // worth of registers and push the accumulators out to scratch memory.
+    // Loads go in groups of up to four accumulator blocks (64 registers in
+    // flight): one round trip per group, and no more than a second half
+    // accumulator's worth of registers (all of them at once would push the
+    // accumulators of the large tile out to scratch memory).
+    static constexpr int PGROUP = FM * FN < 4 ? FM * FN : 4;
     static __device__ __forceinline__ void add_partial(const float* slot, Acc& acc, int tid) {
         tid = opaque(tid);
         const __amdgpu_buffer_rsrc_t rs = slot_rsrc(const_cast<float*>(slot));
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
+        for (int g0 = 0; g0 < FM * FN; g0 += PGROUP) {
+            f32x4 v[PGROUP][4];
 #pragma unroll
-            for (int jg = 0; jg < FN; jg += 2) {
-                f32x4 v[2][4];
+            for (int u = 0; u < PGROUP; ++u)
 #pragma unroll
-                for (int j = jg; j < jg + 2 && j < FN; ++j)
+                for (int r = 0; r < 4; ++r) {
+                    const int q = (g0 + u) * 4 + r;
+                    v[u][r] = __builtin_bit_cast(
+                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent));
+                }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int q = (i * FN + j) * 4 + r;
-                        v[j - jg][r] = __builtin_bit_cast(
-                            f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent));
-                    }
+            for (int u = 0; u < PGROUP; ++u) {
+                const int i = (g0 + u) / FN, j = (g0 + u) % FN;
 #pragma unroll
-                for (int j = jg; j < jg + 2 && j < FN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        acc.v[i][j][4 * r] += v[j - jg][r].x;
-                        acc.v[i][j][4 * r + 1] += v[j - jg][r].y;
-                        acc.v[i][j][4 * r + 2] += v[j - jg][r].z;
-                        acc.v[i][j][4 * r + 3] += v[j - jg][r].w;
-                    }
-                __builtin_amdgcn_sched_barrier(0);
+                for (int r = 0; r < 4; ++r) {
+                    acc.v[i][j][4 * r] += v[u][r].x;
+                    acc.v[i][j][4 * r + 1] += v[u][r].y;
+                    acc.v[i][j][4 * r + 2] += v[u][r].z;
+                    acc.v[i][j][4 * r + 3] += v[u][r].w;
+                }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
