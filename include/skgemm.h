@@ -39,7 +39,8 @@ typedef enum {
     SKGEMM_ERR_INVALID_ARG = 1,   /* bad shape, leading dimension, pointer or enum */
     SKGEMM_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
     SKGEMM_ERR_WORKSPACE = 3,     /* workspace missing, misaligned or too small */
-    SKGEMM_ERR_CAPACITY = 4,      /* grid larger than the co-resident workgroups */
+    SKGEMM_ERR_CAPACITY = 4,      /* grid larger than the co-resident workgroups
+                                     (or than 4096 Stream-K workgroups) */
     SKGEMM_ERR_HIP = 5,           /* a HIP runtime call failed */
     SKGEMM_ERR_TIMEOUT = 6        /* a bounded fix-up wait expired on the device */
 } skgemm_status_t;
@@ -95,9 +96,22 @@ typedef struct {
                                      is cut into s parts at the same k-offsets;
                                      SKGEMM_SHARE_LEADING gives the T mod g extra
                                      iterations to the first workgroups */
+    int32_t fixup;                /* SKGEMM_FIXUP_AUTO (default): when every Stream-K
+                                     tile is cut into s >= 2 equal shares that start
+                                     and end on the tile (g = s * tiles, s divides
+                                     the iterations per tile, one GEMM), the first
+                                     two workgroups of a tile each reduce and write
+                                     half of its 32-row bands and every other share
+                                     is stored for them; otherwise, and always with
+                                     SKGEMM_FIXUP_OWNER, the workgroup holding the
+                                     tile's first iteration reduces and writes the
+                                     whole tile (the paper's fix-up).  Both add the
+                                     shares in the same order: the results are
+                                     bitwise identical. */
 } skgemm_options_t;
 
 typedef enum { SKGEMM_SHARE_PROPORTIONAL = 0, SKGEMM_SHARE_LEADING = 1 } skgemm_share_t;
+typedef enum { SKGEMM_FIXUP_AUTO = 0, SKGEMM_FIXUP_OWNER = 1 } skgemm_fixup_t;
 
 /* Fills *opt with the defaults. */
 void skgemm_default_options(skgemm_options_t* opt);
@@ -115,11 +129,13 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
                             const skgemm_options_t* opt);
 
 /* Bytes of device workspace a run of this plan needs (0 when the plan has no
- * Stream-K region).  The workspace holds the FP32 partial tiles, one per
- * Stream-K workgroup, their ready flags and an error word.  It must be
- * 256-byte aligned and zero-filled once after allocation; the kernel leaves
- * its flags at zero again on success, so it can be reused without clearing.
- * After SKGEMM_ERR_TIMEOUT it must be zero-filled again. */
+ * Stream-K region).  The workspace holds an error word, the ready flags (a
+ * fixed area of 512 KiB for up to 4096 Stream-K workgroups) and the FP32
+ * partial tiles, one per Stream-K workgroup.  It must be 256-byte aligned and
+ * zero-filled once after allocation; the kernel leaves its flags at zero again
+ * on success, so it can be reused without clearing, also by other plans (the
+ * flag area is at the same place for every plan).  After SKGEMM_ERR_TIMEOUT it
+ * must be zero-filled again. */
 skgemm_status_t skgemm_workspace_size(skgemm_plan_t plan, size_t* bytes);
 
 /* Run a planned GEMM.  lda/ldb/ldc follow each operand's layout and must be
@@ -158,8 +174,9 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
  *   15 sk_first (0/1), 16 p (co-resident workgroups), 17 hybrid_min_waves,
  *   18 A K-contiguous (0/1), 19 B K-contiguous (0/1), 20 G (problems of a
  *   grouped plan, 0 for one GEMM; fields 0-2, 7, 8 and 10 are 0 then and
- *   field 9 is the total tile count), 21 share (skgemm_share_t).
- * n is the capacity of info; up to 22 values are written. */
+ *   field 9 is the total tile count), 21 share (skgemm_share_t), 22 shares per
+ * tile under the split fix-up (0 = owner fix-up).
+ * n is the capacity of info; up to 23 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)

@@ -42,6 +42,8 @@ struct skgemm_plan_s {
     int p, hybrid_min_waves;
     int raster, xcds;  // tile raster group rows; XCD count for the workgroup permutation
     bool share_prop;   // proportional (else leading) even share
+    bool fixup_owner;  // the owner alone reduces every split tile
+    int coop_s;        // >= 2: split fix-up over tiles cut into coop_s one-segment shares
     int sk_q, sk_r;
     double model[5];   // a, b, c, d of the grid-size model; e: c with every workgroup slot busy
     // workspace layout
@@ -105,8 +107,8 @@ void model_for(int dt, int v, double* m) {
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
     if (dt == DT_F32) { m[0] = 4.21; m[1] = 5.37; m[2] = 2.12; m[3] = 1.46; m[4] = 3.94; return; }
-    if (v == 1) { m[0] = 5.29; m[1] = 2.95; m[2] = 0.610; m[3] = 1.48; m[4] = 0.920; return; }
-    m[0] = 9.19; m[1] = 5.22; m[2] = 1.356; m[3] = 2.99; m[4] = 1.744;
+    if (v == 1) { m[0] = 5.13; m[1] = 1.98; m[2] = 0.601; m[3] = 0.789; m[4] = 0.950; return; }
+    m[0] = 9.64; m[1] = 2.52; m[2] = 1.352; m[3] = 1.54; m[4] = 1.723;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -381,13 +383,21 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     else if (pl->g_sk) pl->grid = std::max(pl->grid, pl->g_sk);
     // Owners wait on workgroups with higher indices, so every Stream-K
     // workgroup must be resident at once.
-    if (pl->g_sk > pl->p) return SKGEMM_ERR_CAPACITY;
+    if (pl->g_sk > pl->p || pl->g_sk > kMaxFlagLines) return SKGEMM_ERR_CAPACITY;
     if (pl->g_sk) {
         pl->sk_q = int(pl->sk_iters / pl->g_sk);
         pl->sk_r = int(pl->sk_iters % pl->g_sk);
     }
+    // Split fix-up: a single GEMM whose Stream-K tiles are each cut into s
+    // equal shares that start and end on the tile (g = s * tiles, s | ipt), so
+    // each Stream-K workgroup performs exactly one segment.
+    pl->coop_s = 0;
+    if (!pl->fixup_owner && pl->pM.size() == 1 && pl->g_sk && pl->sk_tiles && pl->g_sk % pl->sk_tiles == 0) {
+        const int s = pl->g_sk / pl->sk_tiles;
+        if (s >= 2 && pl->pipt[0] % s == 0) pl->coop_s = s;
+    }
     pl->flags_off = kWsHeaderBytes;
-    pl->partials_off = (kWsHeaderBytes + size_t(pl->g_sk) * kFlagStrideInts * 4 + 255) & ~size_t(255);
+    pl->partials_off = (kWsHeaderBytes + size_t(kMaxFlagLines) * kFlagStrideInts * 4 + 255) & ~size_t(255);
     pl->ws_bytes = pl->g_sk ? pl->partials_off + size_t(pl->g_sk) * pl->BM * pl->BN * 4 : 0;
     int mx = 0;
     for (int x = 0; x < pl->grid; ++x) mx = std::max(mx, walk(*pl, x, [](int, int, int, int, int, int, int) {}));
@@ -423,6 +433,8 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     if (!kernel_exists(pl->dtype, pl->akc, pl->bkc, 0)) return SKGEMM_ERR_UNSUPPORTED;
     pl->hybrid_min_waves = o.hybrid_min_waves;
     if (o.share != SKGEMM_SHARE_PROPORTIONAL && o.share != SKGEMM_SHARE_LEADING) return SKGEMM_ERR_INVALID_ARG;
+    if (o.fixup != SKGEMM_FIXUP_AUTO && o.fixup != SKGEMM_FIXUP_OWNER) return SKGEMM_ERR_INVALID_ARG;
+    pl->fixup_owner = o.fixup == SKGEMM_FIXUP_OWNER;
     pl->share_prop = o.share == SKGEMM_SHARE_PROPORTIONAL;
     pl->raster = o.raster_rows ? o.raster_rows : kDefaultRaster;
     pl->xcds = o.xcds ? o.xcds : kDefaultXcds;
@@ -633,6 +645,7 @@ static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspac
     a->sk_prop = pl->share_prop ? 1 : 0;
     a->raster = pl->raster;
     a->xcds = pl->xcds;
+    a->coop_s = pl->coop_s;
 }
 
 static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
@@ -742,11 +755,11 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[22] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[23] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
                            pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
-                           pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING};
-    for (int i = 0; i < n && i < 22; ++i) info[i] = v[i];
+                           pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s};
+    for (int i = 0; i < n && i < 23; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 

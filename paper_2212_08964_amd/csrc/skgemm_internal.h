@@ -11,6 +11,10 @@ enum Role : int32_t { ROLE_FULL = 0, ROLE_PARTIAL = 1, ROLE_OWNER = 2 };
 
 constexpr int kFlagStrideInts = 32;        // one 128-byte line per ready flag
 constexpr size_t kWsHeaderBytes = 256;     // error word lives at offset 0
+// The flag area has a fixed place and size (ahead of the partial tiles), so a
+// workspace can serve plans with different grids one after another: a
+// plan's partial tiles never overlap another plan's flags.
+constexpr int kMaxFlagLines = 4096;        // Stream-K workgroups a plan may have
 constexpr int kTraceFields = 8;
 constexpr int32_t kErrTimeout = 6;
 
@@ -65,6 +69,8 @@ struct KArgs {
     int32_t sk_prop;           // proportional even share (else leading: first sk_r get sk_q + 1)
     int32_t raster;            // tile rows per raster group (1 = row-major)
     int32_t xcds;              // XCDs the workgroups are spread over (1 = no remapping)
+    int32_t coop_s;            // >= 2: every Stream-K tile has coop_s equal one-segment shares and the
+                               // split fix-up reduces it (0 = owner fix-up)
 };
 
 // Tile variants: 0 = the type's default tile, 1 = the small 16-bit tile.

@@ -691,40 +691,6 @@ struct Gemm {
         return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, BM * BN * 4, kBufferFlags);
     }
 
-    // Loads go in groups of up to four accumulator blocks (64 registers in
-    // flight): one round trip per group, and no more than a second half
-    // accumulator's worth of registers (all of them at once would push the
-    // accumulators of the large tile out to scratch memory).
-    static constexpr int PGROUP = FM * FN < 4 ? FM * FN : 4;
-    static __device__ __forceinline__ void add_partial(const float* slot, Acc& acc, int tid) {
-        tid = opaque(tid);
-        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(const_cast<float*>(slot));
-#pragma unroll
-        for (int g0 = 0; g0 < FM * FN; g0 += PGROUP) {
-            f32x4 v[PGROUP][4];
-#pragma unroll
-            for (int u = 0; u < PGROUP; ++u)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = (g0 + u) * 4 + r;
-                    v[u][r] = __builtin_bit_cast(
-                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent));
-                }
-#pragma unroll
-            for (int u = 0; u < PGROUP; ++u) {
-                const int i = (g0 + u) / FN, j = (g0 + u) % FN;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    acc.v[i][j][4 * r] += v[u][r].x;
-                    acc.v[i][j][4 * r + 1] += v[u][r].y;
-                    acc.v[i][j][4 * r + 2] += v[u][r].z;
-                    acc.v[i][j][4 * r + 3] += v[u][r].w;
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-
     // Output of one 32-row band of the wave's block, staged in `st` (FP32,
     // rows of EPI_LD floats): each lane converts eight consecutive columns of
     // one row and writes them with one store, predicated at the M and N edges.
@@ -786,25 +752,74 @@ struct Gemm {
         }
     }
 
-    // The accumulators leave the registers band by band (FM bands of 32 rows
-    // per wave), either as a partial tile (coherent stores to `slot`, in the
-    // fragment order add_partial reads) or through the epilogue: C = alpha *
-    // s_A * s_B * acc + beta * C, each band staged in the wave's own LDS area
-    // (waves of the first half use stage 0, the others stage 1).  One band
-    // loop serves both, so the accumulators have a single way out of the
-    // registers (two separate consumers made the register allocator spill
+    // How a segment's accumulators leave the registers: 32-row bands (FM per
+    // wave) go out in two passes.  Pass 1 stores the bands in `store_mask`
+    // into this workgroup's slot (coherent stores, fragment order: float4
+    // group q of thread tid at slot[(q * THREADS + tid) * 4]) and raises the
+    // ready-flag words in `flag_words` (bit f: word f of this workgroup's flag
+    // line).  Pass 2 reduces and writes the bands in `fin_mask`: it waits for
+    // word `fw` of the flags of peers lo .. hi (this workgroup excluded), adds
+    // their slots' copy of the band in ascending peer order and writes the band
+    // through the epilogue, C = alpha * s_A * s_B * acc + beta * C, staged in
+    // the wave's own LDS area; then it clears the words it waited on.
+    //
+    //   partial share (owner fix-up):  store all bands, raise word 0
+    //   owner (owner fix-up):          reduce all bands, peers wg+1 .. last, word 0
+    //   whole tile:                    write all bands
+    //   split fix-up, contributor c:   store the bands not reduced by c; c = 0
+    //                                  and c = 1 reduce bands i with i mod 2 = c
+    //                                  over the other contributors, word c
+    //
+    // One routine serves every role, so the accumulators have a single way out
+    // of the registers (separate consumers made the register allocator spill
     // them).  The caller guarantees all waves have left the MAC loop's LDS.
+    struct Exit {
+        int store_mask, flag_words, fin_mask, fw, lo, hi;
+    };
     static constexpr int EPI_LD = WTN + 8;
     static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
     static constexpr int EPI_PER_STAGE = STAGE / EPI_BYTES;    // waves staging in one LDS stage
     static_assert(EPI_PER_STAGE >= 1 && NW <= EPI_PER_STAGE * NS, "epilogue staging must fit in the stages");
     static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
+    static_assert(FM <= 8, "band masks");
 
-    static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, const Acc& acc,
-                                                  int tid, const Stages& sts, float* slot) {
+    static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, Acc& acc, int tid,
+                                                  const Stages& sts, int wg, const Exit& x) {
         tid = opaque(tid);
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const int g = lane >> 5, l32 = lane & 31;
+        const int store_mask = uni(x.store_mask), fin_mask = uni(x.fin_mask);
+        if (store_mask) {
+            const __amdgpu_buffer_rsrc_t own = slot_rsrc(ka.partials + (size_t)wg * (BM * BN));
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                if ((store_mask >> i) & 1) {
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = (i * FN + j) * 4 + r;
+                            const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
+                                             acc.v[i][j][4 * r + 3]};
+                            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), own,
+                                                                   (q * THREADS + tid) * 16, 0, kCoherent);
+                        }
+                }
+            }
+            wait_vmem();          // this wave's coherent partial stores have completed
+            __syncthreads();      // ... and so have every other wave's
+            if (tid == 0) {
+                int32_t* f = ka.flags + (size_t)wg * kFlagStrideInts;
+                if (x.flag_words & 1) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (x.flag_words & 2) __hip_atomic_store(f + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (!fin_mask) return;
+        const int fw = uni(x.fw), lo = uni(x.lo), hi = uni(x.hi);
+        // every wave polls the flags itself (wave-uniform loops: no divergent
+        // region around the accumulators)
+        wait_flags(ka.flags + fw, lo, min(hi, wg - 1), ka.spin_limit, ka.err);
+        wait_flags(ka.flags + fw, max(lo, wg + 1), hi, ka.spin_limit, ka.err);
         int m0, n0;
         tile_origin(a, tile, m0, n0);
         m0 += wm * WTM;
@@ -816,29 +831,37 @@ struct Gemm {
         if constexpr (NS > 3) if (sj == 3) base = sts.template at<3 % NS>();
         if constexpr (NS > 4) if (sj == 4) base = sts.template at<4 % NS>();
         float* st = reinterpret_cast<float*>(base + (w % EPI_PER_STAGE) * EPI_BYTES);
-        float s = a.alpha;
-        if (!slot) {
-            if (ka.scale_a) s *= *ka.scale_a;
-            if (ka.scale_b) s *= *ka.scale_b;
-        }
+        float sc = a.alpha;
+        if (ka.scale_a) sc *= *ka.scale_a;
+        if (ka.scale_b) sc *= *ka.scale_b;
         constexpr int LPR = WTN / 8;
         const int col = n0 + (lane % LPR) * 8;
         const int ncol = min(max(a.N - col, 0), 8);
-        const __amdgpu_buffer_rsrc_t rs = slot_rsrc(slot);
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            if (slot) {
+            if ((fin_mask >> i) & 1) {
+                for (int k = lo; k <= hi; ++k) {
+                    if (k == wg) continue;
+                    const __amdgpu_buffer_rsrc_t rs = slot_rsrc(ka.partials + (size_t)uni(k) * (BM * BN));
+                    f32x4 v[FN][4];
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
+                    for (int j = 0; j < FN; ++j)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int q = (i * FN + j) * 4 + r;
-                        const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
-                                         acc.v[i][j][4 * r + 3]};
-                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs,
-                                                               (q * THREADS + tid) * 16, 0, kCoherent);
-                    }
-            } else {
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = (i * FN + j) * 4 + r;
+                            v[j][r] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                                    rs, (q * THREADS + tid) * 16, 0, kCoherent));
+                        }
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            acc.v[i][j][4 * r] += v[j][r].x;
+                            acc.v[i][j][4 * r + 1] += v[j][r].y;
+                            acc.v[i][j][4 * r + 2] += v[j][r].z;
+                            acc.v[i][j][4 * r + 3] += v[j][r].w;
+                        }
+                }
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -847,13 +870,21 @@ struct Gemm {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (ka.out_dtype == DT_F32) write_band<DT_F32>(a, s, st, m0 + i * 32, col, ncol, lane);
-                else if (ka.out_dtype == DT_BF16) write_band<DT_BF16>(a, s, st, m0 + i * 32, col, ncol, lane);
-                else write_band<DT_F16>(a, s, st, m0 + i * 32, col, ncol, lane);
+                if (ka.out_dtype == DT_F32) write_band<DT_F32>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                else if (ka.out_dtype == DT_BF16) write_band<DT_BF16>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                else write_band<DT_F16>(a, sc, st, m0 + i * 32, col, ncol, lane);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
+        }
+        if (hi >= lo && !(lo == wg && hi == wg)) {
+            __syncthreads();      // every wave has seen every flag: clear the words waited on
+            if (tid == 0)
+                for (int k = lo; k <= hi; ++k)
+                    if (k != wg)
+                        __hip_atomic_store(ka.flags + (size_t)k * kFlagStrideInts + fw, 0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
@@ -896,13 +927,20 @@ struct Gemm {
         return x < r ? x * (q + 1) + pos : r * (q + 1) + (x - r) * q + pos;
     }
 
-    // Relaxed agent-scope polling of a ready flag: coherent loads with no
-    // cache invalidation per poll.  All lanes load the same word, so the
-    // value is wave-uniform and the loop runs as scalar branches.  Bounded:
-    // past spin_limit polls the error word is set and the wait ends.
-    static __device__ __forceinline__ void wait_flag(int32_t* flag, int spin_limit, int32_t* err) {
-        int spins = 0;
-        while (uni(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
+    // Relaxed agent-scope polling of the ready flags of peers first..last,
+    // in order, in one loop: coherent loads with no cache invalidation per
+    // poll.  All lanes load the same word, so the value is wave-uniform and
+    // the loop runs as scalar branches.  Bounded: past spin_limit polls the
+    // error word is set and the wait ends.
+    static __device__ __forceinline__ void wait_flags(const int32_t* flags, int first, int last, int spin_limit,
+                                                      int32_t* err) {
+        int spins = 0, peer = first;
+        while (peer <= last) {
+            if (uni(__hip_atomic_load(flags + (size_t)peer * kFlagStrideInts, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT)) != 0) {
+                ++peer;
+                continue;
+            }
             __builtin_amdgcn_s_sleep(2);
             if (++spins > spin_limit) {
                 __hip_atomic_store(err, kErrTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1001,29 +1039,25 @@ struct Gemm {
 
             mac_loop(pr, st, tile, lo, hi, acc, tid);
 
-            if (role == ROLE_OWNER) {
-                // Every wave waits for each peer's flag itself (a wave-uniform
-                // loop: no divergent region around the accumulators), then
-                // adds that peer's partial.
-                for (int peer = wg + 1; peer <= peer_end; ++peer) {
-                    wait_flag(a.flags + (size_t)peer * kFlagStrideInts, a.spin_limit, a.err);
-                    add_partial(a.partials + (size_t)peer * (BM * BN), acc, tid);   // coherent loads
-                }
-                __syncthreads();   // every wave has seen every flag: clear them for the next launch
-                if (tid == 0)
-                    for (int peer = wg + 1; peer <= peer_end; ++peer)
-                        __hip_atomic_store(a.flags + (size_t)peer * kFlagStrideInts, 0, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+            constexpr int ALL = (1 << FM) - 1;
+            Exit x = {0, 0, ALL, 0, 1, 0};            // whole tile: write every band
+            if (take_sk && a.coop_s) {
+                // split fix-up: the plan cut every Stream-K tile into coop_s
+                // equal shares, one per workgroup; wg is contributor wg mod coop_s
+                const int c = wg % a.coop_s, first = wg - c;
+                constexpr int EVEN = 0x55 & ALL, ODD = 0xAA & ALL;
+                x.store_mask = c == 0 ? ODD : c == 1 ? EVEN : ALL;
+                x.flag_words = c == 0 ? 2 : c == 1 ? 1 : 3;
+                x.fin_mask = c == 0 ? EVEN : c == 1 ? ODD : 0;
+                x.fw = c;
+                x.lo = first;
+                x.hi = first + a.coop_s - 1;
+            } else if (role == ROLE_PARTIAL) {
+                x = Exit{ALL, 1, 0, 0, 1, 0};
+            } else if (role == ROLE_OWNER) {
+                x = Exit{0, 0, ALL, 0, wg + 1, peer_end};
             }
-            const bool partial = role == ROLE_PARTIAL;
-            finish(a, pr, tile, acc, tid, st, partial ? a.partials + (size_t)wg * (BM * BN) : nullptr);
-            if (partial) {
-                wait_vmem();              // this wave's coherent partial stores have completed
-                __syncthreads();          // ... and so have every other wave's
-                if (tid == 0)
-                    __hip_atomic_store(a.flags + (size_t)wg * kFlagStrideInts, 1, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
+            finish(a, pr, tile, acc, tid, st, wg, x);
         }
     }
 };

@@ -35,16 +35,17 @@ EXPORTED = [
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
                "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
-               "share"]
+               "share", "coop_s"]
 SHARE = {"proportional": 0, "leading": 1}
 SHARE_NAME = {v: k for k, v in SHARE.items()}
+FIXUP = {"auto": 0, "owner": 1}
 
 
 class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int), ("force_g", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
                 ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("raster_rows", ctypes.c_int32),
-                ("xcds", ctypes.c_int32), ("share", ctypes.c_int32)]
+                ("xcds", ctypes.c_int32), ("share", ctypes.c_int32), ("fixup", ctypes.c_int32)]
 
 
 class GroupArgs(ctypes.Structure):
@@ -127,13 +128,14 @@ class Plan:
 
     def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0, share="proportional"):
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto"):
         self._h = ctypes.c_void_p()
         o = default_options()
         if tile:
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
         o.raster_rows, o.xcds = int(raster_rows), int(xcds)
         o.share = SHARE[share] if isinstance(share, str) else int(share)
+        o.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
@@ -166,8 +168,8 @@ class Plan:
         return n.value
 
     def info(self) -> dict:
-        buf = (ctypes.c_int64 * 22)()
-        _check(lib().skgemm_plan_info(self._h, buf, 22), "skgemm_plan_info")
+        buf = (ctypes.c_int64 * len(INFO_FIELDS))()
+        _check(lib().skgemm_plan_info(self._h, buf, len(INFO_FIELDS)), "skgemm_plan_info")
         d = dict(zip(INFO_FIELDS, list(buf)))
         d["policy_name"] = POLICY_NAME[d["policy"]]
         d["tile"] = (d["BM"], d["BN"], d["BK"])
@@ -206,7 +208,7 @@ class GroupedPlan(Plan):
 
     def __init__(self, Ms, Ns, Ks, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0, share="proportional"):
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto"):
         self._h = ctypes.c_void_p()
         G = len(Ms)
         if not (len(Ns) == len(Ks) == G):
@@ -216,6 +218,7 @@ class GroupedPlan(Plan):
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
         o.raster_rows, o.xcds = int(raster_rows), int(xcds)
         o.share = SHARE[share] if isinstance(share, str) else int(share)
+        o.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)
         o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
@@ -323,12 +326,12 @@ def workspace(nbytes: int, device):
     return buf
 
 
-def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2, tile=None):
-    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves, tuple(tile) if tile else None)
+def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2, tile=None, fixup="auto"):
+    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves, tuple(tile) if tile else None, fixup)
     p = _plan_cache.get(key)
     if p is None:
         p = Plan(M, N, K, la, lb, lc, ta, tc, policy=policy, force_g=force_g, hybrid_min_waves=hybrid_min_waves,
-                 tile=tile)
+                 tile=tile, fixup=fixup)
         if len(_plan_cache) > 4096:
             _plan_cache.clear()
         _plan_cache[key] = p
@@ -336,7 +339,7 @@ def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_w
 
 
 def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None, scale_b=None,
-           policy="auto", force_g=0, hybrid_min_waves=2, trace=None, tile=None):
+           policy="auto", force_g=0, hybrid_min_waves=2, trace=None, tile=None, fixup="auto"):
     """C = alpha * s_A * s_B * A @ B + beta * C on torch tensors (2-D, on one GPU).
 
     Layouts come from the strides (a non-contiguous operand is copied).  When
@@ -372,7 +375,7 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     if lc is None or out.shape != (M, N):
         raise ValueError("out must be an M x N tensor with one contiguous dimension")
     plan = get_plan(M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy, force_g, hybrid_min_waves,
-                    tile)
+                    tile, fixup)
     nws = plan.workspace_size()
     ws = workspace(nws, A.device) if nws else None
     stream = torch.cuda.current_stream(A.device).cuda_stream

@@ -222,3 +222,58 @@ def test_raster_and_xcd_options():
     scheds = [sk.Plan(3000, 2000, 1000, ta=sk.BF16, policy="sk", num_cus=256, occupancy=1, raster_rows=r,
                       xcds=x).schedule() for r in (0, 1, 3, 8) for x in (0, 1, 8)]
     assert all(s == scheds[0] for s in scheds)
+
+
+def _one_segment_equal_shares(sched, sk_tiles, g_sk, ipt):
+    """s when the enumerated schedule cuts every Stream-K tile into s >= 2
+    equal shares held by s consecutive workgroups with one Stream-K segment
+    each (workgroup x on tile x // s), else 0."""
+    per_wg = [[sg for sg in segs if sg.tile < sk_tiles] for segs in sched[:g_sk]]
+    if not sk_tiles or not g_sk or any(len(v) != 1 for v in per_wg) or g_sk % sk_tiles:
+        return 0
+    s = g_sk // sk_tiles
+    if s < 2:
+        return 0
+    for x, (sg,) in enumerate(per_wg):
+        if sg.tile != x // s or sg.k_lo != (x % s) * (ipt // s) or sg.k_hi - sg.k_lo != ipt // s:
+            return 0
+    return s
+
+
+@pytest.mark.parametrize("policy", ["auto", "sk", "dp_1tile_sk"])
+def test_split_fixup_exactly_for_one_segment_equal_shares(policy):
+    """The plan uses the split fix-up exactly when the enumerator's schedule
+    gives every Stream-K workgroup one segment of an equal cut of its tile;
+    SKGEMM_FIXUP_OWNER always turns it off."""
+    sk = _lib()
+    shapes = [(1024, 1024, 1024), (1000, 1030, 1024), (300, 500, 768), (2560, 3328, 1024), (384, 384, 1000),
+              (640, 768, 4096), (128, 8192, 8192), (4096, 4096, 64)]
+    grids = [0] if policy == "auto" else [0, 5, 24, 36, 64, 96, 128, 144, 256, 320]
+    seen = 0
+    for (M, N, K), g in itertools.product(shapes, grids):
+        try:
+            p = sk.Plan(M, N, K, ta=sk.BF16, policy=policy, force_g=g, num_cus=256, occupancy=2,
+                        tile=(128, 128, 64))
+        except sk.SkgemmError as e:
+            assert e.status == sk.ERR_CAPACITY
+            continue
+        info = p.info()
+        sched = records_to_schedule(p.schedule(), info["grid"])
+        want = _one_segment_equal_shares(sched, info["sk_tiles"], info["g_sk"], info["ipt"])
+        assert info["coop_s"] == want, (M, N, K, policy, g)
+        seen += want > 0
+        o = sk.Plan(M, N, K, ta=sk.BF16, policy=policy, force_g=g, num_cus=256, occupancy=2, tile=(128, 128, 64),
+                    fixup="owner")
+        assert o.info()["coop_s"] == 0
+        assert records_to_schedule(o.schedule(), info["grid"]) == sched
+    assert seen > 0
+
+
+def test_split_fixup_invalid_option():
+    sk = _lib()
+    L = sk.lib()
+    o = sk.default_options()
+    o.fixup = 7
+    h = ctypes.c_void_p()
+    assert L.skgemm_plan(ctypes.byref(h), 64, 64, 64, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                         ctypes.byref(o)) == sk.ERR_INVALID_ARG

@@ -268,3 +268,92 @@ def test_full_size_sampled_rows_bf16():
     rows = np.array([0, 1, 255, 256, 4095, 8191])
     ref = og.gemm_rows_f64(to_f64(A), to_f64(B), rows)
     assert og.rel_frobenius(to_f64(C[torch.from_numpy(rows).to(dev())]), ref) <= TOL_16
+
+
+# ------------------------------------------------------------------ split fix-up
+
+# (M, N, K, dtype, tile, policy, s): g = s * (Stream-K tiles) with s dividing the
+# iterations per tile, so the plan reduces each tile with the split fix-up;
+# s = 3 and 12 have contributors that only store, 5 odd band parity
+SPLIT_CASES = [
+    (1024, 1024, 1024, torch.bfloat16, (128, 128, 64), "sk", 2),
+    (1000, 1030, 1024, torch.bfloat16, (128, 128, 64), "sk", 4),
+    (300, 500, 768, torch.bfloat16, (128, 128, 64), "sk", 3),
+    (300, 500, 768, torch.float16, (128, 128, 64), "sk", 12),
+    (512, 512, 1536, torch.bfloat16, (256, 256, 64), "sk", 3),
+    (600, 520, 640, torch.bfloat16, (256, 256, 64), "sk", 5),
+    (384, 384, 1024, torch.float32, None, "sk", 4),
+    (384, 384, 1024, torch.float32, None, "sk", 16),
+    (2560, 3328, 1024, torch.bfloat16, (128, 128, 64), "dp_1tile_sk", 4),
+]
+
+
+def _split_plan(M, N, K, dtype, tile, policy, s, fixup, out_dtype):
+    dts = sk()._torch_dtypes()
+    probe = sk().get_plan(M, N, K, 0, 0, 0, dts[dtype], dts[out_dtype], "dp", 0, 2, tile)
+    info = probe.info()
+    t, p = info["t"], info["p"]
+    sk_tiles = t if policy == "sk" else t % p
+    return s * sk_tiles, sk().get_plan(M, N, K, 0, 0, 0, dts[dtype], dts[out_dtype], policy, s * sk_tiles, 2,
+                                       tile, fixup)
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES)
+def test_split_fixup_bitwise_equals_owner_fixup(case):
+    M, N, K, dtype, tile, policy, s = case
+    a, b = W.normal_pair(M, N, K, seed=M + N + s)
+    A = torch.from_numpy(a).to(dtype).to(dev())
+    B = torch.from_numpy(b).to(dtype).to(dev())
+    c0 = torch.from_numpy(W.normal_f32(W.rng(s), (M, N))).to(dev())
+    for out_dtype in ([torch.float32] if dtype == torch.float32 else [torch.float32, dtype]):
+        g, plan = _split_plan(M, N, K, dtype, tile, policy, s, "auto", out_dtype)
+        if g > plan.info()["p"] or plan.info()["coop_s"] != s:
+            pytest.skip("this GPU's co-resident capacity gives another plan")
+        _, owner = _split_plan(M, N, K, dtype, tile, policy, s, "owner", out_dtype)
+        assert owner.info()["coop_s"] == 0
+        got = {}
+        for fx in ("auto", "owner"):
+            C = c0.to(out_dtype).clone()
+            mm(A, B, out=C, alpha=0.75, beta=0.5, policy=policy, force_g=g, tile=tile, fixup=fx)
+            got[fx] = C
+        assert torch.equal(got["auto"], got["owner"]), (case, out_dtype)
+        tol = TOL_F32 if out_dtype == torch.float32 else TOL_16
+        assert rel(got["auto"], oracle(A, B, alpha=0.75, beta=0.5, C=c0.to(out_dtype))) <= tol, (case, out_dtype)
+
+
+@pytest.mark.parametrize("s", [2, 3, 6])
+def test_split_fixup_integer_exact(s):
+    M, N, K = 700, 900, 1536
+    g = W.rng(40 + s)
+    A = torch.from_numpy(W.integer_f32(g, (M, K))).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(W.integer_f32(g, (K, N))).to(torch.bfloat16).to(dev())
+    ref = oracle(A, B)
+    gs, plan = _split_plan(M, N, K, torch.bfloat16, (128, 128, 64), "sk", s, "auto", torch.float32)
+    if gs > plan.info()["p"] or plan.info()["coop_s"] != s:
+        pytest.skip("this GPU's co-resident capacity gives another plan")
+    for _ in range(3):        # flags are self-cleaning: repeated runs on one workspace
+        C = mm(A, B, policy="sk", force_g=gs, out_dtype=torch.float32, tile=(128, 128, 64))
+        assert np.array_equal(to_f64(C), ref)
+
+
+def test_shared_workspace_across_grids():
+    """One workspace serves plans with small and large Stream-K grids in turn:
+    the partial tiles of a small-grid plan never land on a large-grid plan's
+    flags (the flag area has a fixed place)."""
+    cases = [(300, 500, 768, 36), (128, 4096, 8192, 256), (300, 500, 768, 144), (128, 4096, 8192, 128)]
+    ws = torch.zeros(64 << 20, dtype=torch.uint8, device=dev())
+    tile = (128, 128, 64)
+    for rep in range(2):
+        for (M, N, K, g) in cases:
+            a, b = W.normal_pair(M, N, K, seed=M + g)
+            A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+            B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+            plan = sk().Plan(M, N, K, ta=sk().BF16, tc=sk().F32, policy="sk", force_g=g, tile=tile)
+            nws = plan.workspace_size()
+            assert nws <= ws.numel()
+            C = torch.empty((M, N), dtype=torch.float32, device=dev())
+            stream = torch.cuda.current_stream().cuda_stream
+            plan.run(A.data_ptr(), K, B.data_ptr(), N, C.data_ptr(), N, 1.0, 0.0, None, None, ws.data_ptr(), nws,
+                     stream=stream)
+            sk().check_device_error(ws.data_ptr(), stream)
+            assert rel(C, oracle(A, B)) <= TOL_16_OUT32, (rep, M, N, K, g)
