@@ -97,9 +97,11 @@ typedef struct {
                                      SKGEMM_SHARE_LEADING gives the T mod g extra
                                      iterations to the first workgroups */
     int32_t fixup;                /* SKGEMM_FIXUP_AUTO (default): when every Stream-K
-                                     tile is cut into s >= 2 equal shares that start
-                                     and end on the tile (g = s * tiles, s divides
-                                     the iterations per tile, one GEMM), the first
+                                     tile is cut into s >= 2 shares that start and
+                                     end on the tile (one GEMM, g = s * tiles, and s
+                                     at most the iterations per tile with the
+                                     proportional share, a divisor of them with the
+                                     leading share), the first
                                      two workgroups of a tile each reduce and write
                                      half of its 32-row bands and every other share
                                      is stored for them; otherwise, and always with

@@ -389,12 +389,14 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
         pl->sk_r = int(pl->sk_iters % pl->g_sk);
     }
     // Split fix-up: a single GEMM whose Stream-K tiles are each cut into s
-    // equal shares that start and end on the tile (g = s * tiles, s | ipt), so
-    // each Stream-K workgroup performs exactly one segment.
+    // shares that start and end on the tile, so each Stream-K workgroup
+    // performs exactly one segment: g = s * tiles and, with the proportional
+    // share (workgroup x starts at floor(x * ipt / s) within tile x / s), any
+    // s <= ipt; with the leading share s must divide ipt.
     pl->coop_s = 0;
     if (!pl->fixup_owner && pl->pM.size() == 1 && pl->g_sk && pl->sk_tiles && pl->g_sk % pl->sk_tiles == 0) {
-        const int s = pl->g_sk / pl->sk_tiles;
-        if (s >= 2 && pl->pipt[0] % s == 0) pl->coop_s = s;
+        const int s = pl->g_sk / pl->sk_tiles, ipt = pl->pipt[0];
+        if (s >= 2 && s <= ipt && (pl->share_prop || ipt % s == 0)) pl->coop_s = s;
     }
     pl->flags_off = kWsHeaderBytes;
     pl->partials_off = (kWsHeaderBytes + size_t(kMaxFlagLines) * kFlagStrideInts * 4 + 255) & ~size_t(255);

@@ -69,7 +69,7 @@ struct KArgs {
     int32_t sk_prop;           // proportional even share (else leading: first sk_r get sk_q + 1)
     int32_t raster;            // tile rows per raster group (1 = row-major)
     int32_t xcds;              // XCDs the workgroups are spread over (1 = no remapping)
-    int32_t coop_s;            // >= 2: every Stream-K tile has coop_s equal one-segment shares and the
+    int32_t coop_s;            // >= 2: every Stream-K tile has coop_s one-segment shares and the
                                // split fix-up reduces it (0 = owner fix-up)
 };
 

@@ -224,10 +224,11 @@ def test_raster_and_xcd_options():
     assert all(s == scheds[0] for s in scheds)
 
 
-def _one_segment_equal_shares(sched, sk_tiles, g_sk, ipt):
+def _one_segment_shares(sched, sk_tiles, g_sk, ipt):
     """s when the enumerated schedule cuts every Stream-K tile into s >= 2
-    equal shares held by s consecutive workgroups with one Stream-K segment
-    each (workgroup x on tile x // s), else 0."""
+    shares held by s consecutive workgroups with one Stream-K segment each
+    (workgroup x on tile x // s, the shares in order and covering the tile),
+    else 0."""
     per_wg = [[sg for sg in segs if sg.tile < sk_tiles] for segs in sched[:g_sk]]
     if not sk_tiles or not g_sk or any(len(v) != 1 for v in per_wg) or g_sk % sk_tiles:
         return 0
@@ -235,16 +236,20 @@ def _one_segment_equal_shares(sched, sk_tiles, g_sk, ipt):
     if s < 2:
         return 0
     for x, (sg,) in enumerate(per_wg):
-        if sg.tile != x // s or sg.k_lo != (x % s) * (ipt // s) or sg.k_hi - sg.k_lo != ipt // s:
+        c = x % s
+        if sg.tile != x // s or (c == 0 and sg.k_lo != 0) or (c == s - 1 and sg.k_hi != ipt):
+            return 0
+        if c and per_wg[x - 1][0].k_hi != sg.k_lo:
             return 0
     return s
 
 
+@pytest.mark.parametrize("share", ["proportional", "leading"])
 @pytest.mark.parametrize("policy", ["auto", "sk", "dp_1tile_sk"])
-def test_split_fixup_exactly_for_one_segment_equal_shares(policy):
+def test_split_fixup_exactly_for_one_segment_shares(policy, share):
     """The plan uses the split fix-up exactly when the enumerator's schedule
-    gives every Stream-K workgroup one segment of an equal cut of its tile;
-    SKGEMM_FIXUP_OWNER always turns it off."""
+    gives every Stream-K workgroup one segment of a cut of its tile (both
+    share rules); SKGEMM_FIXUP_OWNER always turns it off."""
     sk = _lib()
     shapes = [(1024, 1024, 1024), (1000, 1030, 1024), (300, 500, 768), (2560, 3328, 1024), (384, 384, 1000),
               (640, 768, 4096), (128, 8192, 8192), (4096, 4096, 64)]
@@ -253,17 +258,17 @@ def test_split_fixup_exactly_for_one_segment_equal_shares(policy):
     for (M, N, K), g in itertools.product(shapes, grids):
         try:
             p = sk.Plan(M, N, K, ta=sk.BF16, policy=policy, force_g=g, num_cus=256, occupancy=2,
-                        tile=(128, 128, 64))
+                        tile=(128, 128, 64), share=share)
         except sk.SkgemmError as e:
             assert e.status == sk.ERR_CAPACITY
             continue
         info = p.info()
         sched = records_to_schedule(p.schedule(), info["grid"])
-        want = _one_segment_equal_shares(sched, info["sk_tiles"], info["g_sk"], info["ipt"])
+        want = _one_segment_shares(sched, info["sk_tiles"], info["g_sk"], info["ipt"])
         assert info["coop_s"] == want, (M, N, K, policy, g)
         seen += want > 0
         o = sk.Plan(M, N, K, ta=sk.BF16, policy=policy, force_g=g, num_cus=256, occupancy=2, tile=(128, 128, 64),
-                    fixup="owner")
+                    share=share, fixup="owner")
         assert o.info()["coop_s"] == 0
         assert records_to_schedule(o.schedule(), info["grid"]) == sched
     assert seen > 0

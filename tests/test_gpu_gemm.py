@@ -272,11 +272,15 @@ def test_full_size_sampled_rows_bf16():
 
 # ------------------------------------------------------------------ split fix-up
 
-# (M, N, K, dtype, tile, policy, s): g = s * (Stream-K tiles) with s dividing the
-# iterations per tile, so the plan reduces each tile with the split fix-up;
-# s = 3 and 12 have contributors that only store, 5 odd band parity
+# (M, N, K, dtype, tile, policy, s): g = s * (Stream-K tiles) with s at most the
+# iterations per tile, so the plan reduces each tile with the split fix-up
+# (shares of floor / ceil length where s does not divide them); s >= 3 has
+# contributors that only store
 SPLIT_CASES = [
     (1024, 1024, 1024, torch.bfloat16, (128, 128, 64), "sk", 2),
+    (1024, 1024, 1024, torch.bfloat16, (128, 128, 64), "sk", 3),
+    (600, 520, 640, torch.float16, (256, 256, 64), "sk", 3),
+    (640, 768, 4096, torch.bfloat16, (128, 128, 64), "sk", 7),
     (1000, 1030, 1024, torch.bfloat16, (128, 128, 64), "sk", 4),
     (300, 500, 768, torch.bfloat16, (128, 128, 64), "sk", 3),
     (300, 500, 768, torch.float16, (128, 128, 64), "sk", 12),
@@ -321,7 +325,7 @@ def test_split_fixup_bitwise_equals_owner_fixup(case):
         assert rel(got["auto"], oracle(A, B, alpha=0.75, beta=0.5, C=c0.to(out_dtype))) <= tol, (case, out_dtype)
 
 
-@pytest.mark.parametrize("s", [2, 3, 6])
+@pytest.mark.parametrize("s", [2, 3, 5, 6])
 def test_split_fixup_integer_exact(s):
     M, N, K = 700, 900, 1536
     g = W.rng(40 + s)
