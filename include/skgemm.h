@@ -177,14 +177,18 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
  *   18 A K-contiguous (0/1), 19 B K-contiguous (0/1), 20 G (problems of a
  *   grouped plan, 0 for one GEMM; fields 0-2, 7, 8 and 10 are 0 then and
  *   field 9 is the total tile count), 21 share (skgemm_share_t), 22 shares per
- * tile under the split fix-up (0 = owner fix-up).
- * n is the capacity of info; up to 23 values are written. */
+ * tile under the split fix-up (0 = owner fix-up), 23 workgroups per CU
+ * (p = CUs * field 23).
+ * n is the capacity of info; up to 24 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)
- * used by the plan for the dtype of the plan: time = a + b*[peers > 1] +
- * c*iters_per_cta + d*(peers - 1).  Writes 4 doubles. */
-skgemm_status_t skgemm_model_constants(skgemm_plan_t plan, double* abcd);
+ * used by the plan for its dtype and tile: time = a + b*[peers > 1] +
+ * c*iters_per_cta + d*(peers - 1), microseconds.  e is the time of one
+ * iteration on a CU that runs two workgroups: the automatic policy's split
+ * choice uses e instead of c for grids larger than the CU count (p divided
+ * by the occupancy, plan_info field 23).  Writes 5 doubles: a, b, c, d, e. */
+skgemm_status_t skgemm_model_constants(skgemm_plan_t plan, double* abcde);
 
 /* Host-side copy of the schedule the plan launches, in the same record
  * format as skgemm_run_traced (no device access). */

@@ -163,11 +163,17 @@ def model_time(g: int, t: int, ipt: int, a: float, b: float, c: float, d: float)
 
 def model_best_split(t: int, ipt: int, p: int, consts) -> int:
     """Split factor s in [1, min(p // t, ipt)] whose grid g = s * t has the
-    smallest modelled time (smallest s on ties)."""
-    a, b, c, d = consts
+    smallest modelled time (smallest s on ties).
+
+    consts is (a, b, c, d), or (a, b, c, d, e, cus): then a grid of more than
+    cus workgroups (the CU count) is costed with e per iteration instead of c,
+    since some CUs run two workgroups and the slowest one sets the time."""
+    a, b, c, d = consts[:4]
+    e, cus = (consts[4], consts[5]) if len(consts) >= 6 else (c, p)
     best_s, best = 1, None
     for s in range(1, max(1, min(p // max(t, 1), ipt)) + 1):
-        v = model_time(s * t, t, ipt, a, b, c, d)
+        g = s * t
+        v = model_time(g, t, ipt, a, b, e if g > cus else c, d)
         if best is None or v < best:
             best, best_s = v, s
     return best_s
@@ -175,7 +181,7 @@ def model_best_split(t: int, ipt: int, p: int, consts) -> int:
 
 def model_best_g(t: int, ipt: int, p: int, consts) -> int:
     """Grid size in [t, p] with the smallest modelled time (smallest g on ties)."""
-    a, b, c, d = consts
+    a, b, c, d = consts[:4]
     lo, hi = t, max(t, p)
     best_g, best = lo, None
     for g in range(lo, hi + 1):

@@ -52,7 +52,7 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32}[dtype]
     probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
     BM, BN, BK, p = probe["BM"], probe["BN"], probe["BK"], probe["p"]
-    rows, ys = [], []
+    rows, ys, grids = [], [], []
     for t in (1, 2, 4, 8, 16, 32, 64, 128, 192):
         for ipt in (4, 16, 64):
             tm = 1
@@ -86,11 +86,16 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
                     best = min(best, e0.elapsed_time(e1) / reps * 1e3)
                 rows.append(model_terms(t, ipt, g))
                 ys.append(best)
+                grids.append(g)
                 if verbose:
                     print(f"t={t:4d} ipt={ipt:3d} g={g:4d}: {best:8.2f} us", flush=True)
     X = np.array(rows)
     y = np.array(ys)
-    coef, *_ = np.linalg.lstsq(X, y, rcond=None)
+    # a-d describe one workgroup per CU: fit them on grids no larger than the
+    # CU count (the split rule switches to e beyond it)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    one = np.array([g <= cus for g in grids])
+    coef, *_ = np.linalg.lstsq(X[one], y[one], rcond=None)
     a, b, c, d = (float(v) for v in coef)
     # e: per-iteration time with all p slots busy, from a data-parallel problem
     # of four full waves (four tiles per slot) at two depths
@@ -120,7 +125,7 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
         if verbose:
             print(f"full waves: t={t} ipt={ipt}: {tw[-1]:.2f} us per wave", flush=True)
     e = (tw[1] - tw[0]) / (64 - 16)
-    return (a / c, b / c, 1.0, d / c), (a, b, c, d, e), X, y
+    return (a / c, b / c, 1.0, d / c), (a, b, c, d, e), X[one], y[one]
 
 
 def main():

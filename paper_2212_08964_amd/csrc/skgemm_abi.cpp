@@ -39,7 +39,7 @@ struct skgemm_plan_s {
     int policy;
     int sk_tiles, g_sk, grid;
     bool sk_first;
-    int p, hybrid_min_waves;
+    int p, occ, hybrid_min_waves;   // p = CUs * occ co-resident workgroups
     int raster, xcds;  // tile raster group rows; XCD count for the workgroup permutation
     bool share_prop;   // proportional (else leading) even share
     bool fixup_owner;  // the owner alone reduces every split tile
@@ -100,15 +100,16 @@ TileCfg tile_for(int dt, int v) {
 // partial.  The grid-size argmin only depends on their ratios; the absolute
 // values let the planner compare tile variants.
 void model_for(int dt, int v, double* m) {
-    // a-d: least-squares fits over tile-aligned grids (calibrate.py); e: the
-    // per-iteration time of one workgroup when all p co-resident workgroups
-    // run (a data-parallel problem of several full waves), which only the
-    // comparison of tile variants uses.  FP8 shares the 16-bit 256x256
+    // a-d: least-squares fits over tile-aligned grids of at most one
+    // workgroup per CU (calibrate.py); e: the per-iteration time of one
+    // workgroup when all p co-resident workgroups run (a data-parallel problem
+    // of several full waves), used for grids larger than the CU count and in
+    // the comparison of tile variants.  FP8 shares the 16-bit 256x256
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
-    if (dt == DT_F32) { m[0] = 4.21; m[1] = 5.37; m[2] = 2.12; m[3] = 1.46; m[4] = 3.94; return; }
-    if (v == 1) { m[0] = 5.13; m[1] = 1.98; m[2] = 0.601; m[3] = 0.789; m[4] = 0.950; return; }
-    m[0] = 9.64; m[1] = 2.52; m[2] = 1.352; m[3] = 1.54; m[4] = 1.723;
+    if (dt == DT_F32) { m[0] = 5.71; m[1] = 1.00; m[2] = 2.07; m[3] = 0.755; m[4] = 3.82; return; }
+    if (v == 1) { m[0] = 5.21; m[1] = 1.08; m[2] = 0.599; m[3] = 0.781; m[4] = 0.860; return; }
+    m[0] = 9.79; m[1] = 2.35; m[2] = 1.357; m[3] = 1.55; m[4] = 1.641;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -133,13 +134,19 @@ int model_best_g(int64_t t, int64_t ipt, int64_t p, const double* m) {
 }
 
 // Split factor s in [1, min(p / t, ipt)] that minimises the modelled time of
-// basic Stream-K over t tiles with g = s * t (the smallest s on ties).
-int model_best_split(int64_t t, int64_t ipt, int64_t p, const double* m) {
+// basic Stream-K over t tiles with g = s * t (the smallest s on ties).  A grid
+// larger than the CU count puts two workgroups on some CUs, and those run an
+// iteration in e (m[4]) rather than c: the slowest workgroup sets the time.
+int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const double* m) {
     const int64_t smax = std::max<int64_t>(1, std::min(p / std::max<int64_t>(t, 1), ipt));
+    auto time_at = [&](int64_t g) {
+        const double mg[4] = {m[0], m[1], g > cus ? m[4] : m[2], m[3]};
+        return model_time(g, t, ipt, mg);
+    };
     int best_s = 1;
-    double best = model_time(t, t, ipt, m);
+    double best = time_at(t);
     for (int64_t sp = 2; sp <= smax; ++sp) {
-        const double v = model_time(t * sp, t, ipt, m);
+        const double v = time_at(t * sp);
         if (v < best) {
             best = v;
             best_s = int(sp);
@@ -307,6 +314,7 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     const int64_t p = int64_t(cus) * occ;
     if (p <= 0 || p > kMaxDim) return SKGEMM_ERR_INVALID_ARG;
     pl->p = int(p);
+    pl->occ = occ;
     const int np = int(pl->pipt.size());
     const int64_t t = pl->tile_base[np];
     const int64_t total = pl->iter_base[np];
@@ -331,7 +339,7 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
                 // L2.  Unaligned shares start each workgroup at its own
                 // k-offset, which on MI355X's per-XCD L2 costs up to 2x.
                 const int64_t sk_t = w == 0 ? t : r;
-                const int s_best = model_best_split(sk_t, ipt, p, pl->model);
+                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model);
                 if (s_best == 1) policy = SKGEMM_POLICY_DP;
                 else {
                     policy = w == 0 ? SKGEMM_POLICY_SK : SKGEMM_POLICY_DP_1TILE_SK;
@@ -757,17 +765,18 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[23] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[24] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
                            pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
-                           pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s};
-    for (int i = 0; i < n && i < 23; ++i) info[i] = v[i];
+                           pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s,
+                           pl->occ};
+    for (int i = 0; i < n && i < 24; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 
-skgemm_status_t skgemm_model_constants(skgemm_plan_t pl, double* abcd) {
-    if (!pl || !abcd) return SKGEMM_ERR_INVALID_ARG;
-    for (int i = 0; i < 4; ++i) abcd[i] = pl->model[i];
+skgemm_status_t skgemm_model_constants(skgemm_plan_t pl, double* abcde) {
+    if (!pl || !abcde) return SKGEMM_ERR_INVALID_ARG;
+    for (int i = 0; i < 5; ++i) abcde[i] = pl->model[i];
     return SKGEMM_OK;
 }
 

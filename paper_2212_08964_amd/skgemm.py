@@ -35,7 +35,7 @@ EXPORTED = [
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
                "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
-               "share", "coop_s"]
+               "share", "coop_s", "occupancy"]
 SHARE = {"proportional": 0, "leading": 1}
 SHARE_NAME = {v: k for k, v in SHARE.items()}
 FIXUP = {"auto": 0, "owner": 1}
@@ -177,7 +177,8 @@ class Plan:
         return d
 
     def model_constants(self):
-        buf = (ctypes.c_double * 4)()
+        """(a, b, c, d, e) of the plan's grid-size model, microseconds."""
+        buf = (ctypes.c_double * 5)()
         _check(lib().skgemm_model_constants(self._h, buf), "skgemm_model_constants")
         return tuple(buf)
 

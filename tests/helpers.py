@@ -30,8 +30,14 @@ def oracle_plan_for(info, model, policy, force_g=0):
     """The oracle's plan for the problem a library plan launches."""
     return S.make_plan(int(info["M"]), int(info["N"]), int(info["K"]), int(info["BM"]), int(info["BN"]),
                        int(info["BK"]), int(info["p"]), policy=policy, force_g=force_g,
-                       hybrid_min_waves=int(info["hybrid_min_waves"]), model=model,
+                       hybrid_min_waves=int(info["hybrid_min_waves"]), model=model_with_cus(info, model),
                        share=SHARE_BY_ID[int(info.get("share", 0))])
+
+
+def model_with_cus(info, model):
+    """The library's (a, b, c, d, e) plus the CU count of the plan, the form the
+    oracle's split rule takes."""
+    return tuple(model)[:5] + (int(info["p"]) // int(info["occupancy"]),)
 
 
 def bits_u16(t):

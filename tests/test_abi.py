@@ -12,7 +12,7 @@ import re
 
 import pytest
 
-from helpers import POLICY_BY_ID, oracle_plan_for, records_to_schedule
+from helpers import POLICY_BY_ID, model_with_cus, oracle_plan_for, records_to_schedule
 from oracle import schedule as S
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -174,7 +174,7 @@ def test_grouped_planner_matches_enumerator(policy):
             continue
         info = p.info()
         ref = GR.make_grouped_plan(probs, info["BM"], info["BN"], info["BK"], info["p"], policy=policy,
-                                   hybrid_min_waves=2, model=p.model_constants())
+                                   hybrid_min_waves=2, model=model_with_cus(info, p.model_constants()))
         assert (ref.policy, ref.sk_tiles, ref.g_sk, ref.grid) == (
             POLICY_BY_ID[info["policy"]], info["sk_tiles"], info["g_sk"], info["grid"])
         got = records_to_schedule(p.schedule(), info["grid"])

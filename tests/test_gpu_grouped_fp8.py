@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import workloads as W
-from helpers import records_to_schedule, to_f64
+from helpers import model_with_cus, records_to_schedule, to_f64
 from oracle import gemm as og
 from oracle import grouped as GR
 from oracle import lowp
@@ -101,7 +101,7 @@ def test_grouped_trace_matches_enumerator(policy, tile):
     recs = [tuple(int(v) for v in r) for r in tr.cpu().numpy().reshape(-1, 8) if r[0] != -7]
     got = records_to_schedule(recs, info["grid"])
     ref = GR.make_grouped_plan(shapes, info["BM"], info["BN"], info["BK"], info["p"], policy=policy,
-                               model=p.model_constants())
+                               model=model_with_cus(info, p.model_constants()))
     assert got == GR.enumerate_grouped_schedule(ref)
 
 

@@ -14,6 +14,7 @@ import itertools
 import json
 import os
 
+import numpy as np
 import pytest
 
 from oracle import grouped as GR
@@ -250,3 +251,19 @@ def test_grouped_ragged_invariants():
             for pol in ("auto", "sk", "dp", "dp_1tile_sk", "2tile_sk_dp"):
                 g = GR.make_grouped_plan(probs, 2, 2, 1, p, policy=pol)
                 GR.check_grouped_invariants(g, GR.enumerate_grouped_schedule(g))
+
+
+def test_split_rule_occupancy_term():
+    """The split rule's CU term: with e = c it is the four-constant rule; with a
+    prohibitive e it never picks a grid above the CU count when one fits."""
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        t = int(rng.integers(1, 300))
+        ipt = int(rng.integers(1, 80))
+        cus = int(rng.choice([64, 128, 256]))
+        p = cus * int(rng.integers(1, 3))
+        a, b, c, d = (float(v) for v in rng.uniform(0.1, 10.0, 4))
+        assert S.model_best_split(t, ipt, p, (a, b, c, d, c, cus)) == S.model_best_split(t, ipt, p, (a, b, c, d))
+        s = S.model_best_split(t, ipt, p, (a, b, c, d, 1e9, cus))
+        if t <= cus:
+            assert s * t <= cus, (t, ipt, p, cus, s)
