@@ -154,7 +154,7 @@ def cpu_baseline(shapes, budget_s):
                       f"{flops / 1e9:.1f} GFLOP in {secs:.1f} s, FP64 triple loop with OpenMP over rows"}
 
 
-PEAKS = {"f32": 157.3, "bf16": PEAK_BF16_TFLOPS, "f16": PEAK_BF16_TFLOPS, "fp8": 5033.2}
+PEAKS = {"f32": 157.3, "bf16": PEAK_BF16_TFLOPS, "f16": PEAK_BF16_TFLOPS, "fp8": 5033.2, "f64": 78.6}
 
 
 def _best_us(fn, reps, rounds=3):
@@ -249,6 +249,26 @@ def suite(args):
             emit(row)
             del C
         del A32, B32
+        torch.cuda.empty_cache()
+
+    # FP64 (64 x 64 x 16 tiles, FP64 MFMA, FP64 fix-up) on the same shapes
+    for (M, N, K) in [(1024, 1024, 1024), (4096, 4096, 4096), (8192, 8192, 8192), (128, 8192, 8192)]:
+        A64 = torch.randn((M, K), generator=gen, device=dev, dtype=torch.float64)
+        B64 = torch.randn((K, N), generator=gen, device=dev, dtype=torch.float64)
+        C = torch.empty((M, N), device=dev, dtype=torch.float64)
+        fl = 2.0 * M * N * K
+        row = {"workload": f"f64 {M}x{N}x{K}", "dtype": "f64"}
+        for pol in ("auto", "dp"):
+            us = _best_us(lambda pol=pol: sk.matmul(A64, B64, out=C, policy=pol), int(min(50, max(3, 2e11 / fl))))
+            tf = fl / us / 1e6
+            row[pol + "_us"] = round(us, 2)
+            row[pol + "_tflops"] = round(tf, 2)
+            row[pol + "_pct_peak"] = round(100 * tf / PEAKS["f64"], 2)
+        us_t = _best_us(lambda: torch.matmul(A64, B64, out=C), int(min(50, max(3, 2e11 / fl))))
+        row["torch_matmul_us"] = round(us_t, 2)
+        row["torch_matmul_tflops"] = round(fl / us_t / 1e6, 2)
+        emit(row)
+        del A64, B64, C
         torch.cuda.empty_cache()
 
     # grouped: 64 problems, N=4096, K=2048, M ~ Zipf(1.2) on [16, 4096], one launch under a graph

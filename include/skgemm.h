@@ -51,7 +51,8 @@ typedef enum {
     SKGEMM_F32 = 0,
     SKGEMM_F16 = 1,
     SKGEMM_BF16 = 2,
-    SKGEMM_F8E4M3 = 3             /* OCP E4M3FN, used with per-tensor scales */
+    SKGEMM_F8E4M3 = 3,            /* OCP E4M3FN, used with per-tensor scales */
+    SKGEMM_F64 = 4                /* FP64 in, FP64 accumulate, fix-up and out */
 } skgemm_dtype_t;
 
 /* Work decomposition (Work Decomposition Strategies section and

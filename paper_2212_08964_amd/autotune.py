@@ -10,7 +10,10 @@ keeps the fastest:
 * pure data-parallel,
 * basic Stream-K over every tile at grid p and at the model's grid,
 * two-tile SK + DP and DP + one-tile SK,
-* the hybrids with hybrid_min_waves = 1 (two-tile from one full wave on).
+* the hybrids with hybrid_min_waves = 1 (two-tile from one full wave on),
+
+each with the planner's tile choice and with every compiled tile pinned, so
+the tuner picks the tile shape and the DP/SK split together.
 
 Each candidate is timed with HIP events over `reps` back-to-back launches
 after a warm-up (best of three batches).  Decisions are cached in memory and,
@@ -25,7 +28,7 @@ import os
 
 from . import skgemm as sk
 
-CANDIDATES = [
+_POLICIES = [
     dict(policy="auto"),
     dict(policy="dp"),
     dict(policy="sk"),
@@ -34,6 +37,10 @@ CANDIDATES = [
     dict(policy="2tile_sk_dp", hybrid_min_waves=1),
     dict(policy="auto", hybrid_min_waves=1),
 ]
+# every policy with the planner's own tile choice, then with each compiled
+# 16-bit tile pinned (candidates a dtype does not compile are skipped)
+TILES = [None, (256, 256, 64), (128, 128, 64)]
+CANDIDATES = [dict(c, tile=t) for t in TILES for c in _POLICIES]
 
 _memo = {}
 
@@ -73,12 +80,15 @@ def tune_grouped(As, Bs, Cs, reps=10, cache_path=None, candidates=None, verbose=
         with open(cache_path) as fh:
             disk = json.load(fh)
         if key in disk:
-            _memo[key] = disk[key]
-            return disk[key], {}
+            best = dict(disk[key])
+            if best.get("tile"):
+                best["tile"] = tuple(best["tile"])    # JSON keeps it as a list
+            _memo[key] = best
+            return best, {}
     results = {}
     best, best_t = None, float("inf")
     for cand in candidates or CANDIDATES:
-        opts = dict(policy="auto", force_g=0, hybrid_min_waves=2)
+        opts = dict(policy="auto", force_g=0, hybrid_min_waves=2, tile=None)
         opts.update(cand)
         label = json.dumps(opts, sort_keys=True)
         try:

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libskgemm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["kernels_f32.hip", "kernels_f16.hip", "kernels_bf16.hip", "kernels_f8.hip",
+SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "kernels_f16.hip", "kernels_bf16.hip", "kernels_f8.hip",
            "dispatch.hip", "quant.hip", "skgemm_abi.cpp"]
 
 ARCH = "gfx950"

@@ -48,8 +48,8 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     import torch
 
     from . import skgemm as sk
-    tdt = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}[dtype]
-    cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32}[dtype]
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32, "f64": torch.float64}[dtype]
+    cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32, "f64": sk.F64}[dtype]
     probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
     BM, BN, BK, p = probe["BM"], probe["BN"], probe["BK"], probe["p"]
     rows, ys, grids = [], [], []

@@ -9,10 +9,12 @@ const void* kernel_fn_f32(bool akc, bool bkc, int v);
 const void* kernel_fn_f16(bool akc, bool bkc, int v);
 const void* kernel_fn_bf16(bool akc, bool bkc, int v);
 const void* kernel_fn_f8(bool akc, bool bkc, int v);
+const void* kernel_fn_f64(bool akc, bool bkc, int v);
 int kernel_threads_f32(int v);
 int kernel_threads_f16(int v);
 int kernel_threads_bf16(int v);
 int kernel_threads_f8(int v);
+int kernel_threads_f64(int v);
 
 static const void* kernel_for(int dtype, bool akc, bool bkc, int v) {
     switch (dtype) {
@@ -20,6 +22,7 @@ static const void* kernel_for(int dtype, bool akc, bool bkc, int v) {
         case DT_F16: return kernel_fn_f16(akc, bkc, v);
         case DT_BF16: return kernel_fn_bf16(akc, bkc, v);
         case DT_F8: return kernel_fn_f8(akc, bkc, v);
+        case DT_F64: return kernel_fn_f64(akc, bkc, v);
         default: return nullptr;
     }
 }
@@ -32,6 +35,7 @@ int kernel_threads(int dtype, int v) {
         case DT_F16: return kernel_threads_f16(v);
         case DT_BF16: return kernel_threads_bf16(v);
         case DT_F8: return kernel_threads_f8(v);
+        case DT_F64: return kernel_threads_f64(v);
         default: return 0;
     }
 }

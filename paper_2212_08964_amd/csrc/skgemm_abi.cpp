@@ -66,6 +66,7 @@ int elem_bytes(skgemm_dtype_t t) {
         case SKGEMM_F16:
         case SKGEMM_BF16: return 2;
         case SKGEMM_F8E4M3: return 1;
+        case SKGEMM_F64: return 8;
     }
     return 0;
 }
@@ -76,6 +77,7 @@ int to_dt(skgemm_dtype_t t) {
         case SKGEMM_F16: return DT_F16;
         case SKGEMM_BF16: return DT_BF16;
         case SKGEMM_F8E4M3: return DT_F8;
+        case SKGEMM_F64: return DT_F64;
     }
     return -1;
 }
@@ -86,6 +88,7 @@ TileCfg tile_for(int dt, int v) {
         switch (dt) {
             case DT_F32: return kTileF32;
             case DT_F8: return kTileF8;
+            case DT_F64: return kTileF64;
             default: return kTile16;
         }
     }
@@ -107,6 +110,7 @@ void model_for(int dt, int v, double* m) {
     // the comparison of tile variants.  FP8 shares the 16-bit 256x256
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
+    if (dt == DT_F64) { m[0] = 5.0; m[1] = 1.5; m[2] = 0.80; m[3] = 0.80; m[4] = 1.00; return; }
     if (dt == DT_F32) { m[0] = 5.71; m[1] = 1.00; m[2] = 2.07; m[3] = 0.755; m[4] = 3.82; return; }
     if (v == 1) { m[0] = 5.21; m[1] = 1.08; m[2] = 0.599; m[3] = 0.781; m[4] = 0.860; return; }
     m[0] = 9.79; m[1] = 2.35; m[2] = 1.357; m[3] = 1.55; m[4] = 1.641;
@@ -408,7 +412,9 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     }
     pl->flags_off = kWsHeaderBytes;
     pl->partials_off = (kWsHeaderBytes + size_t(kMaxFlagLines) * kFlagStrideInts * 4 + 255) & ~size_t(255);
-    pl->ws_bytes = pl->g_sk ? pl->partials_off + size_t(pl->g_sk) * pl->BM * pl->BN * 4 : 0;
+    // partial tiles accumulate in FP32, or FP64 for FP64 inputs
+    const size_t acc_bytes = pl->dtype == DT_F64 ? 8 : 4;
+    pl->ws_bytes = pl->g_sk ? pl->partials_off + size_t(pl->g_sk) * pl->BM * pl->BN * acc_bytes : 0;
     int mx = 0;
     for (int x = 0; x < pl->grid; ++x) mx = std::max(mx, walk(*pl, x, [](int, int, int, int, int, int, int) {}));
     pl->max_segs = mx;
@@ -428,6 +434,7 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     if (tc == SKGEMM_F8E4M3) return SKGEMM_ERR_UNSUPPORTED;
     if (ta != SKGEMM_F8E4M3 && ta != SKGEMM_F32 && tc != ta && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if (ta == SKGEMM_F32 && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
+    if ((ta == SKGEMM_F64) != (tc == SKGEMM_F64)) return SKGEMM_ERR_UNSUPPORTED;
     if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0) return SKGEMM_ERR_INVALID_ARG;
     if (o.raster_rows < 0 || o.raster_rows > kMaxRaster || o.xcds < 0 || o.xcds > kMaxXcds)
         return SKGEMM_ERR_INVALID_ARG;

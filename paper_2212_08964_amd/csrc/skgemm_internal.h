@@ -6,7 +6,7 @@
 
 namespace skg {
 
-enum DType : int32_t { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3 };
+enum DType : int32_t { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_F64 = 4 };
 enum Role : int32_t { ROLE_FULL = 0, ROLE_PARTIAL = 1, ROLE_OWNER = 2 };
 
 constexpr int kFlagStrideInts = 32;        // one 128-byte line per ready flag
@@ -25,6 +25,7 @@ constexpr TileCfg kTileF32 = {128, 128, 32, 2};
 constexpr TileCfg kTile16 = {256, 256, 64, 2};    // bf16 and f16
 constexpr TileCfg kTile16S = {128, 128, 64, 2};   // bf16 and f16, small-tile variant
 constexpr TileCfg kTileF8 = {256, 256, 128, 2};
+constexpr TileCfg kTileF64 = {64, 64, 16, 2};
 
 // One problem of a grouped launch (device table entry, 128 bytes).  Shapes are
 // as launched (operands already swapped when C is column-major).

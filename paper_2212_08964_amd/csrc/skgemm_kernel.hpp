@@ -41,6 +41,8 @@ namespace skg {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
@@ -60,6 +62,7 @@ template <> struct Cfg<DT_F32, 0> { static constexpr int EB = 4, BM = kTileF32.b
 template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
 template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
 template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4, NS = kTileF8.ns; };
+template <> struct Cfg<DT_F64, 0> { static constexpr int EB = 8, BM = kTileF64.bm, BN = kTileF64.bn, BK = kTileF64.bk, WM = 2, WN = 2, NS = kTileF64.ns; };
 template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 
@@ -257,7 +260,12 @@ struct Slab {
 #pragma unroll 1
                 for (int e = 0; e < VE; ++e) {
                     // the loads return raw bits (unsigned integers of the element's width)
-                    if constexpr (EB == 4) {
+                    if constexpr (EB == 8) {
+                        const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8 * e, 0, 0);
+                        const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8 * e + 4, 0, 0);
+                        *reinterpret_cast<uint32_t*>(dst + 8 * e) = e < kp ? lo : 0u;
+                        *reinterpret_cast<uint32_t*>(dst + 8 * e + 4) = e < kp ? hi : 0u;
+                    } else if constexpr (EB == 4) {
                         const uint32_t x = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * e, 0, 0);
                         *reinterpret_cast<uint32_t*>(dst + 4 * e) = e < kp ? x : 0u;
                     } else if constexpr (EB == 2) {
@@ -391,6 +399,20 @@ __device__ __forceinline__ Prob uniform(const Prob& p) {
                 uni(p.K), uni(p.tn), uni(p.ipt), unif(p.alpha), unif(p.beta), uni(p.raster)};
 }
 
+template <bool B, class T, class F> struct Pick { using type = T; };
+template <class T, class F> struct Pick<false, T, F> { using type = F; };
+
+// One FP64 element of a staged slab: K-contiguous rows of 16 doubles (chunk of
+// two per 16 bytes, swizzled by row) or MN-contiguous rows of one k.
+template <bool KC, int ROWB>
+__device__ __forceinline__ double lds_f64(const unsigned char* lds, int outer, int k) {
+    if constexpr (KC)
+        return *reinterpret_cast<const double*>(lds + outer * ROWB + (((k >> 1) ^ swz<8, true, ROWB>(outer)) << 4) +
+                                                (k & 1) * 8);
+    else
+        return *reinterpret_cast<const double*>(lds + mn_addr<8, ROWB>(k, outer));
+}
+
 template <int DT, bool AKC, bool BKC, int V>
 struct Gemm {
     using C_ = Cfg<DT, V>;
@@ -423,7 +445,49 @@ struct Gemm {
         }
     };
 
-    struct Acc { f32x16 v[FM][FN]; };
+    // FP32 accumulators: one 32x32 MFMA block per (i, j).  FP64: four 16x16
+    // MFMA blocks per 32x32 block (q = 2 * row half + column half), so bands
+    // and blocks cover the same rows and columns for every type.
+    struct Acc32 { f32x16 v[FM][FN]; };
+    struct Acc64 { f64x4 v[FM][FN][4]; };
+    using Acc = typename Pick<DT == DT_F64, Acc64, Acc32>::type;
+    // 16-byte chunks of one block's accumulators per lane (partial tiles are
+    // stored and read in this fragment order)
+    static constexpr int CPB = DT == DT_F64 ? 8 : 4;
+    // floats per partial slot
+    static constexpr int SLOT = DT == DT_F64 ? 2 * BM * BN : BM * BN;
+
+    static __device__ __forceinline__ u32x4 acc_chunk(const Acc& acc, int i, int j, int r) {
+        if constexpr (DT == DT_F64) {
+            const f64x4& b = acc.v[i][j][r >> 1];
+            const f64x2 v = (r & 1) ? f64x2{b[2], b[3]} : f64x2{b[0], b[1]};
+            return __builtin_bit_cast(u32x4, v);
+        } else {
+            const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
+                             acc.v[i][j][4 * r + 3]};
+            return __builtin_bit_cast(u32x4, v);
+        }
+    }
+
+    static __device__ __forceinline__ void acc_add_chunk(Acc& acc, int i, int j, int r, const u32x4& bits) {
+        if constexpr (DT == DT_F64) {
+            const f64x2 v = __builtin_bit_cast(f64x2, bits);
+            f64x4& b = acc.v[i][j][r >> 1];
+            if (r & 1) {
+                b[2] += v.x;
+                b[3] += v.y;
+            } else {
+                b[0] += v.x;
+                b[1] += v.y;
+            }
+        } else {
+            const f32x4 v = __builtin_bit_cast(f32x4, bits);
+            acc.v[i][j][4 * r] += v.x;
+            acc.v[i][j][4 * r + 1] += v.y;
+            acc.v[i][j][4 * r + 2] += v.z;
+            acc.v[i][j][4 * r + 3] += v.w;
+        }
+    }
 
     // MFMAs over one staged k-slab.
     static __device__ __forceinline__ void compute(const unsigned char* As, const unsigned char* Bs,
@@ -461,6 +525,32 @@ struct Gemm {
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(af[cur][i], bf[cur][j], acc.v[i][j]);
                 __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if constexpr (DT == DT_F64) {
+            // v_mfma_f64_16x16x4f64: lane l holds A[row l%16][k l/16] and
+            // B[k l/16][col l%16] of the k4 step; each 32x32 block is four
+            // 16x16 MFMA blocks.
+            const int l16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+            for (int s = 0; s < BK / 4; ++s) {
+                const int k = 4 * s + kq;
+                double af[FM][2], bf[FN][2];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) af[i][h] = lds_f64<AKC, SA::ROWB>(As, wm * WTM + i * 32 + h * 16 + l16, k);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) bf[j][h] = lds_f64<BKC, SB::ROWB>(Bs, wn * WTN + j * 32 + h * 16 + l16, k);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc.v[i][j][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][q >> 1], bf[j][q & 1],
+                                                                                 acc.v[i][j][q], 0, 0, 0);
             }
         } else if constexpr (DT == DT_F32) {
             // Lane group g handles k = 8c + 4g + u of step (c, u).
@@ -659,7 +749,14 @@ struct Gemm {
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc.v[i][j] = f32x16{0};
+            for (int j = 0; j < FN; ++j) {
+                if constexpr (DT == DT_F64) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc.v[i][j][q] = f64x4{0, 0, 0, 0};
+                } else {
+                    acc.v[i][j] = f32x16{0};
+                }
+            }
         if (klo >= khi) return;
         int m0, n0;
         tile_origin(a, tile, m0, n0);
@@ -688,7 +785,7 @@ struct Gemm {
     static constexpr int kCoherent = 16;   // SC1 cache-policy bit
 
     static __device__ __forceinline__ __amdgpu_buffer_rsrc_t slot_rsrc(float* slot) {
-        return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, BM * BN * 4, kBufferFlags);
+        return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, SLOT * 4, kBufferFlags);
     }
 
     // Output of one 32-row band of the wave's block, staged in `st` (FP32,
@@ -783,6 +880,29 @@ struct Gemm {
     static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
     static_assert(FM <= 8, "band masks");
 
+    // FP64 output straight from the MFMA layout: lane l holds column l % 16
+    // of rows l / 16 + 4 e of each 16x16 block, so every store instruction
+    // writes four runs of 128 contiguous bytes.  Predicated at the M and N edges.
+    static __device__ __forceinline__ void write_block_f64(const Prob& a, double s, const Acc& acc, int i, int j,
+                                                           int m0, int n0, int lane) {
+        if constexpr (DT == DT_F64) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int col = n0 + j * 32 + (q & 1) * 16 + (lane & 15);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = m0 + i * 32 + (q >> 1) * 16 + (lane >> 4) + 4 * e;
+                    if (row < a.M && col < a.N) {
+                        gptr<double> cp = global<double>(a.C) + ((int64_t)row * a.ldc + col);
+                        double x = s * acc.v[i][j][q][e];
+                        if (a.beta != 0.0f) x += double(a.beta) * *cp;
+                        *cp = x;
+                    }
+                }
+            }
+        }
+    }
+
     static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, Acc& acc, int tid,
                                                   const Stages& sts, int wg, const Exit& x) {
         tid = opaque(tid);
@@ -790,18 +910,16 @@ struct Gemm {
         const int g = lane >> 5, l32 = lane & 31;
         const int store_mask = uni(x.store_mask), fin_mask = uni(x.fin_mask);
         if (store_mask) {
-            const __amdgpu_buffer_rsrc_t own = slot_rsrc(ka.partials + (size_t)wg * (BM * BN));
+            const __amdgpu_buffer_rsrc_t own = slot_rsrc(ka.partials + (size_t)wg * SLOT);
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 if ((store_mask >> i) & 1) {
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int q = (i * FN + j) * 4 + r;
-                            const f32x4 v = {acc.v[i][j][4 * r], acc.v[i][j][4 * r + 1], acc.v[i][j][4 * r + 2],
-                                             acc.v[i][j][4 * r + 3]};
-                            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), own,
+                        for (int r = 0; r < CPB; ++r) {
+                            const int q = (i * FN + j) * CPB + r;
+                            __builtin_amdgcn_raw_buffer_store_b128(acc_chunk(acc, i, j, r), own,
                                                                    (q * THREADS + tid) * 16, 0, kCoherent);
                         }
                 }
@@ -842,40 +960,39 @@ struct Gemm {
             if ((fin_mask >> i) & 1) {
                 for (int k = lo; k <= hi; ++k) {
                     if (k == wg) continue;
-                    const __amdgpu_buffer_rsrc_t rs = slot_rsrc(ka.partials + (size_t)uni(k) * (BM * BN));
-                    f32x4 v[FN][4];
+                    const __amdgpu_buffer_rsrc_t rs = slot_rsrc(ka.partials + (size_t)uni(k) * SLOT);
+                    u32x4 v[FN][CPB];
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int q = (i * FN + j) * 4 + r;
-                            v[j][r] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                                    rs, (q * THREADS + tid) * 16, 0, kCoherent));
+                        for (int r = 0; r < CPB; ++r) {
+                            const int q = (i * FN + j) * CPB + r;
+                            v[j][r] = __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent);
                         }
 #pragma unroll
                     for (int j = 0; j < FN; ++j)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            acc.v[i][j][4 * r] += v[j][r].x;
-                            acc.v[i][j][4 * r + 1] += v[j][r].y;
-                            acc.v[i][j][4 * r + 2] += v[j][r].z;
-                            acc.v[i][j][4 * r + 3] += v[j][r].w;
-                        }
+                        for (int r = 0; r < CPB; ++r) acc_add_chunk(acc, i, j, r, v[j][r]);
                 }
+                if constexpr (DT == DT_F64) {
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
+                    for (int j = 0; j < FN; ++j) write_block_f64(a, double(sc), acc, i, j, m0, n0, lane);
+                } else {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (ka.out_dtype == DT_F32) write_band<DT_F32>(a, sc, st, m0 + i * 32, col, ncol, lane);
-                else if (ka.out_dtype == DT_BF16) write_band<DT_BF16>(a, sc, st, m0 + i * 32, col, ncol, lane);
-                else write_band<DT_F16>(a, sc, st, m0 + i * 32, col, ncol, lane);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (ka.out_dtype == DT_F32) write_band<DT_F32>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                    else if (ka.out_dtype == DT_BF16) write_band<DT_BF16>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                    else write_band<DT_F16>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
             }
         }
         if (hi >= lo && !(lo == wg && hi == wg)) {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "libskgemm.so")
 # enums of include/skgemm.h
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CAPACITY, ERR_HIP, ERR_TIMEOUT = range(7)
 ROW_MAJOR, COL_MAJOR = 0, 1
-F32, F16, BF16, F8E4M3 = 0, 1, 2, 3
+F32, F16, BF16, F8E4M3, F64 = 0, 1, 2, 3, 4
 POLICY = {"auto": 0, "dp": 1, "sk": 2, "dp_1tile_sk": 3, "2tile_sk_dp": 4}
 POLICY_NAME = {v: k for k, v in POLICY.items()}
 ROLE_NAME = {0: "full", 1: "partial", 2: "owner"}
@@ -270,7 +270,7 @@ def _torch_dtypes():
     if _TORCH_DT is None:
         import torch
         _TORCH_DT = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16,
-                     torch.float8_e4m3fn: F8E4M3}
+                     torch.float8_e4m3fn: F8E4M3, torch.float64: F64}
     return _TORCH_DT
 
 

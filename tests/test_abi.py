@@ -282,3 +282,19 @@ def test_split_fixup_invalid_option():
     h = ctypes.c_void_p()
     assert L.skgemm_plan(ctypes.byref(h), 64, 64, 64, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
                          ctypes.byref(o)) == sk.ERR_INVALID_ARG
+
+
+def test_f64_plans():
+    """FP64 in needs FP64 out; its partial tiles are FP64 (8 bytes per element)."""
+    sk = _lib()
+    p = sk.Plan(1000, 700, 900, ta=sk.F64, policy="sk", force_g=100, num_cus=256, occupancy=4)
+    info = p.info()
+    assert (info["BM"], info["BN"], info["BK"]) == (64, 64, 16)
+    q = sk.Plan(1000, 700, 900, ta=sk.F64, policy="sk", force_g=50, num_cus=256, occupancy=4)
+    assert p.workspace_size() - q.workspace_size() == 50 * 64 * 64 * 8
+    for ta, tc in [(sk.F64, sk.F32), (sk.F32, sk.F64), (sk.BF16, sk.F64)]:
+        with pytest.raises(sk.SkgemmError) as e:
+            sk.Plan(100, 100, 100, ta=ta, tc=tc, num_cus=256, occupancy=1)
+        assert e.value.status == sk.ERR_UNSUPPORTED
+    ref = oracle_plan_for(info, p.model_constants(), "sk", force_g=100)
+    assert records_to_schedule(p.schedule(), info["grid"]) == S.enumerate_schedule(ref)

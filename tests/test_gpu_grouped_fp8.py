@@ -14,6 +14,8 @@ products at about 16 significant bits before the FP32 accumulate, which
 measures as a relative error of ~1.5e-5 independent of K (FP32 accumulation
 alone would give ~1e-7).
 """
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -186,3 +188,26 @@ def test_fp8_gemm_parity(shape):
         total_err = og.rel_frobenius(to_f64(C), og.gemm_f64(a, b))
         assert kernel_err <= 5e-5, (pol, kernel_err)
         assert total_err <= 6e-2, (pol, total_err)
+
+
+def test_autotuner_picks_tile_and_split(tmp_path):
+    """The grouped autotuner times every policy with the planner's tile and
+    with each 16-bit tile pinned, keeps the fastest, and caches the decision."""
+    from paper_2212_08964_amd import autotune
+    Ms = W.zipf_ms(16, lo=16, hi=1024, seed=3)
+    As, Bs = _problems(8, Ms, 512, 384)
+    Cs = [torch.empty((m, 512), dtype=torch.bfloat16, device=dev()) for m in Ms]
+    cache = str(tmp_path / "tune.json")
+    autotune._memo.clear()
+    best, times = autotune.tune_grouped(As, Bs, Cs, reps=2, cache_path=cache)
+    tiles = {json.loads(k)["tile"] and tuple(json.loads(k)["tile"]) for k in times}
+    assert {(256, 256, 64), (128, 128, 64), None} <= tiles
+    assert json.dumps(best, sort_keys=True) in times
+    assert times[json.dumps(best, sort_keys=True)] == min(times.values())
+    Cs2, _ = sk().grouped_matmul(As, Bs, **best)
+    torch.cuda.synchronize()
+    for A, B, C in zip(As, Bs, Cs2):
+        assert og.rel_frobenius(to_f64(C), og.gemm_f64(to_f64(A), to_f64(B))) <= 1e-2
+    autotune._memo.clear()
+    again, fresh = autotune.tune_grouped(As, Bs, Cs, reps=2, cache_path=cache)
+    assert again == best and fresh == {}
