@@ -166,14 +166,19 @@ def model_best_split(t: int, ipt: int, p: int, consts) -> int:
     smallest modelled time (smallest s on ties).
 
     consts is (a, b, c, d), or (a, b, c, d, e, cus): then a grid of more than
-    cus workgroups (the CU count) is costed with e per iteration instead of c,
-    since some CUs run two workgroups and the slowest one sets the time."""
+    cus workgroups (the CU count) puts n = ceil(g / cus) workgroups on some
+    CUs, and the slowest of them sets the time: an iteration costs
+    c + (e - c)(n - 1)/(occ - 1), where e is its cost with all occ = p / cus
+    workgroup slots of a CU busy."""
     a, b, c, d = consts[:4]
     e, cus = (consts[4], consts[5]) if len(consts) >= 6 else (c, p)
+    occ = max(1, p // max(cus, 1))
     best_s, best = 1, None
     for s in range(1, max(1, min(p // max(t, 1), ipt)) + 1):
         g = s * t
-        v = model_time(g, t, ipt, a, b, e if g > cus else c, d)
+        n = cdiv(g, cus)
+        cg = c if n <= 1 or occ <= 1 else c + (e - c) * (n - 1) / (occ - 1)
+        v = model_time(g, t, ipt, a, b, cg, d)
         if best is None or v < best:
             best, best_s = v, s
     return best_s

@@ -10,7 +10,7 @@ events, and fits (a, b, c, d) by least squares.  It
 prints the constants normalised to c = 1, in the form the library's model
 table uses.
 
-Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32] [BMxBNxBK, e.g. 256x256x32]
+Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32|f64] [BMxBNxBK, e.g. 256x256x32]
 """
 from __future__ import annotations
 

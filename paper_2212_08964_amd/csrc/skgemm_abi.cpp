@@ -110,7 +110,7 @@ void model_for(int dt, int v, double* m) {
     // the comparison of tile variants.  FP8 shares the 16-bit 256x256
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
-    if (dt == DT_F64) { m[0] = 5.0; m[1] = 1.5; m[2] = 0.80; m[3] = 0.80; m[4] = 1.00; return; }
+    if (dt == DT_F64) { m[0] = 4.81; m[1] = 1.24; m[2] = 0.668; m[3] = 0.751; m[4] = 2.61; return; }
     if (dt == DT_F32) { m[0] = 5.71; m[1] = 1.00; m[2] = 2.07; m[3] = 0.755; m[4] = 3.82; return; }
     if (v == 1) { m[0] = 5.21; m[1] = 1.08; m[2] = 0.599; m[3] = 0.781; m[4] = 0.860; return; }
     m[0] = 9.79; m[1] = 2.35; m[2] = 1.357; m[3] = 1.55; m[4] = 1.641;
@@ -139,12 +139,17 @@ int model_best_g(int64_t t, int64_t ipt, int64_t p, const double* m) {
 
 // Split factor s in [1, min(p / t, ipt)] that minimises the modelled time of
 // basic Stream-K over t tiles with g = s * t (the smallest s on ties).  A grid
-// larger than the CU count puts two workgroups on some CUs, and those run an
-// iteration in e (m[4]) rather than c: the slowest workgroup sets the time.
+// larger than the CU count puts n = ceil(g / cus) workgroups on some CUs, and
+// those run an iteration in c + (e - c)(n - 1)/(occ - 1) rather than c (e,
+// m[4], with all occ = p / cus slots of a CU busy): the slowest workgroup
+// sets the time.
 int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const double* m) {
     const int64_t smax = std::max<int64_t>(1, std::min(p / std::max<int64_t>(t, 1), ipt));
+    const int64_t occ = std::max<int64_t>(1, p / std::max<int64_t>(cus, 1));
     auto time_at = [&](int64_t g) {
-        const double mg[4] = {m[0], m[1], g > cus ? m[4] : m[2], m[3]};
+        const int64_t n = cdiv(g, cus);
+        const double c = n <= 1 || occ <= 1 ? m[2] : m[2] + (m[4] - m[2]) * double(n - 1) / double(occ - 1);
+        const double mg[4] = {m[0], m[1], c, m[3]};
         return model_time(g, t, ipt, mg);
     };
     int best_s = 1;

@@ -267,3 +267,9 @@ def test_split_rule_occupancy_term():
         s = S.model_best_split(t, ipt, p, (a, b, c, d, 1e9, cus))
         if t <= cus:
             assert s * t <= cus, (t, ipt, p, cus, s)
+        # two slots per CU: any grid above the CU count pays e per iteration
+        e = c * float(rng.uniform(1.0, 3.0))
+        s = S.model_best_split(t, ipt, 2 * cus, (a, b, c, d, e, cus))
+        smax = max(1, min(2 * cus // t, ipt))
+        cost = [S.model_time(k * t, t, ipt, a, b, e if k * t > cus else c, d) for k in range(1, smax + 1)]
+        assert s == 1 + int(np.argmin(cost))
