@@ -110,10 +110,10 @@ void model_for(int dt, int v, double* m) {
     // the comparison of tile variants.  FP8 shares the 16-bit 256x256
     // constants: same tile, same wave layout, twice the k per iteration at
     // twice the MFMA rate.
-    if (dt == DT_F64) { m[0] = 4.81; m[1] = 1.24; m[2] = 0.668; m[3] = 0.751; m[4] = 2.61; return; }
-    if (dt == DT_F32) { m[0] = 5.71; m[1] = 1.00; m[2] = 2.07; m[3] = 0.755; m[4] = 3.82; return; }
-    if (v == 1) { m[0] = 5.21; m[1] = 1.08; m[2] = 0.599; m[3] = 0.781; m[4] = 0.860; return; }
-    m[0] = 9.79; m[1] = 2.35; m[2] = 1.357; m[3] = 1.55; m[4] = 1.641;
+    if (dt == DT_F64) { m[0] = 4.74; m[1] = 1.49; m[2] = 0.678; m[3] = 0.778; m[4] = 1.62; return; }
+    if (dt == DT_F32) { m[0] = 6.20; m[1] = 1.25; m[2] = 2.07; m[3] = 0.569; m[4] = 3.99; return; }
+    if (v == 1) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
+    m[0] = 9.88; m[1] = 2.78; m[2] = 1.351; m[3] = 0.941; m[4] = 1.693;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

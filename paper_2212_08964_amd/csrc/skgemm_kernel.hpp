@@ -70,9 +70,10 @@ template <int DT, int V>
 constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
 
 // Waves per SIMD the register budget must allow: two workgroups per CU for
-// the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one).
+// the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one); three
+// for the small FP64 tile, whose accumulators take a quarter of the others'.
 template <int DT, int V>
-constexpr int kWavesPerEU = 2;
+constexpr int kWavesPerEU = DT == DT_F64 ? 3 : 2;
 
 // Buffer descriptor word 3 for untyped buffer loads on gfx9-family targets.
 constexpr int kBufferFlags = 0x00020000;
@@ -469,6 +470,39 @@ struct Gemm {
         }
     }
 
+    // One block's worth of partial sums kept apart from the accumulators (the
+    // running sum of the contributors ahead of this one in the split fix-up).
+    struct Blk32 { f32x16 v; };
+    struct Blk64 { f64x4 q[4]; };
+    using Blk = typename Pick<DT == DT_F64, Blk64, Blk32>::type;
+
+    // T chunk r = bits (first) or T chunk r += bits
+    static __device__ __forceinline__ void blk_take_chunk(Blk& T, int r, const u32x4& bits, bool first) {
+        if constexpr (DT == DT_F64) {
+            const f64x2 v = __builtin_bit_cast(f64x2, bits);
+            f64x4& b = T.q[r >> 1];
+            const int o = (r & 1) * 2;
+            b[o] = first ? v.x : b[o] + v.x;
+            b[o + 1] = first ? v.y : b[o + 1] + v.y;
+        } else {
+            const f32x4 v = __builtin_bit_cast(f32x4, bits);
+            T.v[4 * r] = first ? v.x : T.v[4 * r] + v.x;
+            T.v[4 * r + 1] = first ? v.y : T.v[4 * r + 1] + v.y;
+            T.v[4 * r + 2] = first ? v.z : T.v[4 * r + 2] + v.z;
+            T.v[4 * r + 3] = first ? v.w : T.v[4 * r + 3] + v.w;
+        }
+    }
+
+    // block (i, j) of acc = T + block (i, j)
+    static __device__ __forceinline__ void acc_add_blk(Acc& acc, int i, int j, const Blk& T) {
+        if constexpr (DT == DT_F64) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc.v[i][j][q] = T.q[q] + acc.v[i][j][q];
+        } else {
+            acc.v[i][j] = T.v + acc.v[i][j];
+        }
+    }
+
     static __device__ __forceinline__ void acc_add_chunk(Acc& acc, int i, int j, int r, const u32x4& bits) {
         if constexpr (DT == DT_F64) {
             const f64x2 v = __builtin_bit_cast(f64x2, bits);
@@ -788,13 +822,13 @@ struct Gemm {
         return __builtin_amdgcn_make_buffer_rsrc(slot, (short)0, SLOT * 4, kBufferFlags);
     }
 
-    // Output of one 32-row band of the wave's block, staged in `st` (FP32,
-    // rows of EPI_LD floats): each lane converts eight consecutive columns of
-    // one row and writes them with one store, predicated at the M and N edges.
-    template <int OUT>
+    // Output of 32 rows x W columns staged in `st` (FP32, rows of EPI_LD
+    // floats): each lane converts eight consecutive columns of one row and
+    // writes them with one store, predicated at the M and N edges.
+    template <int OUT, int W>
     static __device__ __forceinline__ void write_band(const Prob& a, float s, const float* st, int row0, int col,
                                                       int ncol, int lane) {
-        constexpr int LPR = WTN / 8;          // lanes per row
+        constexpr int LPR = W / 8;            // lanes per row
         constexpr int RPP = 64 / LPR;         // rows per pass
 #pragma unroll
         for (int pass = 0; pass < 32 / RPP; ++pass) {
@@ -849,37 +883,6 @@ struct Gemm {
         }
     }
 
-    // How a segment's accumulators leave the registers: 32-row bands (FM per
-    // wave) go out in two passes.  Pass 1 stores the bands in `store_mask`
-    // into this workgroup's slot (coherent stores, fragment order: float4
-    // group q of thread tid at slot[(q * THREADS + tid) * 4]) and raises the
-    // ready-flag words in `flag_words` (bit f: word f of this workgroup's flag
-    // line).  Pass 2 reduces and writes the bands in `fin_mask`: it waits for
-    // word `fw` of the flags of peers lo .. hi (this workgroup excluded), adds
-    // their slots' copy of the band in ascending peer order and writes the band
-    // through the epilogue, C = alpha * s_A * s_B * acc + beta * C, staged in
-    // the wave's own LDS area; then it clears the words it waited on.
-    //
-    //   partial share (owner fix-up):  store all bands, raise word 0
-    //   owner (owner fix-up):          reduce all bands, peers wg+1 .. last, word 0
-    //   whole tile:                    write all bands
-    //   split fix-up, contributor c:   store the bands not reduced by c; c = 0
-    //                                  and c = 1 reduce bands i with i mod 2 = c
-    //                                  over the other contributors, word c
-    //
-    // One routine serves every role, so the accumulators have a single way out
-    // of the registers (separate consumers made the register allocator spill
-    // them).  The caller guarantees all waves have left the MAC loop's LDS.
-    struct Exit {
-        int store_mask, flag_words, fin_mask, fw, lo, hi;
-    };
-    static constexpr int EPI_LD = WTN + 8;
-    static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
-    static constexpr int EPI_PER_STAGE = STAGE / EPI_BYTES;    // waves staging in one LDS stage
-    static_assert(EPI_PER_STAGE >= 1 && NW <= EPI_PER_STAGE * NS, "epilogue staging must fit in the stages");
-    static_assert(WTN % 8 == 0 && (64 % (WTN / 8)) == 0, "epilogue lane mapping");
-    static_assert(FM <= 8, "band masks");
-
     // FP64 output straight from the MFMA layout: lane l holds column l % 16
     // of rows l / 16 + 4 e of each 16x16 block, so every store instruction
     // writes four runs of 128 contiguous bytes.  Predicated at the M and N edges.
@@ -903,6 +906,115 @@ struct Gemm {
         }
     }
 
+    // How a segment's accumulators leave the registers: units of one 32x32
+    // block (FM x FN per wave, unit u = i * FN + j) go out in two passes.
+    // Pass 1 stores the units in `store_mask` into this workgroup's slot
+    // (coherent stores, fragment order: 16-byte chunk q of thread tid at byte
+    // (q * THREADS + tid) * 16) and raises the ready-flag words in
+    // `flag_words` (bit f: word f of this workgroup's flag line).  Pass 2
+    // reduces and writes the units in `fin_mask`: it waits for word `fw` of
+    // the flags of peers lo .. hi (this workgroup excluded) and sums every
+    // unit over lo .. hi in ascending order, its own accumulators in its own
+    // place (the peers ahead of it are summed apart first, then added to
+    // them), and writes the unit through the epilogue, C = alpha * s_A * s_B *
+    // acc + beta * C; then it clears the words it waited on.  The next peer's
+    // copy is loaded while the current one is added.
+    //
+    //   partial share (owner fix-up):  store all units, raise word 0
+    //   owner (owner fix-up):          reduce all units, peers wg+1 .. last, word 0
+    //   whole tile:                    write all units
+    //   split fix-up, contributor c:   the first R = min(s, REDUCERS) contributors
+    //                                  reduce: whole bands (band i to contributor
+    //                                  i mod R) when R <= FM, else units u with
+    //                                  u mod R = c; every contributor stores
+    //                                  the units it does not reduce and raises a
+    //                                  word per reducer
+    //
+    // A band reduced by one workgroup is staged and written in one pass; a
+    // band split between workgroups goes block by block.
+    //
+    // One routine serves every role, so the accumulators have a single way out
+    // of the registers (separate consumers made the register allocator spill
+    // them).  The caller guarantees all waves have left the MAC loop's LDS.
+    struct Exit {
+        int store_mask, flag_words, fin_mask, fw, lo, hi;
+    };
+    static constexpr int UNITS = FM * FN;
+    // Reducers split bands into blocks only where a wave has few bands (the
+    // large tiles' second epilogue form would push their accumulators out of
+    // the registers); REDUCERS caps the reducing contributors.
+    static constexpr bool kBlockUnits = FM < 4;
+    static constexpr int REDUCERS = kBlockUnits ? UNITS : FM;
+    static constexpr int EPI_LD = WTN + 8;                     // staged rows: one band wide
+    static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
+    static constexpr int EPI_PER_STAGE = STAGE / EPI_BYTES;    // waves staging in one LDS stage
+    static_assert(EPI_PER_STAGE >= 1 && NW <= EPI_PER_STAGE * NS, "epilogue staging must fit in the stages");
+    static_assert(UNITS <= 8, "unit masks and flag words");
+
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t peer_slot(const KArgs& ka, int k, bool valid) {
+        return __builtin_amdgcn_make_buffer_rsrc(ka.partials + (size_t)uni(k) * SLOT, (short)0,
+                                                 valid ? SLOT * 4 : 0, kBufferFlags);
+    }
+
+    // Unit (i, j) of peer slot rs into buf (zero-length rs: zeros, no access).
+    static __device__ __forceinline__ void load_unit(__amdgpu_buffer_rsrc_t rs, int i, int j, u32x4 (&buf)[CPB],
+                                                     int tid) {
+#pragma unroll
+        for (int r = 0; r < CPB; ++r)
+            buf[r] = __builtin_amdgcn_raw_buffer_load_b128(rs, (((i * FN + j) * CPB + r) * THREADS + tid) * 16, 0,
+                                                           kCoherent);
+    }
+
+    // Adds the copy of peer k (in buf) to the sum of unit (i, j).
+    static __device__ __forceinline__ void take_unit(Acc& acc, Blk& T, bool& ahead, int i, int j, int k, int wg,
+                                                     const u32x4 (&buf)[CPB]) {
+        if (k < wg) {                        // a peer ahead of this workgroup: into the apart sum
+#pragma unroll
+            for (int r = 0; r < CPB; ++r) blk_take_chunk(T, r, buf[r], !ahead);
+            ahead = true;
+        } else {
+            if (ahead) acc_add_blk(acc, i, j, T);
+            ahead = false;
+#pragma unroll
+            for (int r = 0; r < CPB; ++r) acc_add_chunk(acc, i, j, r, buf[r]);
+        }
+    }
+
+    static __device__ __forceinline__ int next_peer(int k, int wg) { return k + 1 == wg ? k + 2 : k + 1; }
+
+    static __device__ __forceinline__ void reduce_unit(const KArgs& ka, Acc& acc, int i, int j, int lo, int hi,
+                                                       int wg, int tid) {
+        Blk T;
+        bool ahead = false;
+        if constexpr (DT == DT_F64) {
+            // one copy at a time: the FP64 tile trades the pipeline for occupancy
+            for (int k = lo; k <= hi; ++k) {
+                if (k == wg) continue;
+                u32x4 buf[CPB];
+                load_unit(peer_slot(ka, k, true), i, j, buf, tid);
+                take_unit(acc, T, ahead, i, j, k, wg, buf);
+            }
+            if (ahead) acc_add_blk(acc, i, j, T);
+            return;
+        }
+        u32x4 buf0[CPB], buf1[CPB];
+        int k = lo == wg ? lo + 1 : lo;
+        load_unit(peer_slot(ka, k, k <= hi), i, j, buf0, tid);
+        while (k <= hi) {
+            int k1 = next_peer(k, wg);
+            load_unit(peer_slot(ka, k1, k1 <= hi), i, j, buf1, tid);
+            take_unit(acc, T, ahead, i, j, k, wg, buf0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (k1 > hi) break;
+            const int k2 = next_peer(k1, wg);
+            load_unit(peer_slot(ka, k2, k2 <= hi), i, j, buf0, tid);
+            take_unit(acc, T, ahead, i, j, k1, wg, buf1);
+            __builtin_amdgcn_sched_barrier(0);
+            k = k2;
+        }
+        if (ahead) acc_add_blk(acc, i, j, T);   // the peers ahead were the last ones
+    }
+
     static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, Acc& acc, int tid,
                                                   const Stages& sts, int wg, const Exit& x) {
         tid = opaque(tid);
@@ -912,24 +1024,23 @@ struct Gemm {
         if (store_mask) {
             const __amdgpu_buffer_rsrc_t own = slot_rsrc(ka.partials + (size_t)wg * SLOT);
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                if ((store_mask >> i) & 1) {
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
+                for (int j = 0; j < FN; ++j)
+                    if ((store_mask >> (i * FN + j)) & 1) {
 #pragma unroll
                         for (int r = 0; r < CPB; ++r) {
                             const int q = (i * FN + j) * CPB + r;
                             __builtin_amdgcn_raw_buffer_store_b128(acc_chunk(acc, i, j, r), own,
                                                                    (q * THREADS + tid) * 16, 0, kCoherent);
                         }
-                }
-            }
+                    }
             wait_vmem();          // this wave's coherent partial stores have completed
             __syncthreads();      // ... and so have every other wave's
             if (tid == 0) {
                 int32_t* f = ka.flags + (size_t)wg * kFlagStrideInts;
-                if (x.flag_words & 1) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (x.flag_words & 2) __hip_atomic_store(f + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int b = 0; b < 8; ++b)
+                    if ((x.flag_words >> b) & 1) __hip_atomic_store(f + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         if (!fin_mask) return;
@@ -952,50 +1063,62 @@ struct Gemm {
         float sc = a.alpha;
         if (ka.scale_a) sc *= *ka.scale_a;
         if (ka.scale_b) sc *= *ka.scale_b;
-        constexpr int LPR = WTN / 8;
-        const int col = n0 + (lane % LPR) * 8;
-        const int ncol = min(max(a.N - col, 0), 8);
+        const bool peers = hi >= lo && !(lo == wg && hi == wg);
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-            if ((fin_mask >> i) & 1) {
-                for (int k = lo; k <= hi; ++k) {
-                    if (k == wg) continue;
-                    const __amdgpu_buffer_rsrc_t rs = slot_rsrc(ka.partials + (size_t)uni(k) * SLOT);
-                    u32x4 v[FN][CPB];
+            constexpr int BAND = (1 << FN) - 1;
+            const bool whole = ((fin_mask >> (i * FN)) & BAND) == BAND;
+            if constexpr (DT == DT_F64) {
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
-#pragma unroll
-                        for (int r = 0; r < CPB; ++r) {
-                            const int q = (i * FN + j) * CPB + r;
-                            v[j][r] = __builtin_amdgcn_raw_buffer_load_b128(rs, (q * THREADS + tid) * 16, 0, kCoherent);
-                        }
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-#pragma unroll
-                        for (int r = 0; r < CPB; ++r) acc_add_chunk(acc, i, j, r, v[j][r]);
+                for (int j = 0; j < FN; ++j) {
+                    if (!((fin_mask >> (i * FN + j)) & 1)) continue;
+                    if (peers) reduce_unit(ka, acc, i, j, lo, hi, wg, tid);
+                    write_block_f64(a, double(sc), acc, i, j, m0, n0, lane);
                 }
-                if constexpr (DT == DT_F64) {
+            } else if (whole) {
+                // the whole band: reduce its blocks, stage them side by side, one write pass
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) write_block_f64(a, double(sc), acc, i, j, m0, n0, lane);
-                } else {
+                for (int j = 0; j < FN; ++j) {
+                    if (peers) reduce_unit(ka, acc, i, j, lo, hi, wg, tid);
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
+                    for (int r = 0; r < 16; ++r)
+                        st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
+                }
+                constexpr int LPR = WTN / 8;
+                const int col = n0 + (lane % LPR) * 8;
+                const int ncol = min(max(a.N - col, 0), 8);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (ka.out_dtype == DT_F32) write_band<DT_F32, WTN>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                else if (ka.out_dtype == DT_BF16) write_band<DT_BF16, WTN>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                else write_band<DT_F16, WTN>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else if constexpr (kBlockUnits) {
+                // single blocks of the band
 #pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + j * 32 + l32] = acc.v[i][j][r];
+                for (int j = 0; j < FN; ++j) {
+                    if (!((fin_mask >> (i * FN + j)) & 1)) continue;
+                    if (peers) reduce_unit(ka, acc, i, j, lo, hi, wg, tid);
+                    const int col = n0 + j * 32 + (lane % 4) * 8;
+                    const int ncol = min(max(a.N - col, 0), 8);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) st[(8 * (r >> 2) + 4 * g + (r & 3)) * EPI_LD + l32] = acc.v[i][j][r];
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (ka.out_dtype == DT_F32) write_band<DT_F32>(a, sc, st, m0 + i * 32, col, ncol, lane);
-                    else if (ka.out_dtype == DT_BF16) write_band<DT_BF16>(a, sc, st, m0 + i * 32, col, ncol, lane);
-                    else write_band<DT_F16>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                    if (ka.out_dtype == DT_F32) write_band<DT_F32, 32>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                    else if (ka.out_dtype == DT_BF16) write_band<DT_BF16, 32>(a, sc, st, m0 + i * 32, col, ncol, lane);
+                    else write_band<DT_F16, 32>(a, sc, st, m0 + i * 32, col, ncol, lane);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
         }
-        if (hi >= lo && !(lo == wg && hi == wg)) {
+        if (peers) {
             __syncthreads();      // every wave has seen every flag: clear the words waited on
             if (tid == 0)
                 for (int k = lo; k <= hi; ++k)
@@ -1156,16 +1279,21 @@ struct Gemm {
 
             mac_loop(pr, st, tile, lo, hi, acc, tid);
 
-            constexpr int ALL = (1 << FM) - 1;
-            Exit x = {0, 0, ALL, 0, 1, 0};            // whole tile: write every band
+            constexpr int ALL = (1 << UNITS) - 1;
+            Exit x = {0, 0, ALL, 0, 1, 0};            // whole tile: write every unit
             if (take_sk && a.coop_s) {
                 // split fix-up: the plan cut every Stream-K tile into coop_s
-                // equal shares, one per workgroup; wg is contributor wg mod coop_s
+                // shares, one per workgroup; wg is contributor wg mod coop_s,
+                // and the first R contributors reduce (whole bands if R <= FM)
                 const int c = wg % a.coop_s, first = wg - c;
-                constexpr int EVEN = 0x55 & ALL, ODD = 0xAA & ALL;
-                x.store_mask = c == 0 ? ODD : c == 1 ? EVEN : ALL;
-                x.flag_words = c == 0 ? 2 : c == 1 ? 1 : 3;
-                x.fin_mask = c == 0 ? EVEN : c == 1 ? ODD : 0;
+                const int R = min(a.coop_s, REDUCERS);
+                int mine = 0;
+                if (c < R)
+                    for (int u = 0; u < UNITS; ++u)
+                        if ((R <= FM ? (u / FN) % R : u % R) == c) mine |= 1 << u;
+                x.store_mask = ALL & ~mine;
+                x.flag_words = ((1 << R) - 1) & ~(c < R ? 1 << c : 0);
+                x.fin_mask = mine;
                 x.fw = c;
                 x.lo = first;
                 x.hi = first + a.coop_s - 1;
