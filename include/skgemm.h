@@ -58,7 +58,8 @@ typedef enum {
 /* Work decomposition (Work Decomposition Strategies section and
  * Data-parallel Hybridization subsection). */
 typedef enum {
-    SKGEMM_POLICY_AUTO = 0,       /* DP when tiles fill whole waves; otherwise the
+    SKGEMM_POLICY_AUTO = 0,       /* DP when tiles fill whole waves or make four
+                                     full waves or more; otherwise the
                                      remainder tiles (all tiles when there are fewer
                                      than workgroups) are split into s equal parts
                                      each, s from the grid-size model over

@@ -20,7 +20,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
-from .schedule import (FULL, OWNER, PARTIAL, Segment, cdiv, model_best_g, model_best_split, owner_of,
+from .schedule import (AUTO_MAX_WAVES, FULL, OWNER, PARTIAL, Segment, cdiv, model_best_g, model_best_split, owner_of,
                        share_start)
 
 
@@ -64,7 +64,7 @@ def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_
     ipts = {ipt for (_, _, ipt) in pl.tiles}
     auto_g = 0
     if policy == "auto":
-        if r == 0:
+        if r == 0 or (len(ipts) == 1 and w >= AUTO_MAX_WAVES):
             policy = "dp"
         elif len(ipts) == 1:
             # every tile has the same iterations: the tile-aligned split of the

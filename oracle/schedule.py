@@ -198,6 +198,10 @@ def model_best_g(t: int, ipt: int, p: int, consts) -> int:
 
 # ---------------------------------------------------------------- planning
 
+# Reading M1: the automatic policy stays data-parallel from this many full waves on.
+AUTO_MAX_WAVES = 4
+
+
 def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
               policy: str = "auto", force_g: int = 0, hybrid_min_waves: int = 2,
               model=(0.0, 0.0, 1.0, 0.0), share: str = "proportional") -> Plan:
@@ -214,7 +218,7 @@ def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
     w, r = divmod(t, p)
     auto_g = 0
     if policy == "auto":
-        if r == 0:
+        if r == 0 or w >= AUTO_MAX_WAVES:
             policy = "dp"
         else:
             count = t if w == 0 else r

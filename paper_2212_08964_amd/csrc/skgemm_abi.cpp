@@ -93,6 +93,7 @@ TileCfg tile_for(int dt, int v) {
         }
     }
     if (v == 1 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
+    if (v == 1 && dt == DT_F8) return kTileF8S;
     return TileCfg{0, 0, 0};
 }
 
@@ -107,8 +108,8 @@ void model_for(int dt, int v, double* m) {
     // workgroup per CU (calibrate.py); e: the per-iteration time of one
     // workgroup when all p co-resident workgroups run (a data-parallel problem
     // of several full waves), used for grids larger than the CU count and in
-    // the comparison of tile variants.  FP8 shares the 16-bit 256x256
-    // constants: same tile, same wave layout, twice the k per iteration at
+    // the comparison of tile variants.  FP8 shares the 16-bit constants of
+    // the same tile size: same wave layout, twice the k per iteration at
     // twice the MFMA rate.
     if (dt == DT_F64) { m[0] = 4.74; m[1] = 1.49; m[2] = 0.678; m[3] = 0.778; m[4] = 1.62; return; }
     if (dt == DT_F32) { m[0] = 6.20; m[1] = 1.25; m[2] = 2.07; m[3] = 0.569; m[4] = 3.99; return; }
@@ -339,6 +340,12 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
         const int64_t w = t / p, r = t % p;
         if (policy == SKGEMM_POLICY_AUTO) {
             if (r == 0) {
+                policy = SKGEMM_POLICY_DP;
+            } else if (uniform_ipt(*pl) && w >= kAutoMaxWaves) {
+                // enough whole waves that the remainder is a small part of the
+                // time: persistent workgroups with a fixed share of
+                // data-parallel tiles lose more to their uneven progress than
+                // a split remainder gains (FP64 8192^3: -5 %)
                 policy = SKGEMM_POLICY_DP;
             } else if (uniform_ipt(*pl)) {
                 // Tile-aligned split of the remainder: with g = s * (its tile

@@ -15,6 +15,8 @@ constexpr size_t kWsHeaderBytes = 256;     // error word lives at offset 0
 // workspace can serve plans with different grids one after another: a
 // plan's partial tiles never overlap another plan's flags.
 constexpr int kMaxFlagLines = 4096;        // Stream-K workgroups a plan may have
+// The automatic policy stays data-parallel from this many full waves on.
+constexpr int kAutoMaxWaves = 4;
 constexpr int kTraceFields = 8;
 constexpr int32_t kErrTimeout = 6;
 
@@ -25,6 +27,7 @@ constexpr TileCfg kTileF32 = {128, 128, 32, 2};
 constexpr TileCfg kTile16 = {256, 256, 64, 2};    // bf16 and f16
 constexpr TileCfg kTile16S = {128, 128, 64, 2};   // bf16 and f16, small-tile variant
 constexpr TileCfg kTileF8 = {256, 256, 128, 2};
+constexpr TileCfg kTileF8S = {128, 128, 128, 2};   // fp8, small-tile variant
 constexpr TileCfg kTileF64 = {64, 64, 16, 2};
 
 // One problem of a grouped launch (device table entry, 128 bytes).  Shapes are

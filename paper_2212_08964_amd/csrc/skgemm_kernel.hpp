@@ -53,8 +53,8 @@ typedef short i16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Tile per input type and variant, and the wave grid that covers it (WM x WN
-// wavefronts).  Variant 1 is the small 16-bit tile (cheaper partial tiles
-// and epilogues for small, memory-bound problems; two workgroups per CU).
+// wavefronts).  Variant 1 is the small 16-bit or FP8 tile (cheaper partial
+// tiles and epilogues for small, memory-bound problems; two workgroups per CU).
 template <int DT, int V> struct Cfg;
 // NS is the number of LDS stages of the MAC-loop pipeline (NS - 1 k-slabs in
 // flight while one is consumed).
@@ -62,6 +62,7 @@ template <> struct Cfg<DT_F32, 0> { static constexpr int EB = 4, BM = kTileF32.b
 template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
 template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
 template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4, NS = kTileF8.ns; };
+template <> struct Cfg<DT_F8, 1> { static constexpr int EB = 1, BM = kTileF8S.bm, BN = kTileF8S.bn, BK = kTileF8S.bk, WM = 2, WN = 2, NS = kTileF8S.ns; };
 template <> struct Cfg<DT_F64, 0> { static constexpr int EB = 8, BM = kTileF64.bm, BN = kTileF64.bn, BK = kTileF64.bk, WM = 2, WN = 2, NS = kTileF64.ns; };
 template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };

@@ -499,7 +499,7 @@ def quantize_e4m3(X, layout="row", out=None, scale=None):
     return out, scale
 
 
-def matmul_fp8(A, B, *, out_dtype=None, alpha=1.0, policy="auto", force_g=0):
+def matmul_fp8(A, B, *, out_dtype=None, alpha=1.0, policy="auto", force_g=0, tile=None):
     """FP8 GEMM of higher-precision A and B: per-tensor E4M3 quantisation of
     A (row-major) and B (column-major), then the FP8 Stream-K GEMM with the
     scales applied in the epilogue.  Returns (C, (qA, sA), (qB, sB))."""
@@ -507,5 +507,5 @@ def matmul_fp8(A, B, *, out_dtype=None, alpha=1.0, policy="auto", force_g=0):
     qa, sa = quantize_e4m3(A, "row")
     qb, sb = quantize_e4m3(B, "col")
     C = matmul(qa, qb, out_dtype=out_dtype or torch.float32, alpha=alpha, scale_a=sa, scale_b=sb,
-               policy=policy, force_g=force_g)
+               policy=policy, force_g=force_g, tile=tile)
     return C, (qa, sa), (qb, sb)

@@ -172,22 +172,23 @@ def test_quantize_edge_cases():
     assert np.array_equal(Q.cpu().view(torch.uint8).numpy(), qref)
 
 
+@pytest.mark.parametrize("tile", [None, (256, 256, 128), (128, 128, 128)])
 @pytest.mark.parametrize("shape", [(256, 256, 128), (300, 500, 700), (1024, 1024, 1024), (128, 2048, 4096),
                                    (1, 1, 1), (513, 257, 131)])
-def test_fp8_gemm_parity(shape):
+def test_fp8_gemm_parity(shape, tile):
     M, N, K = shape
     a, b = W.normal_pair(M, N, K, seed=M + K)
     A = torch.from_numpy(a).to(dev())
     B = torch.from_numpy(b).to(dev())
     for pol in ("auto", "sk", "dp"):
-        C, (qa, sa), (qb, sb) = sk().matmul_fp8(A, B, policy=pol)
+        C, (qa, sa), (qb, sb) = sk().matmul_fp8(A, B, policy=pol, tile=tile)
         torch.cuda.synchronize()
         dqa = to_f64(qa) * sa.item()
         dqb = to_f64(qb) * sb.item()
         kernel_err = og.rel_frobenius(to_f64(C), og.gemm_f64(dqa, dqb))
         total_err = og.rel_frobenius(to_f64(C), og.gemm_f64(a, b))
-        assert kernel_err <= 5e-5, (pol, kernel_err)
-        assert total_err <= 6e-2, (pol, total_err)
+        assert kernel_err <= 5e-5, (pol, tile, kernel_err)
+        assert total_err <= 6e-2, (pol, tile, total_err)
 
 
 def test_autotuner_picks_tile_and_split(tmp_path):
@@ -211,3 +212,24 @@ def test_autotuner_picks_tile_and_split(tmp_path):
     autotune._memo.clear()
     again, fresh = autotune.tune_grouped(As, Bs, Cs, reps=2, cache_path=cache)
     assert again == best and fresh == {}
+
+
+@pytest.mark.parametrize("tile", [(256, 256, 128), (128, 128, 128)])
+def test_fp8_integer_exact_split_fixup(tile):
+    """Integer-valued inputs with scale 1 (absmax 2 is not used: the values are
+    stored directly as E4M3), every policy and split grids: bit-exact."""
+    M, N, K = 700, 900, 1536
+    g = W.rng(21)
+    a = W.integer_f32(g, (M, K))
+    b = W.integer_f32(g, (K, N))
+    qa = torch.from_numpy(a).to(torch.float8_e4m3fn).to(dev())
+    qb = torch.from_numpy(np.ascontiguousarray(b.T)).to(torch.float8_e4m3fn).to(dev()).t()
+    ref = og.gemm_f64(a.astype(np.float64), b.astype(np.float64))
+    t = sk().Plan(M, N, K, 0, 1, 0, sk().F8E4M3, sk().F32, policy="dp", tile=tile).info()["t"]
+    p = sk().Plan(M, N, K, 0, 1, 0, sk().F8E4M3, sk().F32, policy="dp", tile=tile).info()["p"]
+    for pol, fg in [("auto", 0), ("dp", 0), ("sk", 0), ("sk", 2 * t), ("sk", 3 * t), ("sk", 101)]:
+        if fg > p:
+            continue
+        C = sk().matmul(qa, qb, out_dtype=torch.float32, policy=pol, force_g=fg, tile=tile)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_f64(C), ref), (pol, fg)

@@ -168,6 +168,9 @@ def test_auto_policy_regimes():
         pl = S.make_plan(256 * (16 * waves + 1), 256 * 16, 4096, 256, 256, 64, p, model=m)
         assert pl.policy == "dp_1tile_sk" and pl.sk_tiles == 16 and pl.g_sk % 16 == 0
         assert pl.g_sk // 16 == S.model_best_split(16, pl.ipt, p, m) and pl.grid == p
+    # from AUTO_MAX_WAVES full waves on the remainder is left data-parallel
+    pl = S.make_plan(256 * (16 * S.AUTO_MAX_WAVES + 1), 256 * 16, 4096, 256, 256, 64, p, model=m)
+    assert pl.policy == "dp" and pl.grid == pl.t
 
 
 @pytest.mark.parametrize("t,ipt,s", [(3, 10, 4), (7, 9, 2), (5, 64, 8), (12, 88, 10), (1, 7, 7)])
