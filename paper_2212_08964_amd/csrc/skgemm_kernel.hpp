@@ -546,19 +546,31 @@ struct Gemm {
                     else bf[buf][j] = lds_tr16<SB::ROWB>(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
                 }
             };
+            // LDS reads per step: one per K-contiguous fragment, two per
+            // transposed one
+            constexpr int READS = FM * (AKC ? 1 : 2) + FN * (BKC ? 1 : 2);
+            constexpr int MFMAS = FM * FN;
             load(0, 0);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const int cur = s & 1;
-                // The reads of step s+1 are issued ahead of the MFMAs of step
-                // s, which then cover their latency; scheduling barriers keep
-                // the compiler from sinking them back next to their users.
+                // The reads of step s+1 are interleaved one by one between
+                // the MFMAs of step s, which cover their latency; the group
+                // barriers fix that order (MFMA, read, MFMA, read, ...) and
+                // the closing barrier keeps the compiler from moving work
+                // across steps.
                 if (s + 1 < KS) load(s + 1, cur ^ 1);
-                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(af[cur][i], bf[cur][j], acc.v[i][j]);
+                if (s + 1 < KS) {
+#pragma unroll
+                    for (int k = 0; k < READS || k < MFMAS; ++k) {
+                        if (k < MFMAS) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+                        if (k < READS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+                    }
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else if constexpr (DT == DT_F64) {

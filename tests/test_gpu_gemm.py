@@ -361,3 +361,28 @@ def test_shared_workspace_across_grids():
                      stream=stream)
             sk().check_device_error(ws.data_ptr(), stream)
             assert rel(C, oracle(A, B)) <= TOL_16_OUT32, (rep, M, N, K, g)
+
+
+@pytest.mark.parametrize("fixup", ["auto", "owner"])
+def test_determinism_under_concurrent_noise(fixup):
+    """100 runs of one split plan, each beside elementwise kernels on another
+    stream (the fix-up waits and the order partials arrive in change from run to
+    run): C is bitwise identical every time.  The grid (2 shares x 64 tiles)
+    leaves room on the GPU for the other stream's work."""
+    M, N, K = 1024, 1024, 2048
+    a, b = W.normal_pair(M, N, K, seed=31)
+    A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+    tile = (128, 128, 64)
+    first = mm(A, B, policy="sk", force_g=128, out_dtype=torch.float32, tile=tile, fixup=fixup).clone()
+    noise_stream = torch.cuda.Stream()
+    X = torch.randn((2048, 2048), device=dev())
+    noise_stream.wait_stream(torch.cuda.current_stream())
+    for it in range(100):
+        with torch.cuda.stream(noise_stream):
+            for _ in range(1 + it % 3):
+                X = X * 0.999 + 0.001
+        C = sk().matmul(A, B, policy="sk", force_g=128, out_dtype=torch.float32, tile=tile, fixup=fixup)
+        torch.cuda.synchronize()
+        assert torch.equal(C, first), it
+    assert og.rel_frobenius(to_f64(first), oracle(A, B)) <= TOL_16_OUT32
