@@ -817,10 +817,10 @@ struct Gemm {
         if (khi > kfast) loop<true>(a, st, m0, n0, kfast, khi, acc, tid);
     }
 
-    // Partial tiles are stored in fragment order: float4 group q of thread tid
-    // at slot[(q * THREADS + tid) * 4], so each store instruction of the
-    // workgroup writes THREADS * 16 bytes contiguously and the reader uses the
-    // same mapping.
+    // Partial tiles are stored in fragment order: 16-byte chunk q of thread
+    // tid at byte (q * THREADS + tid) * 16 of the slot, so each store
+    // instruction of the workgroup writes THREADS * 16 bytes contiguously and
+    // the reader uses the same mapping.
     //
     // The eight XCDs keep separate, non-coherent L2 caches, and the reader of a
     // partial usually runs on another XCD.  Partials and flags therefore move
