@@ -40,18 +40,24 @@ METRIC = "TFLOP/s & % MFMA peak, Stream-K vs data-parallel tiles, bf16 shape swe
 # each scaled by its reading for a plain 256 MiB copy); valid only for the kernel sources
 # they were taken on, identified by the hash below (see profiles/skgemm_bf16_sweep_hbm_traffic.md).
 TRAFFIC_BYTES_PER_LAUNCH = 66.84e6
-TRAFFIC_SOURCES_SHA256 = "63c86718e33da28d"
+TRAFFIC_SOURCES_SHA256 = "5166c7767636855d"
 
 
 def kernel_sources_hash() -> str:
+    """Hash of the kernel sources' code (comments and blank lines left out, so
+    that a comment edit does not invalidate counters taken on the same code)."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2212_08964_amd", "csrc", "*"))):
         if f.endswith((".hpp", ".hip", ".h", ".cpp")):
             h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+            with open(f) as fh:
+                text = fh.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            code = [ln.split("//", 1)[0].rstrip() for ln in text.splitlines()]
+            h.update("\n".join(ln for ln in code if ln.strip()).encode())
     return h.hexdigest()[:16]
 PEAK_BF16_TFLOPS = 2516.6      # MI355X dense BF16 MFMA, 256 CU x 4096 flop/clk x 2.4 GHz
 HBM_GBS = 8000.0
