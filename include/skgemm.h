@@ -112,6 +112,9 @@ typedef struct {
                                      whole tile (the paper's fix-up).  Both add the
                                      shares in the same order: the results are
                                      bitwise identical. */
+    int32_t tile_waves;           /* 0 = any; else the wavefronts per workgroup of the
+                                     tile configuration (the 128x128x64 16-bit tile
+                                     exists on 4 and on 8 waves) */
 } skgemm_options_t;
 
 typedef enum { SKGEMM_SHARE_PROPORTIONAL = 0, SKGEMM_SHARE_LEADING = 1 } skgemm_share_t;
@@ -180,8 +183,8 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
  *   grouped plan, 0 for one GEMM; fields 0-2, 7, 8 and 10 are 0 then and
  *   field 9 is the total tile count), 21 share (skgemm_share_t), 22 shares per
  * tile under the split fix-up (0 = owner fix-up), 23 workgroups per CU
- * (p = CUs * field 23).
- * n is the capacity of info; up to 24 values are written. */
+ * (p = CUs * field 23), 24 wavefronts per workgroup.
+ * n is the capacity of info; up to 25 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)

@@ -38,8 +38,9 @@ _POLICIES = [
     dict(policy="auto", hybrid_min_waves=1),
 ]
 # every policy with the planner's own tile choice, then with each compiled
-# 16-bit tile pinned (candidates a dtype does not compile are skipped)
-TILES = [None, (256, 256, 64), (128, 128, 64)]
+# 16-bit tile configuration pinned (candidates a dtype does not compile are
+# skipped)
+TILES = [None, (256, 256, 64), (128, 128, 64, 4), (128, 128, 64, 8)]
 CANDIDATES = [dict(c, tile=t) for t in TILES for c in _POLICIES]
 
 _memo = {}

@@ -10,7 +10,7 @@ events, and fits (a, b, c, d) by least squares.  It
 prints the constants normalised to c = 1, in the form the library's model
 table uses.
 
-Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32|f64] [BMxBNxBK, e.g. 256x256x32]
+Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32|f64] [BMxBNxBK[xWAVES], e.g. 128x128x64x8]
 """
 from __future__ import annotations
 
@@ -52,6 +52,7 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32, "f64": sk.F64}[dtype]
     probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
     BM, BN, BK, p = probe["BM"], probe["BN"], probe["BK"], probe["p"]
+    full_tile = probe["tile"]        # (BM, BN, BK, waves): pins this exact configuration
     rows, ys, grids = [], [], []
     for t in (1, 2, 4, 8, 16, 32, 64, 128, 192):
         for ipt in (4, 16, 64):
@@ -68,7 +69,7 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
             # planner's automatic policy launches
             gs = [t * s for s in range(1, ipt + 1) if ipt % s == 0 and t * s <= p]
             for g in gs:
-                plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="sk", force_g=g, tile=(BM, BN, BK))
+                plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="sk", force_g=g, tile=full_tile)
                 nws = plan.workspace_size()
                 ws = torch.zeros(max(nws, 256), dtype=torch.uint8, device="cuda")
                 launch = _launcher(sk, plan, A, B, C, ws if nws else None, nws)
@@ -110,7 +111,7 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
         A = torch.randn(M, K, device="cuda").to(tdt)
         B = torch.randn(K, N, device="cuda").to(tdt)
         C = torch.empty(M, N, device="cuda", dtype=tdt)
-        plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="dp", tile=(BM, BN, BK))
+        plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="dp", tile=full_tile)
         launch = _launcher(sk, plan, A, B, C, None, 0)
         launch()
         torch.cuda.synchronize()

@@ -17,9 +17,17 @@ const void* kernel_fn_bf16(bool akc, bool bkc, int v) {
         return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 1>)
                    : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 1>);
     }
+    if (v == 2) {
+        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 2>)
+                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false, 2>);
+        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 2>)
+                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 2>);
+    }
     return nullptr;
 }
 
-int kernel_threads_bf16(int v) { return v == 0 ? kThreadsOf<DT_BF16, 0> : v == 1 ? kThreadsOf<DT_BF16, 1> : 0; }
+int kernel_threads_bf16(int v) {
+    return v == 0 ? kThreadsOf<DT_BF16, 0> : v == 1 ? kThreadsOf<DT_BF16, 1> : v == 2 ? kThreadsOf<DT_BF16, 2> : 0;
+}
 
 }  // namespace skg

@@ -92,7 +92,7 @@ TileCfg tile_for(int dt, int v) {
             default: return kTile16;
         }
     }
-    if (v == 1 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
+    if ((v == 1 || v == 2) && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 1 && dt == DT_F8) return kTileF8S;
     return TileCfg{0, 0, 0};
 }
@@ -113,6 +113,7 @@ void model_for(int dt, int v, double* m) {
     // twice the MFMA rate.
     if (dt == DT_F64) { m[0] = 4.74; m[1] = 1.49; m[2] = 0.678; m[3] = 0.778; m[4] = 1.62; return; }
     if (dt == DT_F32) { m[0] = 6.20; m[1] = 1.25; m[2] = 2.07; m[3] = 0.569; m[4] = 3.99; return; }
+    if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
     if (v == 1) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
     m[0] = 9.88; m[1] = 2.78; m[2] = 1.351; m[3] = 0.941; m[4] = 1.693;
 }
@@ -447,7 +448,7 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     if (ta != SKGEMM_F8E4M3 && ta != SKGEMM_F32 && tc != ta && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if (ta == SKGEMM_F32 && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if ((ta == SKGEMM_F64) != (tc == SKGEMM_F64)) return SKGEMM_ERR_UNSUPPORTED;
-    if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0) return SKGEMM_ERR_INVALID_ARG;
+    if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0 || o.tile_waves < 0) return SKGEMM_ERR_INVALID_ARG;
     if (o.raster_rows < 0 || o.raster_rows > kMaxRaster || o.xcds < 0 || o.xcds > kMaxXcds)
         return SKGEMM_ERR_INVALID_ARG;
     if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_2TILE_SK_DP) return SKGEMM_ERR_INVALID_ARG;
@@ -510,6 +511,7 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
         if (named && ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) ||
                       (o.tile_k && o.tile_k != tc_.bk)))
             continue;
+        if (o.tile_waves && kernel_threads(base->dtype, v) != 64 * o.tile_waves) continue;
         skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s(*base);
         if (!pl) return SKGEMM_ERR_HIP;
         pl->variant = v;
@@ -784,12 +786,12 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[24] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[25] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
                            pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
                            pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s,
-                           pl->occ};
-    for (int i = 0; i < n && i < 24; ++i) info[i] = v[i];
+                           pl->occ, kernel_threads(pl->dtype, pl->variant) / 64};
+    for (int i = 0; i < n && i < 25; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 

@@ -77,8 +77,9 @@ struct KArgs {
                                // split fix-up reduces it (0 = owner fix-up)
 };
 
-// Tile variants: 0 = the type's default tile, 1 = the small 16-bit tile.
-constexpr int kVariants = 2;
+// Tile variants: 0 = the type's default tile, 1 = the small 16-bit / FP8 tile
+// (four waves), 2 = the small 16-bit tile on eight waves.
+constexpr int kVariants = 3;
 
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
 int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, int variant, const KArgs& args, int grid,

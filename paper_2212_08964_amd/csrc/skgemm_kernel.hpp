@@ -54,7 +54,10 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 // Tile per input type and variant, and the wave grid that covers it (WM x WN
 // wavefronts).  Variant 1 is the small 16-bit or FP8 tile (cheaper partial
-// tiles and epilogues for small, memory-bound problems; two workgroups per CU).
+// tiles and epilogues for small, memory-bound problems; two workgroups per
+// CU); variant 2 the small 16-bit tile on eight waves (two per SIMD from one
+// workgroup: shorter iterations when a CU holds one workgroup, longer when it
+// holds two).
 template <int DT, int V> struct Cfg;
 // NS is the number of LDS stages of the MAC-loop pipeline (NS - 1 k-slabs in
 // flight while one is consumed).
@@ -66,15 +69,18 @@ template <> struct Cfg<DT_F8, 1> { static constexpr int EB = 1, BM = kTileF8S.bm
 template <> struct Cfg<DT_F64, 0> { static constexpr int EB = 8, BM = kTileF64.bm, BN = kTileF64.bn, BK = kTileF64.bk, WM = 2, WN = 2, NS = kTileF64.ns; };
 template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
+template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
+template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 
 template <int DT, int V>
 constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
 
 // Waves per SIMD the register budget must allow: two workgroups per CU for
-// the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one); three
-// for the small FP64 tile, whose accumulators take a quarter of the others'.
+// the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one, and the
+// 8-wave small tile two workgroups); three for the small FP64 tile, whose
+// accumulators take a quarter of the others'.
 template <int DT, int V>
-constexpr int kWavesPerEU = DT == DT_F64 ? 3 : 2;
+constexpr int kWavesPerEU = DT == DT_F64 ? 3 : V == 2 ? 4 : 2;
 
 // Buffer descriptor word 3 for untyped buffer loads on gfx9-family targets.
 constexpr int kBufferFlags = 0x00020000;

@@ -35,7 +35,7 @@ EXPORTED = [
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
                "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
-               "share", "coop_s", "occupancy"]
+               "share", "coop_s", "occupancy", "waves"]
 SHARE = {"proportional": 0, "leading": 1}
 SHARE_NAME = {v: k for k, v in SHARE.items()}
 FIXUP = {"auto": 0, "owner": 1}
@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int), ("force_g", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
                 ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("raster_rows", ctypes.c_int32),
-                ("xcds", ctypes.c_int32), ("share", ctypes.c_int32), ("fixup", ctypes.c_int32)]
+                ("xcds", ctypes.c_int32), ("share", ctypes.c_int32), ("fixup", ctypes.c_int32),
+                ("tile_waves", ctypes.c_int32)]
 
 
 class GroupArgs(ctypes.Structure):
@@ -132,7 +133,9 @@ class Plan:
         self._h = ctypes.c_void_p()
         o = default_options()
         if tile:
-            o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
+            o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile[:3])
+            if len(tile) > 3:
+                o.tile_waves = int(tile[3])
         o.raster_rows, o.xcds = int(raster_rows), int(xcds)
         o.share = SHARE[share] if isinstance(share, str) else int(share)
         o.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)
@@ -172,7 +175,7 @@ class Plan:
         _check(lib().skgemm_plan_info(self._h, buf, len(INFO_FIELDS)), "skgemm_plan_info")
         d = dict(zip(INFO_FIELDS, list(buf)))
         d["policy_name"] = POLICY_NAME[d["policy"]]
-        d["tile"] = (d["BM"], d["BN"], d["BK"])
+        d["tile"] = (d["BM"], d["BN"], d["BK"], d["waves"])   # pins this exact configuration
         d["share_name"] = SHARE_NAME[d["share"]]
         return d
 
@@ -216,7 +219,9 @@ class GroupedPlan(Plan):
             raise ValueError("Ms, Ns, Ks must have the same length")
         o = default_options()
         if tile:
-            o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile)
+            o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile[:3])
+            if len(tile) > 3:
+                o.tile_waves = int(tile[3])
         o.raster_rows, o.xcds = int(raster_rows), int(xcds)
         o.share = SHARE[share] if isinstance(share, str) else int(share)
         o.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)

@@ -145,7 +145,7 @@ def test_workspace_scales_with_grid_not_problem():
         small = sk.Plan(300, 300, 4096, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1, tile=tile)
         big = sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
                       tile=tile)
-        assert small.info()["tile"] == big.info()["tile"] == tile
+        assert small.info()["tile"][:3] == big.info()["tile"][:3] == tile
         assert small.workspace_size() == big.workspace_size()
     # one FP32 partial tile per workgroup: the small tile needs a quarter of the partial storage
     w = {t: sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,

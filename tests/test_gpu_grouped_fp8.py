@@ -48,7 +48,7 @@ def _problems(seed, Ms, N, K, dtype=torch.bfloat16):
 
 
 @pytest.mark.parametrize("policy", ["auto", "sk", "dp", "2tile_sk_dp", "dp_1tile_sk"])
-@pytest.mark.parametrize("tile", [None, (256, 256, 64), (128, 128, 64)])
+@pytest.mark.parametrize("tile", [None, (256, 256, 64), (128, 128, 64, 4), (128, 128, 64, 8)])
 def test_grouped_zipf_parity(policy, tile):
     Ms = W.zipf_ms(24, lo=16, hi=1024, seed=1)
     As, Bs = _problems(2, Ms, 1024, 512)
@@ -74,7 +74,7 @@ def test_grouped_ragged_mixed_shapes_bf16_out():
             assert og.rel_frobenius(to_f64(C), ref) <= 1e-2
 
 
-@pytest.mark.parametrize("tile", [(256, 256, 64), (128, 128, 64)])
+@pytest.mark.parametrize("tile", [(256, 256, 64), (128, 128, 64, 4), (128, 128, 64, 8)])
 def test_grouped_integer_exact_forced_grids(tile):
     Ms = [37, 300, 16, 520]
     g = W.rng(4)
@@ -89,7 +89,7 @@ def test_grouped_integer_exact_forced_grids(tile):
 
 
 @pytest.mark.parametrize("policy", ["auto", "sk", "2tile_sk_dp"])
-@pytest.mark.parametrize("tile", [None, (128, 128, 64)])
+@pytest.mark.parametrize("tile", [None, (128, 128, 64, 4), (128, 128, 64, 8)])
 def test_grouped_trace_matches_enumerator(policy, tile):
     Ms = W.zipf_ms(64, seed=0)
     shapes = [(m, 4096, 2048) for m in Ms]
@@ -202,7 +202,7 @@ def test_autotuner_picks_tile_and_split(tmp_path):
     autotune._memo.clear()
     best, times = autotune.tune_grouped(As, Bs, Cs, reps=2, cache_path=cache)
     tiles = {json.loads(k)["tile"] and tuple(json.loads(k)["tile"]) for k in times}
-    assert {(256, 256, 64), (128, 128, 64), None} <= tiles
+    assert {(256, 256, 64), (128, 128, 64, 4), (128, 128, 64, 8), None} <= tiles
     assert json.dumps(best, sort_keys=True) in times
     assert times[json.dumps(best, sort_keys=True)] == min(times.values())
     Cs2, _ = sk().grouped_matmul(As, Bs, **best)
