@@ -39,8 +39,8 @@ METRIC = "TFLOP/s & % MFMA peak, Stream-K vs data-parallel tiles, bf16 shape swe
 # HBM bytes per launch of the sweep, from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE,
 # each scaled by its reading for a plain 256 MiB copy); valid only for the kernel sources
 # they were taken on, identified by the hash below (see profiles/skgemm_bf16_sweep_hbm_traffic.md).
-TRAFFIC_BYTES_PER_LAUNCH = 66.84e6
-TRAFFIC_SOURCES_SHA256 = "5166c7767636855d"
+TRAFFIC_BYTES_PER_LAUNCH = 67.08e6
+TRAFFIC_SOURCES_SHA256 = "35aecb80530d9523"
 
 
 def kernel_sources_hash() -> str:
@@ -503,7 +503,8 @@ def main():
                                "bf16 out, row-major",
                    "n_shapes": n, "policy": "auto (DP waves + Stream-K remainder)",
                    "baseline": "same kernel and tile, policy=dp (one workgroup per tile)",
-                   "tiles": "256x256x64, or 128x128x64 where the model predicts it faster (same tile for both)",
+                   "tiles": "256x256x64, or 128x128x64 (4 or 8 waves) where the planner predicts it faster "
+                            "(same tile for both)",
                    "total_gflop": round(total_flops / 1e9, 1), "parallelism": "single GPU"},
         "pct_mfma_peak": round(100.0 * value / PEAK_BF16_TFLOPS, 2),
         "dp_value": round(dp_value, 3),
