@@ -227,6 +227,14 @@ struct Slab {
         return tail ? min(max(lim - chunk_col(j, tid) * VE, 0), VE) : VE;
     }
 
+    // A chunk that reaches past the inner edge but whose 16 bytes all lie
+    // inside the buffer range (nr bytes from the slab origin) is loaded whole:
+    // the bytes past the edge belong to the rest of the row (or the gap up to
+    // the leading dimension, or the next row) and are cleared once the chunk
+    // has landed.  Only a chunk that reaches past the operand's end needs the
+    // element-by-element path.
+    __device__ __forceinline__ bool whole(int j, uint32_t nr) const { return voff[j] + 16u <= nr; }
+
     // Issue the direct-to-LDS loads of iteration `it` (counted from kbeg), whose
     // first k is k0, into the stage at `lds`.  EDGE = false: the caller knows
     // the slab is wholly inside the inner edge (no per-chunk checks).
@@ -239,31 +247,50 @@ struct Slab {
         const int w = uni(tid >> 6);
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
-            const uint32_t off = (!EDGE || keep(j, tail, lim, tid) == VE) ? voff[j] : 0x80000000u;
+            uint32_t off = voff[j];
+            if constexpr (EDGE) {
+                const int kp = keep(j, tail, lim, tid);
+                if (kp == 0 || (kp < VE && !whole(j, uint32_t(d[2])))) off = 0x80000000u;
+            }
             dma16(d, off, lds_addr(lds + (w + j * NW) * 1024));
         }
     }
 
-    // After the stage's loads have landed: write the partly-inside chunks of
-    // an edge slab element by element.
+    // After the stage's loads have landed: clear the bytes past the edge of
+    // the partly-inside chunks that were loaded whole, and write the others
+    // element by element.
     __device__ __forceinline__ void fix_edge(int it, int k0, int K, int o0, int dout, unsigned char* lds,
                                              int tid) const {
         const bool tail = KC ? (k0 + BK > K) : (o0 + R > dout);
         if (!tail) return;
         tid = opaque(tid);   // recompute the chunk positions here rather than keep issue()'s live
         const int lim = KC ? (K - k0) : (dout - o0);
-        const __amdgpu_buffer_rsrc_t rs = rsrc(it);
+        const uint32_t nr = uint32_t(uni(nrec(it)));
         const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
         for (int j = 0; j < PER_WAVE; ++j) {
             const int kp = keep(j, tail, lim, tid);
-            if (kp > 0 && kp < VE) {
-                // Element by element, in a loop that is not unrolled: this
-                // runs once per tile at most, and an unrolled form needs
-                // enough registers to push the accumulators out to scratch.
-                // Elements past the edge are loaded too (inside the operand's
-                // buffer range, or zero past it) and replaced by zero.
+            // a chunk that starts past the operand's end has landed as zeros
+            if (kp > 0 && kp < VE && voff[j] < nr) {
                 unsigned char* dst = lds + (w + j * NW) * 1024 + lane * 16;
+                if (whole(j, nr)) {
+                    u32x4 v = *reinterpret_cast<const u32x4*>(dst);
+                    const int nb = kp * EB;   // bytes inside the edge
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int kb = min(max(nb - 4 * q, 0), 4);
+                        v[q] &= kb == 4 ? 0xffffffffu : (1u << (8 * kb)) - 1u;
+                    }
+                    *reinterpret_cast<u32x4*>(dst) = v;
+                    continue;
+                }
+                // Element by element, in a loop that is not unrolled: this
+                // runs only for chunks that straddle the operand's end, and
+                // an unrolled form needs enough registers to push the
+                // accumulators out to scratch.  Elements past the edge are
+                // loaded too (zero past the operand's end) and replaced by
+                // zero.
+                const __amdgpu_buffer_rsrc_t rs = rsrc(it);
                 const int off = int(voff[j]);
 #pragma unroll 1
                 for (int e = 0; e < VE; ++e) {
@@ -713,27 +740,30 @@ struct Gemm {
     // iteration it + NS - 1 into stage `nxt` (freed by iteration it - 1, which
     // every wave finished before the last barrier), run the MFMAs of `cur`,
     // wait for the slab of iteration it + 1 (stage `fix`) and synchronise.
-    // EDGE = false: every slab of [kbeg, kend) lies inside the operands'
-    // inner edges.
-    template <bool EDGE>
+    // Slabs of iterations from kedge on are loaded with per-chunk checks
+    // against the operands' inner edges (and fixed up once they have landed);
+    // the others lie wholly inside them.
     static __device__ __forceinline__ bool step(const Prob& a, const SA& sa, const SB& sb, int it, int kbeg,
-                                                int kend, int m0, int n0, unsigned char* cur, unsigned char* nxt,
-                                                unsigned char* fix, Acc& acc, int tid) {
+                                                int kend, int kedge, int m0, int n0, unsigned char* cur,
+                                                unsigned char* nxt, unsigned char* fix, Acc& acc, int tid) {
         const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
         const int ahead = it + NS - 1;
         if (ahead < kend) {
-            sa.template issue<EDGE>(ahead - kbeg, ahead * BK, a.K, m0, a.M, nxt, tid);
-            sb.template issue<EDGE>(ahead - kbeg, ahead * BK, a.K, n0, a.N, nxt + SA::BYTES, tid);
+            if (ahead < kedge) {
+                sa.template issue<false>(ahead - kbeg, ahead * BK, a.K, m0, a.M, nxt, tid);
+                sb.template issue<false>(ahead - kbeg, ahead * BK, a.K, n0, a.N, nxt + SA::BYTES, tid);
+            } else {
+                sa.template issue<true>(ahead - kbeg, ahead * BK, a.K, m0, a.M, nxt, tid);
+                sb.template issue<true>(ahead - kbeg, ahead * BK, a.K, n0, a.N, nxt + SA::BYTES, tid);
+            }
         }
         compute(cur, cur + SA::BYTES, acc, wm, wn, lane);
         const bool more = it + 1 < kend;
         if (more) {
-            if constexpr (EDGE) {
-                wait_vmem();
+            wait_slab(min(NS - 2, kend - 2 - it));
+            if (it + 1 >= kedge) {
                 sa.fix_edge(it + 1 - kbeg, (it + 1) * BK, a.K, m0, a.M, fix, tid);
                 sb.fix_edge(it + 1 - kbeg, (it + 1) * BK, a.K, n0, a.N, fix + SA::BYTES, tid);
-            } else {
-                wait_slab(min(NS - 2, kend - 2 - it));
             }
         }
         step_barrier();
@@ -742,50 +772,61 @@ struct Gemm {
 
     // Iterations kk + U (U = 0 .. NS-1) of the pipeline, each on its own
     // stage; false once the last iteration has been consumed.
-    template <bool EDGE, int... U>
+    template <int... U>
     static __device__ __forceinline__ bool steps(const Prob& a, const SA& sa, const SB& sb, int kk, int kbeg,
-                                                 int kend, int m0, int n0, const Stages& st, Acc& acc, int tid,
-                                                 std::integer_sequence<int, U...>) {
-        return (step<EDGE>(a, sa, sb, kk + U, kbeg, kend, m0, n0, st.template at<U>(),
-                           st.template at<(U + NS - 1) % NS>(), st.template at<(U + 1) % NS>(), acc, tid) &&
+                                                 int kend, int kedge, int m0, int n0, const Stages& st, Acc& acc,
+                                                 int tid, std::integer_sequence<int, U...>) {
+        return (step(a, sa, sb, kk + U, kbeg, kend, kedge, m0, n0, st.template at<U>(),
+                     st.template at<(U + NS - 1) % NS>(), st.template at<(U + 1) % NS>(), acc, tid) &&
                 ...);
     }
 
+    // Slab kbeg + J into stage J, checked from kedge on.
+    template <int J>
+    static __device__ __forceinline__ void prologue_one(const Prob& a, const SA& sa, const SB& sb, int kbeg,
+                                                        int kend, int kedge, int m0, int n0, const Stages& st,
+                                                        int tid) {
+        const int it = kbeg + J;
+        if (it >= kend) return;
+        if (it < kedge) {
+            sa.template issue<false>(J, it * BK, a.K, m0, a.M, st.template at<J>(), tid);
+            sb.template issue<false>(J, it * BK, a.K, n0, a.N, st.template at<J>() + SA::BYTES, tid);
+        } else {
+            sa.template issue<true>(J, it * BK, a.K, m0, a.M, st.template at<J>(), tid);
+            sb.template issue<true>(J, it * BK, a.K, n0, a.N, st.template at<J>() + SA::BYTES, tid);
+        }
+    }
+
     // Prologue: slab kbeg + J into stage J (J = 0 .. NS-2).
-    template <bool EDGE, int... J>
+    template <int... J>
     static __device__ __forceinline__ void prologue(const Prob& a, const SA& sa, const SB& sb, int kbeg, int kend,
-                                                    int m0, int n0, const Stages& st, int tid,
+                                                    int kedge, int m0, int n0, const Stages& st, int tid,
                                                     std::integer_sequence<int, J...>) {
-        (((kbeg + J < kend)
-              ? (sa.template issue<EDGE>(J, (kbeg + J) * BK, a.K, m0, a.M, st.template at<J>(), tid),
-                 sb.template issue<EDGE>(J, (kbeg + J) * BK, a.K, n0, a.N, st.template at<J>() + SA::BYTES, tid))
-              : void()),
-         ...);
+        (prologue_one<J>(a, sa, sb, kbeg, kend, kedge, m0, n0, st, tid), ...);
     }
 
     // Iterations [kbeg, kend) of a tile: the first NS - 1 slabs are loaded
     // up front, then each step consumes one stage and refills the stage the
     // previous step consumed.  Iteration it uses stage (it - kbeg) mod NS.
-    template <bool EDGE>
+    // Slabs of iterations from kedge on get per-chunk edge checks, inside the
+    // same pipeline.
     static __device__ __forceinline__ void loop(const Prob& a, const Stages& st, int m0, int n0, int kbeg, int kend,
-                                                Acc& acc, int tid) {
+                                                int kedge, Acc& acc, int tid) {
         tid = opaque(tid);
         SA sa;
         SB sb;
         sa.init(a.A, a.lda, m0, a.M, kbeg, a.K, tid);
         sb.init(a.B, a.ldb, n0, a.N, kbeg, a.K, tid);
         __syncthreads();   // LDS may still be in use (previous epilogue or loop)
-        prologue<EDGE>(a, sa, sb, kbeg, kend, m0, n0, st, tid, std::make_integer_sequence<int, NS - 1>{});
-        if constexpr (EDGE) {
-            wait_vmem();
+        prologue(a, sa, sb, kbeg, kend, kedge, m0, n0, st, tid, std::make_integer_sequence<int, NS - 1>{});
+        wait_slab(min(NS - 2, kend - 1 - kbeg));
+        if (kbeg >= kedge) {
             sa.fix_edge(0, kbeg * BK, a.K, m0, a.M, st.template at<0>(), tid);
             sb.fix_edge(0, kbeg * BK, a.K, n0, a.N, st.template at<0>() + SA::BYTES, tid);
-        } else {
-            wait_slab(min(NS - 2, kend - 1 - kbeg));
         }
         step_barrier();
         for (int kk = kbeg;; kk += NS)
-            if (!steps<EDGE>(a, sa, sb, kk, kbeg, kend, m0, n0, st, acc, tid, std::make_integer_sequence<int, NS>{}))
+            if (!steps(a, sa, sb, kk, kbeg, kend, kedge, m0, n0, st, acc, tid, std::make_integer_sequence<int, NS>{}))
                 return;
     }
 
@@ -818,9 +859,8 @@ struct Gemm {
         const bool check_last = ((AKC || BKC) && a.K % BK != 0) || a_edge || b_edge;
         // rows shorter than a chunk: chunks of earlier rows can reach the end too
         const bool check_all = (a_edge && a.lda * EB < 16) || (b_edge && a.ldb * EB < 16);
-        const int kfast = check_all ? klo : (check_last && khi > klast) ? max(klo, klast) : khi;
-        if (kfast > klo) loop<false>(a, st, m0, n0, klo, kfast, acc, tid);
-        if (khi > kfast) loop<true>(a, st, m0, n0, kfast, khi, acc, tid);
+        const int kedge = check_all ? klo : check_last ? klast : khi;
+        loop(a, st, m0, n0, klo, khi, kedge, acc, tid);
     }
 
     // Partial tiles are stored in fragment order: 16-byte chunk q of thread
