@@ -6,10 +6,13 @@
 // Three launches, all HBM-bound: absmax_partial reads X once (16-byte loads
 // when rows are aligned) and writes one maximum per workgroup; absmax_finish
 // (one workgroup) reduces those and writes s on the device, so no host round
-// trip or memset is needed and the sequence can be captured in a graph;
-// quantize_tiles reads X again in 64x64 tiles through LDS, so it can change
-// the layout on the way out (the FP8 GEMM wants both operands K-contiguous)
-// with coalesced reads and writes on both sides.
+// trip or memset is needed and the sequence can be captured in a graph; a
+// third kernel reads X again and writes the codes.  Where every row is
+// 16-byte aligned that is quantize_rows (same storage order: 16 elements per
+// thread, 16-byte loads and stores) or quantize_transpose (the FP8 GEMM
+// wants both operands K-contiguous, so a row-major B changes order on the
+// way out: 64x64 tiles through LDS, 16-byte loads and stores); otherwise
+// quantize_tiles (element loads, 4-byte stores, any alignment).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -152,6 +155,99 @@ __global__ void __launch_bounds__(kQThreads) quantize_tiles(const void* x, int64
     }
 }
 
+// Eight codes of two 16-byte input words of a 16-bit type, or four of one
+// FP32 word: the input vector's elements in order.
+template <int DT>
+__device__ __forceinline__ void unpack(const uint4& u, float* v) {
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if constexpr (DT == DT_F32) {
+            v[e] = __builtin_bit_cast(float, w[e]);
+        } else if constexpr (DT == DT_BF16) {
+            v[2 * e] = __builtin_bit_cast(float, w[e] << 16);
+            v[2 * e + 1] = __builtin_bit_cast(float, w[e] & 0xffff0000u);
+        } else {
+            v[2 * e] = float(__builtin_bit_cast(_Float16, uint16_t(w[e])));
+            v[2 * e + 1] = float(__builtin_bit_cast(_Float16, uint16_t(w[e] >> 16)));
+        }
+    }
+}
+
+// Sixteen codes of v[0..15] as one 16-byte word.
+__device__ __forceinline__ uint4 codes16(const float* v, float s) {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        w[i] = to_e4m3x2<false>(v[4 * i], v[4 * i + 1], s, 0u);
+        w[i] = to_e4m3x2<true>(v[4 * i + 2], v[4 * i + 3], s, w[i]);
+    }
+    return uint4{w[0], w[1], w[2], w[3]};
+}
+
+// Same storage order in and out (`outer` rows of `inner` contiguous
+// elements), inner a multiple of 16 and every row 16-byte aligned on both
+// sides: each thread converts 16 consecutive elements of one row with 16-byte
+// loads and one 16-byte store.
+template <int DT>
+__global__ void __launch_bounds__(kQThreads) quantize_rows(const void* x, int64_t groups, int64_t per_row, int64_t ldx,
+                                                           uint8_t* q, int64_t ldq, const float* scale) {
+    constexpr int EB = DT == DT_F32 ? 4 : 2, NV = 16 * EB / 16;   // input vectors per group
+    const int64_t g = int64_t(blockIdx.x) * kQThreads + threadIdx.x;
+    if (g >= groups) return;
+    const int64_t o = g / per_row, c = (g - o * per_row) * 16;
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(x) + (o * ldx + c) * EB);
+    uint4 u[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) u[k] = src[k];
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) unpack<DT>(u[k], v + k * (16 / NV));
+    *reinterpret_cast<uint4*>(q + o * ldq + c) = codes16(v, *scale);
+}
+
+// Transposing form: X stored as `outer` rows of `inner` contiguous elements,
+// Q stored as `inner` rows of `outer` contiguous codes.  One 64 x 64 tile per
+// workgroup through LDS: 16-byte loads along X's rows, 16-byte stores along
+// Q's.  Needs inner a multiple of the elements per 16 bytes, outer a multiple
+// of 16 and 16-byte aligned rows on both sides.
+template <int DT>
+__global__ void __launch_bounds__(kQThreads) quantize_transpose(const void* x, int64_t outer, int64_t inner,
+                                                                int64_t ldx, uint8_t* q, int64_t ldq,
+                                                                const float* scale) {
+    constexpr int EB = DT == DT_F32 ? 4 : 2, VE = 16 / EB, VPR = 64 / VE, LOADS = 64 * VPR / kQThreads;
+    __shared__ float tile[64][65];
+    const int64_t i0 = int64_t(blockIdx.x) * 64, o0 = int64_t(blockIdx.y) * 64;
+    const int t = threadIdx.x;
+    uint4 u[LOADS];
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) {
+        const int idx = t + k * kQThreads, row = idx / VPR, vc = idx % VPR;
+        const int64_t o = o0 + row, i = i0 + int64_t(vc) * VE;
+        u[k] = uint4{0u, 0u, 0u, 0u};
+        if (o < outer && i < inner)
+            u[k] = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(x) + (o * ldx + i) * EB);
+    }
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) {
+        const int idx = t + k * kQThreads, row = idx / VPR, vc = idx % VPR;
+        float v[VE];
+        unpack<DT>(u[k], v);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) tile[row][vc * VE + e] = v[e];
+    }
+    __syncthreads();
+    // Q row (X column) and group of 16 X rows: four neighbouring lanes write
+    // the 64 contiguous codes of one Q row
+    const int ic = t >> 2, rg = t & 3;
+    const int64_t i = i0 + ic, o = o0 + 16 * rg;
+    if (i >= inner || o >= outer) return;
+    float v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = tile[16 * rg + e][ic];
+    *reinterpret_cast<uint4*>(q + i * ldq + o) = codes16(v, *scale);
+}
+
 int quant_workspace_floats() { return kAbsmaxBlocks; }
 
 int launch_quantize(int dtype, const void* x, int64_t rows, int64_t cols, int64_t ldx, bool x_col, uint8_t* q,
@@ -164,25 +260,32 @@ int launch_quantize(int dtype, const void* x, int64_t rows, int64_t cols, int64_
     const int blocks = int(std::max<int64_t>(1, std::min<int64_t>(kAbsmaxBlocks, (work + kQThreads - 1) / kQThreads)));
     const dim3 tiles(unsigned((cols + 63) / 64), unsigned((rows + 63) / 64));
     const bool any = rows > 0 && cols > 0;
+    // vectorised forms where every row is 16-byte aligned on both sides
+    const auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    const bool rows_ok = (ldx * eb) % 16 == 0 && a16(x) && ldq % 16 == 0 && a16(q);
+    const int form = !any || !rows_ok ? 0
+                     : x_col == q_col ? (inner % 16 == 0 ? 1 : 0)
+                                      : (inner % (16 / eb) == 0 && outer % 16 == 0 ? 2 : 0);
+    const int64_t groups = outer * (inner / 16);
+    const unsigned row_blocks = unsigned((groups + kQThreads - 1) / kQThreads);
+    const dim3 ttiles(unsigned((inner + 63) / 64), unsigned((outer + 63) / 64));
+#define SKG_QUANT(DT_)                                                                                         \
+    absmax_partial<DT_><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);                     \
+    absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);                                           \
+    if (form == 1)                                                                                             \
+        quantize_rows<DT_><<<row_blocks, kQThreads, 0, st>>>(x, groups, inner / 16, ldx, q, ldq, scale);       \
+    else if (form == 2)                                                                                        \
+        quantize_transpose<DT_><<<ttiles, kQThreads, 0, st>>>(x, outer, inner, ldx, q, ldq, scale);            \
+    else if (any)                                                                                              \
+        quantize_tiles<DT_><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
     switch (dtype) {
-        case DT_F32:
-            absmax_partial<DT_F32><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);
-            absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);
-            if (any) quantize_tiles<DT_F32><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
-            break;
-        case DT_BF16:
-            absmax_partial<DT_BF16><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);
-            absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);
-            if (any) quantize_tiles<DT_BF16><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
-            break;
-        case DT_F16:
-            absmax_partial<DT_F16><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);
-            absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);
-            if (any) quantize_tiles<DT_F16><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
-            break;
+        case DT_F32: SKG_QUANT(DT_F32) break;
+        case DT_BF16: SKG_QUANT(DT_BF16) break;
+        case DT_F16: SKG_QUANT(DT_F16) break;
         default:
             return int(hipErrorInvalidValue);
     }
+#undef SKG_QUANT
     return int(hipGetLastError());
 }
 
