@@ -115,6 +115,14 @@ typedef struct {
     int32_t tile_waves;           /* 0 = any; else the wavefronts per workgroup of the
                                      tile configuration (the 128x128x64 16-bit tile
                                      exists on 4 and on 8 waves) */
+    int32_t spin_limit;           /* 0 = default (2^22): polls of a peer's ready flag
+                                     (a short sleep between polls) after which a
+                                     fix-up wait gives up: it sets the workspace's
+                                     error word (SKGEMM_ERR_TIMEOUT from
+                                     skgemm_check_device_error) and the workgroup
+                                     finishes with the sum it has, so the kernel
+                                     always exits.  A small value forces that path
+                                     (tests of the error handling). */
 } skgemm_options_t;
 
 typedef enum { SKGEMM_SHARE_PROPORTIONAL = 0, SKGEMM_SHARE_LEADING = 1 } skgemm_share_t;

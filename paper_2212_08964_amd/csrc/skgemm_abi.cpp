@@ -41,6 +41,7 @@ struct skgemm_plan_s {
     bool sk_first;
     int p, occ, hybrid_min_waves;   // p = CUs * occ co-resident workgroups
     int raster, xcds;  // tile raster group rows; XCD count for the workgroup permutation
+    int spin_limit;    // polls before a fix-up wait gives up
     bool share_prop;   // proportional (else leading) even share
     bool fixup_owner;  // the owner alone reduces every split tile
     int coop_s;        // >= 2: split fix-up over tiles cut into coop_s one-segment shares
@@ -286,6 +287,9 @@ constexpr int64_t kMaxDim = (int64_t(1) << 31) - 1;
 constexpr int kDefaultRaster = 8, kMaxRaster = 1 << 16;
 // MI355X hands workgroups round-robin to its 8 XCDs.
 constexpr int kDefaultXcds = 8, kMaxXcds = 64;
+// Polls of a ready flag before a fix-up wait gives up (each poll sleeps about
+// 128 clocks: well over a second in all, against microseconds for a hand-off).
+constexpr int kDefaultSpinLimit = 1 << 22;
 
 }  // namespace
 
@@ -448,7 +452,8 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     if (ta != SKGEMM_F8E4M3 && ta != SKGEMM_F32 && tc != ta && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if (ta == SKGEMM_F32 && tc != SKGEMM_F32) return SKGEMM_ERR_UNSUPPORTED;
     if ((ta == SKGEMM_F64) != (tc == SKGEMM_F64)) return SKGEMM_ERR_UNSUPPORTED;
-    if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0 || o.tile_waves < 0) return SKGEMM_ERR_INVALID_ARG;
+    if (o.force_g < 0 || o.num_cus < 0 || o.occupancy < 0 || o.tile_waves < 0 || o.spin_limit < 0)
+        return SKGEMM_ERR_INVALID_ARG;
     if (o.raster_rows < 0 || o.raster_rows > kMaxRaster || o.xcds < 0 || o.xcds > kMaxXcds)
         return SKGEMM_ERR_INVALID_ARG;
     if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_2TILE_SK_DP) return SKGEMM_ERR_INVALID_ARG;
@@ -468,6 +473,7 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     pl->share_prop = o.share == SKGEMM_SHARE_PROPORTIONAL;
     pl->raster = o.raster_rows ? o.raster_rows : kDefaultRaster;
     pl->xcds = o.xcds ? o.xcds : kDefaultXcds;
+    pl->spin_limit = o.spin_limit ? o.spin_limit : kDefaultSpinLimit;
     return SKGEMM_OK;
 }
 
@@ -695,7 +701,7 @@ static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspac
     }
     a->trace = trace;
     a->trace_per_wg = trace ? pl->max_segs : 0;
-    a->spin_limit = 1 << 22;
+    a->spin_limit = pl->spin_limit;
     a->sk_prop = pl->share_prop ? 1 : 0;
     a->raster = pl->raster;
     a->xcds = pl->xcds;

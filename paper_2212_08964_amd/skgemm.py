@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
                 ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("raster_rows", ctypes.c_int32),
                 ("xcds", ctypes.c_int32), ("share", ctypes.c_int32), ("fixup", ctypes.c_int32),
-                ("tile_waves", ctypes.c_int32)]
+                ("tile_waves", ctypes.c_int32), ("spin_limit", ctypes.c_int32)]
 
 
 class GroupArgs(ctypes.Structure):
@@ -129,7 +129,7 @@ class Plan:
 
     def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0, share="proportional", fixup="auto"):
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto", spin_limit=0):
         self._h = ctypes.c_void_p()
         o = default_options()
         if tile:
@@ -143,6 +143,7 @@ class Plan:
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
         o.num_cus = int(num_cus)
+        o.spin_limit = int(spin_limit)
         o.occupancy = int(occupancy)
         tc = ta if tc is None else tc
         _check(lib().skgemm_plan(ctypes.byref(self._h), int(M), int(N), int(K), la, lb, lc, ta, ta, tc,
@@ -212,7 +213,7 @@ class GroupedPlan(Plan):
 
     def __init__(self, Ms, Ns, Ks, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0, share="proportional", fixup="auto"):
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto", spin_limit=0):
         self._h = ctypes.c_void_p()
         G = len(Ms)
         if not (len(Ns) == len(Ks) == G):
@@ -229,6 +230,7 @@ class GroupedPlan(Plan):
         o.force_g = int(force_g)
         o.hybrid_min_waves = int(hybrid_min_waves)
         o.num_cus = int(num_cus)
+        o.spin_limit = int(spin_limit)
         o.occupancy = int(occupancy)
         tc = ta if tc is None else tc
         arr = ctypes.c_int64 * max(G, 1)

@@ -284,6 +284,29 @@ def test_split_fixup_invalid_option():
                          ctypes.byref(o)) == sk.ERR_INVALID_ARG
 
 
+def test_spin_limit_option():
+    """A negative spin limit is refused; 0 (the default) and positive limits plan,
+    and the options structure the binding passes has the header's size (the
+    library clears exactly that many bytes in skgemm_default_options)."""
+    sk = _lib()
+    L = sk.lib()
+    h = ctypes.c_void_p()
+    o = sk.default_options()
+    o.spin_limit = -1
+    assert L.skgemm_plan(ctypes.byref(h), 64, 64, 64, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                         ctypes.byref(o)) == sk.ERR_INVALID_ARG
+    for lim in (0, 1, 1000):
+        p = sk.Plan(300, 200, 900, ta=sk.BF16, policy="sk", num_cus=256, occupancy=2, spin_limit=lim)
+        assert p.info()["grid"] > 0
+    # 14 int32 fields, in the header's order; the padding after them is not
+    # touched by the library
+    assert ctypes.sizeof(sk.Options) == 14 * 4
+    guard = (ctypes.c_int32 * 16)(*([0x5A5A5A5A] * 16))
+    L.skgemm_default_options(ctypes.cast(guard, ctypes.POINTER(sk.Options)))
+    assert list(guard[:14]) == [sk.POLICY["auto"], 0, 0, 0, 0, 2] + [0] * 8
+    assert list(guard[14:]) == [0x5A5A5A5A] * 2
+
+
 def test_f64_plans():
     """FP64 in needs FP64 out; its partial tiles are FP64 (8 bytes per element)."""
     sk = _lib()

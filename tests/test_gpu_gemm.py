@@ -407,3 +407,42 @@ def test_sweep_sample_as_benchmarked():
         got = to_f64(C[torch.from_numpy(rows).to(dev())])
         assert og.rel_frobenius(got, ref) <= TOL_16, (M, N, K, info["policy_name"])
     assert ("sk", True) in seen and ("dp", False) in seen
+
+
+@pytest.mark.parametrize("fixup", ["auto", "owner"])
+def test_fixup_wait_timeout_reported_and_recovered(fixup):
+    """The error path of the bounded fix-up waits, forced from the host with a
+    spin limit of one poll: every kernel still exits, skgemm_check_device_error
+    reports the timeout, and once the workspace is zero-filled again a plan
+    with the default limit gives the exact result in the same workspace."""
+    M, N, K = 1000, 700, 900
+    g = W.rng(31)
+    a = W.integer_f32(g, (M, K))
+    b = W.integer_f32(g, (K, N))
+    A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+    ref = og.gemm_f64(a.astype(np.float64), b.astype(np.float64))
+    tile = (256, 256, 64)
+    t = sk().Plan(M, N, K, ta=sk().BF16, tc=sk().F32, policy="dp", tile=tile).info()["t"]
+    kw = dict(ta=sk().BF16, tc=sk().F32, policy="sk", force_g=3 * t, tile=tile, fixup=fixup)
+    bad = sk().Plan(M, N, K, spin_limit=1, **kw)
+    good = sk().Plan(M, N, K, **kw)
+    nb = max(bad.workspace_size(), good.workspace_size())
+    ws = torch.zeros(nb, dtype=torch.uint8, device=dev())
+    C = torch.empty((M, N), dtype=torch.float32, device=dev())
+    args = (A.data_ptr(), K, B.data_ptr(), N, C.data_ptr(), N, 1.0, 0.0, None, None, ws.data_ptr(), nb)
+    seen = 0
+    for _ in range(3):
+        bad.run(*args)
+        torch.cuda.synchronize()
+        try:
+            sk().check_device_error(ws.data_ptr())
+        except sk().SkgemmError as e:
+            assert e.status == sk().ERR_TIMEOUT
+            seen += 1
+        ws.zero_()
+    assert seen > 0
+    good.run(*args)
+    torch.cuda.synchronize()
+    sk().check_device_error(ws.data_ptr())
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), ref)
