@@ -73,3 +73,28 @@ def test_padded_nan_gaps_exact(shape, dtype, tile, layouts):
         torch.cuda.synchronize()
         assert np.array_equal(to_f64(C) if out_dt == torch.float32 else C.cpu().numpy(), ref), pol
         assert torch.isnan(Cst[:, N:]).all(), pol
+
+
+@pytest.mark.parametrize("policy", ["auto", "sk", "dp"])
+@pytest.mark.parametrize("dtype,tile", [(torch.bfloat16, (256, 256, 64)), (torch.bfloat16, (128, 128, 64, 8)),
+                                        (torch.float32, None)])
+def test_grouped_padded_nan_gaps_exact(policy, dtype, tile):
+    """One grouped launch over ragged problems whose operands and outputs all
+    sit in NaN-padded storage (leading dimensions from the per-problem table)."""
+    shapes = [(333, 517, 290), (64, 64, 9), (130, 2, 69), (200, 260, 1030), (1, 1, 1)]
+    g = W.rng(41)
+    As, Bs, Cs, Cst, refs = [], [], [], [], []
+    for M, N, K in shapes:
+        a = W.integer_f32(g, (M, K))
+        b = W.integer_f32(g, (K, N))
+        As.append(padded(a, dtype, False))
+        Bs.append(padded(b, dtype, False))
+        st = torch.full((M, N + PAD), float("nan"), dtype=torch.float32, device=dev())
+        Cst.append(st)
+        Cs.append(st[:, :N])
+        refs.append(og.gemm_f64(a.astype(np.float64), b.astype(np.float64)))
+    sk().grouped_matmul(As, Bs, Cs, policy=policy, tile=tile)
+    torch.cuda.synchronize()
+    for (M, N, K), C, st, ref in zip(shapes, Cs, Cst, refs):
+        assert np.array_equal(to_f64(C), ref), (M, N, K)
+        assert torch.isnan(st[:, N:]).all(), (M, N, K)
