@@ -75,8 +75,12 @@ typedef enum {
 typedef struct {
     skgemm_policy_t policy;       /* default SKGEMM_POLICY_AUTO */
     int32_t force_g;              /* >0: Stream-K grid size instead of the model's choice */
-    int32_t tile_m, tile_n, tile_k;   /* 0 = the dtype's default tile; else must name
-                                         a compiled tile configuration */
+    int32_t tile_m, tile_n, tile_k;   /* 0 = the planner picks among the dtype's
+                                         compiled tiles by modelled time; else must
+                                         name one: FP32 128x128x32; FP16/BF16
+                                         256x256x64 or 128x128x64; FP8 256x256x128
+                                         or 128x128x128; FP64 64x64x16 or
+                                         128x128x16 */
     int32_t hybrid_min_waves;     /* full waves needed for the two-tile hybrid (default 2) */
     int32_t num_cus;              /* >0: plan for this many CUs instead of querying */
     int32_t occupancy;            /* >0: workgroups per CU instead of querying */

@@ -11,9 +11,15 @@ const void* kernel_fn_f64(bool akc, bool bkc, int v) {
         return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F64, false, true, 0>)
                    : reinterpret_cast<const void*>(&skgemm_kernel<DT_F64, false, false, 0>);
     }
+    if (v == 1) {
+        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F64, true, true, 1>)
+                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_F64, true, false, 1>);
+        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F64, false, true, 1>)
+                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_F64, false, false, 1>);
+    }
     return nullptr;
 }
 
-int kernel_threads_f64(int v) { return v == 0 ? kThreadsOf<DT_F64, 0> : 0; }
+int kernel_threads_f64(int v) { return v == 0 ? kThreadsOf<DT_F64, 0> : v == 1 ? kThreadsOf<DT_F64, 1> : 0; }
 
 }  // namespace skg

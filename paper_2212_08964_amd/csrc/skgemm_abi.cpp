@@ -95,6 +95,7 @@ TileCfg tile_for(int dt, int v) {
     }
     if ((v == 1 || v == 2) && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 1 && dt == DT_F8) return kTileF8S;
+    if (v == 1 && dt == DT_F64) return kTileF64L;
     return TileCfg{0, 0, 0};
 }
 
@@ -112,7 +113,8 @@ void model_for(int dt, int v, double* m) {
     // the comparison of tile variants.  FP8 shares the 16-bit constants of
     // the same tile size: same wave layout, twice the k per iteration at
     // twice the MFMA rate.
-    if (dt == DT_F64) { m[0] = 4.74; m[1] = 1.49; m[2] = 0.678; m[3] = 0.778; m[4] = 1.62; return; }
+    if (dt == DT_F64 && v == 1) { m[0] = 7.98; m[1] = 1.22; m[2] = 2.04; m[3] = 1.13; m[4] = 3.84; return; }
+    if (dt == DT_F64) { m[0] = 5.00; m[1] = 1.23; m[2] = 0.713; m[3] = 1.13; m[4] = 2.09; return; }
     if (dt == DT_F32) { m[0] = 6.20; m[1] = 1.25; m[2] = 2.07; m[3] = 0.569; m[4] = 3.99; return; }
     if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
     if (v == 1) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }

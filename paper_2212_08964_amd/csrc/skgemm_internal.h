@@ -29,6 +29,7 @@ constexpr TileCfg kTile16S = {128, 128, 64, 2};   // bf16 and f16, small-tile va
 constexpr TileCfg kTileF8 = {256, 256, 128, 2};
 constexpr TileCfg kTileF8S = {128, 128, 128, 2};   // fp8, small-tile variant
 constexpr TileCfg kTileF64 = {64, 64, 16, 2};
+constexpr TileCfg kTileF64L = {128, 128, 16, 2};   // fp64, large-tile variant
 
 // One problem of a grouped launch (device table entry, 128 bytes).  Shapes are
 // as launched (operands already swapped when C is column-major).
@@ -78,7 +79,8 @@ struct KArgs {
 };
 
 // Tile variants: 0 = the type's default tile, 1 = the small 16-bit / FP8 tile
-// (four waves), 2 = the small 16-bit tile on eight waves.
+// (four waves) or the large FP64 tile, 2 = the small 16-bit tile on eight
+// waves.
 constexpr int kVariants = 3;
 
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.

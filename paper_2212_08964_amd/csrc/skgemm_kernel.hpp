@@ -67,6 +67,7 @@ template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.b
 template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4, NS = kTileF8.ns; };
 template <> struct Cfg<DT_F8, 1> { static constexpr int EB = 1, BM = kTileF8S.bm, BN = kTileF8S.bn, BK = kTileF8S.bk, WM = 2, WN = 2, NS = kTileF8S.ns; };
 template <> struct Cfg<DT_F64, 0> { static constexpr int EB = 8, BM = kTileF64.bm, BN = kTileF64.bn, BK = kTileF64.bk, WM = 2, WN = 2, NS = kTileF64.ns; };
+template <> struct Cfg<DT_F64, 1> { static constexpr int EB = 8, BM = kTileF64L.bm, BN = kTileF64L.bn, BK = kTileF64L.bk, WM = 2, WN = 2, NS = kTileF64L.ns; };
 template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
@@ -77,10 +78,10 @@ constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
 
 // Waves per SIMD the register budget must allow: two workgroups per CU for
 // the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one, and the
-// 8-wave small tile two workgroups); three for the small FP64 tile, whose
-// accumulators take a quarter of the others'.
+// 8-wave small tile two workgroups); three for the 64x64 FP64 tile, whose
+// accumulators take a quarter of the others', two for the 128x128 one.
 template <int DT, int V>
-constexpr int kWavesPerEU = DT == DT_F64 ? 3 : V == 2 ? 4 : 2;
+constexpr int kWavesPerEU = DT == DT_F64 ? (V == 1 ? 2 : 3) : V == 2 ? 4 : 2;
 
 // Buffer descriptor word 3 for untyped buffer loads on gfx9-family targets.
 constexpr int kBufferFlags = 0x00020000;
@@ -168,7 +169,8 @@ struct Slab {
     static constexpr int BLOCKS = BYTES / 1024;
     static constexpr int PER_WAVE = BLOCKS / NW;
     static_assert(!KC || BK * EB == 128 || BK * EB == 64, "K-contiguous slab rows must be 64 or 128 bytes");
-    static_assert(KC || ROWB == 512 || ROWB == 256, "MN-contiguous slab rows must be 256 or 512 bytes");
+    static_assert(KC || ROWB == 1024 || ROWB == 512 || ROWB == 256,
+                  "MN-contiguous slab rows must be 256, 512 or 1024 bytes");
     static_assert(BLOCKS % NW == 0, "slab must split evenly over the waves");
 
     uint32_t voff[PER_WAVE];     // byte offset of the lane's chunk from the slab origin
@@ -1053,12 +1055,29 @@ struct Gemm {
         Blk T;
         bool ahead = false;
         if constexpr (DT == DT_F64) {
-            // one copy at a time: the FP64 tile trades the pipeline for occupancy
+            // One copy at a time, half a block per load (the FP64 tiles trade
+            // the pipeline for occupancy and registers).  Each element still
+            // takes the peers in the same order.
+            constexpr int H = CPB / 2;
             for (int k = lo; k <= hi; ++k) {
                 if (k == wg) continue;
-                u32x4 buf[CPB];
-                load_unit(peer_slot(ka, k, true), i, j, buf, tid);
-                take_unit(acc, T, ahead, i, j, k, wg, buf);
+                const __amdgpu_buffer_rsrc_t rs = peer_slot(ka, k, true);
+                const bool into_apart = k < wg, first = !ahead;
+                if (!into_apart && ahead) acc_add_blk(acc, i, j, T);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    u32x4 buf[H];
+#pragma unroll
+                    for (int r = 0; r < H; ++r)
+                        buf[r] = __builtin_amdgcn_raw_buffer_load_b128(
+                            rs, (((i * FN + j) * CPB + h * H + r) * THREADS + tid) * 16, 0, kCoherent);
+#pragma unroll
+                    for (int r = 0; r < H; ++r) {
+                        if (into_apart) blk_take_chunk(T, h * H + r, buf[r], first);
+                        else acc_add_chunk(acc, i, j, h * H + r, buf[r]);
+                    }
+                }
+                ahead = into_apart;
             }
             if (ahead) acc_add_blk(acc, i, j, T);
             return;

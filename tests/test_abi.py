@@ -310,11 +310,15 @@ def test_spin_limit_option():
 def test_f64_plans():
     """FP64 in needs FP64 out; its partial tiles are FP64 (8 bytes per element)."""
     sk = _lib()
+    for tile in [(64, 64, 16), (128, 128, 16)]:
+        t = sk.Plan(1000, 700, 900, ta=sk.F64, policy="sk", force_g=100, num_cus=256, occupancy=2, tile=tile)
+        assert t.info()["tile"][:3] == tile
+        u = sk.Plan(1000, 700, 900, ta=sk.F64, policy="sk", force_g=50, num_cus=256, occupancy=2, tile=tile)
+        assert t.workspace_size() - u.workspace_size() == 50 * tile[0] * tile[1] * 8
+    # unpinned, the planner takes the tile with the smaller modelled time
     p = sk.Plan(1000, 700, 900, ta=sk.F64, policy="sk", force_g=100, num_cus=256, occupancy=4)
     info = p.info()
-    assert (info["BM"], info["BN"], info["BK"]) == (64, 64, 16)
-    q = sk.Plan(1000, 700, 900, ta=sk.F64, policy="sk", force_g=50, num_cus=256, occupancy=4)
-    assert p.workspace_size() - q.workspace_size() == 50 * 64 * 64 * 8
+    assert info["tile"][:3] in [(64, 64, 16), (128, 128, 16)]
     for ta, tc in [(sk.F64, sk.F32), (sk.F32, sk.F64), (sk.BF16, sk.F64)]:
         with pytest.raises(sk.SkgemmError) as e:
             sk.Plan(100, 100, 100, ta=ta, tc=tc, num_cus=256, occupancy=1)

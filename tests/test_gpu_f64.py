@@ -23,6 +23,8 @@ POLICIES = ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"]
 SHAPES = [(64, 64, 16), (1000, 700, 900), (1, 1, 1), (65, 129, 17), (384, 384, 1024), (2048, 512, 4096),
           (7, 300, 5000), (130, 2, 64)]
 U64 = 2.0 ** -53
+# the two FP64 tiles (the planner picks one per problem; tests pin each)
+TILES = [(64, 64, 16), (128, 128, 16)]
 
 
 def sk():
@@ -52,22 +54,24 @@ def _check(C, ref_bound):
     assert np.all(np.abs(got - ref) <= bound)
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("shape", SHAPES)
-def test_f64_parity_every_policy(shape):
+def test_f64_parity_every_policy(shape, tile):
     M, N, K = shape
     a, b = _inputs(M, N, K, seed=M + N + K)
     A = torch.from_numpy(a).to(dev())
     B = torch.from_numpy(b).to(dev())
     rb = _reference(a, b, K)
     for pol in POLICIES:
-        C = sk().matmul(A, B, policy=pol)
+        C = sk().matmul(A, B, policy=pol, tile=tile)
         torch.cuda.synchronize()
         assert C.dtype == torch.float64
         _check(C, rb)
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("g", [1, 3, 16, 100, 176, 352, 500])
-def test_f64_integer_exact_forced_grids(g):
+def test_f64_integer_exact_forced_grids(g, tile):
     M, N, K = 1000, 700, 900
     rng = W.rng(11)
     a = rng.integers(-2, 3, (M, K)).astype(np.float64)
@@ -75,7 +79,7 @@ def test_f64_integer_exact_forced_grids(g):
     A = torch.from_numpy(a).to(dev())
     B = torch.from_numpy(b).to(dev())
     try:
-        C = sk().matmul(A, B, policy="sk", force_g=g)
+        C = sk().matmul(A, B, policy="sk", force_g=g, tile=tile)
     except sk().SkgemmError as e:
         assert e.status == sk().ERR_CAPACITY
         pytest.skip("grid larger than the co-resident capacity of this GPU")
@@ -83,9 +87,10 @@ def test_f64_integer_exact_forced_grids(g):
     assert np.array_equal(C.cpu().numpy(), og.gemm_f64(a, b))
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("layouts", ["nn", "nt", "tn", "tt"])
 @pytest.mark.parametrize("c_col", [False, True])
-def test_f64_layouts(layouts, c_col):
+def test_f64_layouts(layouts, c_col, tile):
     M, N, K = 333, 517, 290
     a, b = _inputs(M, N, K, seed=5)
     A = torch.from_numpy(a).to(dev())
@@ -98,7 +103,7 @@ def test_f64_layouts(layouts, c_col):
         torch.empty((M, N), dtype=torch.float64, device=dev())
     rb = _reference(a, b, K)
     for pol in ("auto", "sk", "dp"):
-        C = sk().matmul(A, B, out=out, policy=pol)
+        C = sk().matmul(A, B, out=out, policy=pol, tile=tile)
         torch.cuda.synchronize()
         _check(C, rb)
 
@@ -124,14 +129,15 @@ def test_f64_alpha_beta_and_nan_c():
 @pytest.mark.parametrize("shape,policy,g", [((1000, 700, 900), "sk", 0), ((1000, 700, 900), "sk", 333),
                                             ((384, 384, 1024), "auto", 0), ((4096, 4096, 64), "dp_1tile_sk", 0),
                                             ((4096, 4096, 64), "2tile_sk_dp", 0)])
-def test_f64_trace_matches_enumerator(shape, policy, g):
+@pytest.mark.parametrize("tile", TILES)
+def test_f64_trace_matches_enumerator(shape, policy, g, tile):
     M, N, K = shape
     a, b = _inputs(M, N, K, seed=9)
     A = torch.from_numpy(a).to(dev())
     B = torch.from_numpy(b).to(dev())
-    p = sk().get_plan(M, N, K, 0, 0, 0, sk().F64, sk().F64, policy, g, 2, None)
+    p = sk().get_plan(M, N, K, 0, 0, 0, sk().F64, sk().F64, policy, g, 2, tile)
     tr = torch.full((max(p.trace_capacity(), 1) * 8,), -7, dtype=torch.int32, device=dev())
-    C = sk().matmul(A, B, policy=policy, force_g=g, trace=tr)
+    C = sk().matmul(A, B, policy=policy, force_g=g, trace=tr, tile=tile)
     torch.cuda.synchronize()
     info = p.info()
     recs = [tuple(int(v) for v in r) for r in tr.cpu().numpy().reshape(-1, 8) if r[0] != -7]
@@ -141,18 +147,19 @@ def test_f64_trace_matches_enumerator(shape, policy, g):
     _check(C, _reference(a, b, K))
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("s", [2, 3, 7])
-def test_f64_split_fixup_bitwise_equals_owner(s):
+def test_f64_split_fixup_bitwise_equals_owner(s, tile):
     M, N, K = 640, 448, 1600
     a, b = _inputs(M, N, K, seed=s)
     A = torch.from_numpy(a).to(dev())
     B = torch.from_numpy(b).to(dev())
-    t = sk().Plan(M, N, K, ta=sk().F64, policy="dp").info()["t"]
-    plan = sk().get_plan(M, N, K, 0, 0, 0, sk().F64, sk().F64, "sk", s * t, 2, None, "auto")
+    t = sk().Plan(M, N, K, ta=sk().F64, policy="dp", tile=tile).info()["t"]
+    plan = sk().get_plan(M, N, K, 0, 0, 0, sk().F64, sk().F64, "sk", s * t, 2, tile, "auto")
     if plan.info()["coop_s"] != s:
         pytest.skip("this GPU's co-resident capacity gives another plan")
-    C1 = sk().matmul(A, B, policy="sk", force_g=s * t, fixup="auto")
-    C2 = sk().matmul(A, B, policy="sk", force_g=s * t, fixup="owner")
+    C1 = sk().matmul(A, B, policy="sk", force_g=s * t, fixup="auto", tile=tile)
+    C2 = sk().matmul(A, B, policy="sk", force_g=s * t, fixup="owner", tile=tile)
     torch.cuda.synchronize()
     assert torch.equal(C1, C2)
     _check(C1, _reference(a, b, K))
