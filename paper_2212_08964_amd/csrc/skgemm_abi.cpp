@@ -255,13 +255,14 @@ int walk(const skgemm_plan_s& pl, int x, F&& emit) {
 
 struct DevInfo {
     int cus = 0;
-    int occ[4][2][2][kVariants] = {};
-    bool have_occ[4][2][2][kVariants] = {};
+    int occ[kDTypes][2][2][kVariants] = {};
+    bool have_occ[kDTypes][2][2][kVariants] = {};
 };
 std::mutex g_dev_mu;
 DevInfo g_dev[64];
 
 skgemm_status_t device_capacity(int dt, bool akc, bool bkc, int v, int* cus, int* occ) {
+    if (dt < 0 || dt >= kDTypes || v < 0 || v >= kVariants) return SKGEMM_ERR_UNSUPPORTED;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SKGEMM_ERR_HIP;
     std::lock_guard<std::mutex> lk(g_dev_mu);

@@ -7,6 +7,7 @@
 namespace skg {
 
 enum DType : int32_t { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2, DT_F8 = 3, DT_F64 = 4 };
+constexpr int kDTypes = 5;                 // number of DType values
 enum Role : int32_t { ROLE_FULL = 0, ROLE_PARTIAL = 1, ROLE_OWNER = 2 };
 
 constexpr int kFlagStrideInts = 32;        // one 128-byte line per ready flag

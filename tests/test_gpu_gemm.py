@@ -446,3 +446,27 @@ def test_fixup_wait_timeout_reported_and_recovered(fixup):
     torch.cuda.synchronize()
     sk().check_device_error(ws.data_ptr())
     assert np.array_equal(C.cpu().numpy().astype(np.float64), ref)
+
+
+def test_occupancy_per_dtype_and_tile_is_sane_and_stable():
+    """The library's per-device occupancy cache holds one entry per input type
+    and tile: every entry is a plausible workgroup count, planning one type
+    leaves the others' entries alone, and the plan's capacity is CUs times it."""
+    cases = [(sk().F32, None), (sk().BF16, (256, 256, 64)), (sk().BF16, (128, 128, 64, 4)),
+             (sk().BF16, (128, 128, 64, 8)), (sk().F16, (256, 256, 64)), (sk().F64, (64, 64, 16)),
+             (sk().F64, (128, 128, 16))]
+    tc = {sk().F32: sk().F32, sk().BF16: sk().BF16, sk().F16: sk().F16, sk().F64: sk().F64}
+
+    def occ(ta, tile):
+        info = sk().Plan(512, 512, 512, ta=ta, tc=tc[ta], policy="dp", tile=tile).info()
+        assert info["p"] % info["occupancy"] == 0
+        return info["occupancy"]
+
+    first = [occ(ta, tile) for ta, tile in cases]
+    assert all(1 <= o <= 8 for o in first), first
+    assert [occ(ta, tile) for ta, tile in reversed(cases)][::-1] == first
+    # FP8 (both operands K-contiguous)
+    for tile in [(256, 256, 128), (128, 128, 128)]:
+        info = sk().Plan(512, 512, 512, 0, 1, 0, sk().F8E4M3, sk().F32, policy="dp", tile=tile).info()
+        assert 1 <= info["occupancy"] <= 8
+    assert [occ(ta, tile) for ta, tile in cases] == first
