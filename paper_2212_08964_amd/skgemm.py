@@ -162,9 +162,13 @@ class Plan:
             self._h = ctypes.c_void_p()
 
     def workspace_size(self) -> int:
-        n = ctypes.c_size_t()
-        _check(lib().skgemm_workspace_size(self._h, ctypes.byref(n)), "skgemm_workspace_size")
-        return n.value
+        # a plan is immutable: ask the library once
+        ws = getattr(self, "_ws_bytes", None)
+        if ws is None:
+            n = ctypes.c_size_t()
+            _check(lib().skgemm_workspace_size(self._h, ctypes.byref(n)), "skgemm_workspace_size")
+            ws = self._ws_bytes = n.value
+        return ws
 
     def trace_capacity(self) -> int:
         n = ctypes.c_size_t()
@@ -326,7 +330,7 @@ def workspace(nbytes: int, device):
     """A zero-filled, 256-byte aligned device workspace of at least nbytes,
     cached per device (runs on one device must not overlap in time)."""
     import torch
-    key = torch.device(device).index
+    key = device.index if isinstance(device, torch.device) else torch.device(device).index
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
