@@ -3,16 +3,21 @@
 //   s = absmax(X) / 448   (1 when X is all zero), rounded to FP32
 //   Q = E4M3_RNE(clamp(X / s, -448, 448))
 //
-// Three launches, all HBM-bound: absmax_partial reads X once (16-byte loads
-// when rows are aligned) and writes one maximum per workgroup; absmax_finish
-// (one workgroup) reduces those and writes s on the device, so no host round
-// trip or memset is needed and the sequence can be captured in a graph; a
-// third kernel reads X again and writes the codes.  Where every row is
-// 16-byte aligned that is quantize_rows (same storage order: 16 elements per
-// thread, 16-byte loads and stores) or quantize_transpose (the FP8 GEMM
-// wants both operands K-contiguous, so a row-major B changes order on the
-// way out: 64x64 tiles through LDS, 16-byte loads and stores); otherwise
-// quantize_tiles (element loads, 4-byte stores, any alignment).
+// Two or three launches, all HBM-bound: absmax_partial reads X once (16-byte
+// loads when rows are aligned) and writes one maximum per workgroup; the
+// quantising kernel reduces those maxima to s in every workgroup (its first
+// workgroup stores s for the GEMM), reads X again and writes the codes.  On
+// grids of more than kFoldMaxBlocks workgroups a one-workgroup kernel
+// (absmax_finish) reduces the maxima once instead, before the quantising
+// kernel.  Nothing goes through the host and no memory needs clearing, so
+// the sequence can be captured in a graph.  An empty X takes absmax_finish
+// alone (s = 1).
+// Where every row is 16-byte aligned the second kernel is quantize_rows
+// (same storage order: 16 elements per thread, 16-byte loads and stores) or
+// quantize_transpose (the FP8 GEMM wants both operands K-contiguous, so a
+// row-major B changes order on the way out: 64x64 tiles through LDS, 16-byte
+// loads and stores); otherwise quantize_tiles (element loads, 4-byte stores,
+// any alignment).
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,6 +31,7 @@ namespace skg {
 constexpr int kQThreads = 256;
 constexpr int kAbsmaxBlocks = 1024;
 constexpr float kE4M3Max = 448.0f;
+constexpr int64_t kFoldMaxBlocks = 4096;   // quantising grids that reduce the maxima themselves
 
 template <int DT>
 __device__ __forceinline__ float elem(const void* x, int64_t i) {
@@ -100,6 +106,28 @@ __global__ void __launch_bounds__(kQThreads) absmax_finish(const float* partial,
     if (threadIdx.x == 0) scale[0] = m == 0.0f ? 1.0f : m / kE4M3Max;
 }
 
+// s from the per-workgroup maxima of absmax_partial, computed by every
+// workgroup of the quantising pass (the same formula as absmax_finish, so the
+// same bits); the first workgroup also stores it for the GEMM's epilogue.
+// n = 0: absmax_finish has stored s already (large grids, where every
+// workgroup reading all maxima would cost more than the extra launch).
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ float scale_of(const float* partial, int n, float* scale, bool store) {
+    if (n == 0) return *scale;
+    __shared__ float red[kQThreads / 64];
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < n; i += kQThreads) m = fmaxf(m, partial[i]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = red[0];
+#pragma unroll
+    for (int k = 1; k < kQThreads / 64; ++k) m = fmaxf(m, red[k]);
+    const float s = m == 0.0f ? 1.0f : m / kE4M3Max;
+    if (store && threadIdx.x == 0) scale[0] = s;
+    return s;
+}
+
 // X / s rounded to FP32, clamped to the E4M3 range, rounded to E4M3 (nearest
 // even) by the hardware conversion; two codes per call.
 template <bool HI>
@@ -114,8 +142,9 @@ __device__ __forceinline__ uint32_t to_e4m3x2(float a, float b, float s, uint32_
 template <int DT>
 __global__ void __launch_bounds__(kQThreads) quantize_tiles(const void* x, int64_t rows, int64_t cols, int64_t ldx,
                                                             int x_col, uint8_t* q, int64_t ldq, int q_col,
-                                                            const float* scale) {
+                                                            const float* partial, int np, float* scale) {
     __shared__ float tile[64][65];
+    const float s = scale_of(partial, np, scale, blockIdx.x == 0 && blockIdx.y == 0);
     const int64_t r0 = int64_t(blockIdx.y) * 64, c0 = int64_t(blockIdx.x) * 64;
     const int t = threadIdx.x;
     // read: consecutive threads walk the input's contiguous dimension
@@ -130,7 +159,6 @@ __global__ void __launch_bounds__(kQThreads) quantize_tiles(const void* x, int64
         tile[rl][cl] = v;
     }
     __syncthreads();
-    const float s = *scale;
     // write: each thread converts four consecutive elements of the output's
     // contiguous dimension
 #pragma unroll
@@ -191,8 +219,10 @@ __device__ __forceinline__ uint4 codes16(const float* v, float s) {
 // loads and one 16-byte store.
 template <int DT>
 __global__ void __launch_bounds__(kQThreads) quantize_rows(const void* x, int64_t groups, int64_t per_row, int64_t ldx,
-                                                           uint8_t* q, int64_t ldq, const float* scale) {
+                                                           uint8_t* q, int64_t ldq, const float* partial, int np,
+                                                           float* scale) {
     constexpr int EB = DT == DT_F32 ? 4 : 2, NV = 16 * EB / 16;   // input vectors per group
+    const float s = scale_of(partial, np, scale, blockIdx.x == 0);
     const int64_t g = int64_t(blockIdx.x) * kQThreads + threadIdx.x;
     if (g >= groups) return;
     const int64_t o = g / per_row, c = (g - o * per_row) * 16;
@@ -203,7 +233,7 @@ __global__ void __launch_bounds__(kQThreads) quantize_rows(const void* x, int64_
     float v[16];
 #pragma unroll
     for (int k = 0; k < NV; ++k) unpack<DT>(u[k], v + k * (16 / NV));
-    *reinterpret_cast<uint4*>(q + o * ldq + c) = codes16(v, *scale);
+    *reinterpret_cast<uint4*>(q + o * ldq + c) = codes16(v, s);
 }
 
 // Transposing form: X stored as `outer` rows of `inner` contiguous elements,
@@ -214,9 +244,10 @@ __global__ void __launch_bounds__(kQThreads) quantize_rows(const void* x, int64_
 template <int DT>
 __global__ void __launch_bounds__(kQThreads) quantize_transpose(const void* x, int64_t outer, int64_t inner,
                                                                 int64_t ldx, uint8_t* q, int64_t ldq,
-                                                                const float* scale) {
+                                                                const float* partial, int np, float* scale) {
     constexpr int EB = DT == DT_F32 ? 4 : 2, VE = 16 / EB, VPR = 64 / VE, LOADS = 64 * VPR / kQThreads;
     __shared__ float tile[64][65];
+    const float s = scale_of(partial, np, scale, blockIdx.x == 0 && blockIdx.y == 0);
     const int64_t i0 = int64_t(blockIdx.x) * 64, o0 = int64_t(blockIdx.y) * 64;
     const int t = threadIdx.x;
     uint4 u[LOADS];
@@ -245,7 +276,7 @@ __global__ void __launch_bounds__(kQThreads) quantize_transpose(const void* x, i
     float v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = tile[16 * rg + e][ic];
-    *reinterpret_cast<uint4*>(q + i * ldq + o) = codes16(v, *scale);
+    *reinterpret_cast<uint4*>(q + i * ldq + o) = codes16(v, s);
 }
 
 int quant_workspace_floats() { return kAbsmaxBlocks; }
@@ -269,15 +300,23 @@ int launch_quantize(int dtype, const void* x, int64_t rows, int64_t cols, int64_
     const int64_t groups = outer * (inner / 16);
     const unsigned row_blocks = unsigned((groups + kQThreads - 1) / kQThreads);
     const dim3 ttiles(unsigned((inner + 63) / 64), unsigned((outer + 63) / 64));
+    // the quantising pass reduces the maxima itself when its grid is small
+    // (one launch fewer); larger grids keep the one-workgroup reduction
+    const int64_t qblocks = form == 1 ? int64_t(row_blocks)
+                            : form == 2 ? int64_t(ttiles.x) * ttiles.y : int64_t(tiles.x) * tiles.y;
+    const int np = any && qblocks <= kFoldMaxBlocks ? blocks : 0;
 #define SKG_QUANT(DT_)                                                                                         \
     absmax_partial<DT_><<<blocks, kQThreads, 0, st>>>(x, outer, inner, ldx, vec, partial);                     \
-    absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);                                           \
+    if (np == 0) absmax_finish<<<1, kQThreads, 0, st>>>(partial, blocks, scale);                               \
     if (form == 1)                                                                                             \
-        quantize_rows<DT_><<<row_blocks, kQThreads, 0, st>>>(x, groups, inner / 16, ldx, q, ldq, scale);       \
+        quantize_rows<DT_><<<row_blocks, kQThreads, 0, st>>>(x, groups, inner / 16, ldx, q, ldq, partial, np,  \
+                                                             scale);                                           \
     else if (form == 2)                                                                                        \
-        quantize_transpose<DT_><<<ttiles, kQThreads, 0, st>>>(x, outer, inner, ldx, q, ldq, scale);            \
+        quantize_transpose<DT_><<<ttiles, kQThreads, 0, st>>>(x, outer, inner, ldx, q, ldq, partial, np,       \
+                                                              scale);                                          \
     else if (any)                                                                                              \
-        quantize_tiles<DT_><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, scale);
+        quantize_tiles<DT_><<<tiles, kQThreads, 0, st>>>(x, rows, cols, ldx, x_col, q, ldq, q_col, partial,    \
+                                                         np, scale);
     switch (dtype) {
         case DT_F32: SKG_QUANT(DT_F32) break;
         case DT_BF16: SKG_QUANT(DT_BF16) break;
