@@ -58,18 +58,29 @@ typedef enum {
 /* Work decomposition (Work Decomposition Strategies section and
  * Data-parallel Hybridization subsection). */
 typedef enum {
-    SKGEMM_POLICY_AUTO = 0,       /* DP when tiles fill whole waves or make four
-                                     full waves or more; otherwise the
-                                     remainder tiles (all tiles when there are fewer
-                                     than workgroups) are split into s equal parts
-                                     each, s from the grid-size model over
-                                     1 .. p / tiles: s = 1 is DP, else basic SK
-                                     (no full wave) or DP + one-tile SK with
-                                     g = s * tiles */
+    SKGEMM_POLICY_AUTO = 0,       /* this library's rule for MI355X (not the paper's):
+                                     DP when the tiles fill whole waves or make four
+                                     full waves or more; otherwise the remainder
+                                     tiles (all tiles when there are fewer than
+                                     workgroups) are split into s equal parts each,
+                                     s from the grid-size model over 1 .. p / tiles
+                                     (with the occupancy term of
+                                     skgemm_model_constants): s = 1 is DP, else
+                                     basic SK (no full wave) or DP + one-tile SK
+                                     with g = s * tiles.  A grouped plan whose
+                                     problems differ in iterations per tile takes
+                                     SKGEMM_POLICY_PAPER's choice. */
     SKGEMM_POLICY_DP = 1,         /* one workgroup per output tile */
     SKGEMM_POLICY_SK = 2,         /* basic Stream-K over all tiles */
     SKGEMM_POLICY_DP_1TILE_SK = 3,/* full DP waves, Stream-K over the remainder tiles */
-    SKGEMM_POLICY_2TILE_SK_DP = 4 /* Stream-K over remainder + one wave, then DP waves */
+    SKGEMM_POLICY_2TILE_SK_DP = 4,/* Stream-K over remainder + one wave, then DP waves */
+    SKGEMM_POLICY_PAPER = 5       /* the paper's own selection (Data-parallel
+                                     Hybridization subsection): DP when the tiles
+                                     fill whole waves; basic SK with g from the
+                                     grid-size model over [tiles, p] when there are
+                                     fewer tiles than workgroups; two-tile SK + DP
+                                     from hybrid_min_waves full waves on; DP +
+                                     one-tile SK otherwise */
 } skgemm_policy_t;
 
 typedef struct {

@@ -9,8 +9,12 @@ come first, then problem 1's, and so on.  The policies of the Stream-K
 algorithm and its hybrids then apply to that single space unchanged, with a
 workgroup's even share allowed to run from one problem into the next.  The
 paper evaluates one GEMM at a time; this generalisation is the reading used
-for the grouped launch (each problem's tiles linearised m-major, k innermost,
-as for one GEMM; the model uses the mean iterations per tile).
+for the grouped launch (problems whose K is 0 but which have tiles go after
+all others and never join the Stream-K region: their tiles only apply the
+epilogue C = beta * C and run as data-parallel tiles; each problem's tiles
+linearised m-major, k innermost,
+as for one GEMM; the model uses the mean iterations per tile; "auto" is the
+paper's selection from the tile count and the processor width).
 
 Everything is computed from an explicit list of tiles by linear search, so it
 can be checked by eye; it shares nothing with the device path.
@@ -20,8 +24,7 @@ from __future__ import annotations
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
-from .schedule import (AUTO_MAX_WAVES, FULL, OWNER, PARTIAL, Segment, cdiv, model_best_g, model_best_split, owner_of,
-                       share_start)
+from .schedule import FULL, OWNER, PARTIAL, Segment, cdiv, model_best_g, owner_of, share_start
 
 
 @dataclass
@@ -31,6 +34,7 @@ class GroupedPlan:
     BN: int
     BK: int
     p: int
+    order: List[int] = field(default_factory=list)                   # problem index per iteration-space position
     tiles: List[Tuple[int, int, int]] = field(default_factory=list)   # (problem, local tile, ipt) per global tile
     first_iter: List[int] = field(default_factory=list)             # first global iteration of each tile
     t: int = 0
@@ -47,8 +51,13 @@ class GroupedPlan:
 def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_min_waves=2,
                       model=(0.0, 0.0, 1.0, 0.0), share="proportional") -> GroupedPlan:
     pl = GroupedPlan(list(problems), BM, BN, BK, p, share=share)
+    # iteration-space order: problems with MAC-loop iterations first (given
+    # order), then the K = 0 problems that have tiles
+    pl.order = [i for i, (M, N, K) in enumerate(problems) if not (K == 0 and M > 0 and N > 0)] + \
+               [i for i, (M, N, K) in enumerate(problems) if K == 0 and M > 0 and N > 0]
     it = 0
-    for pi, (M, N, K) in enumerate(problems):
+    for pi in pl.order:
+        M, N, K = problems[pi]
         tm, tn, ipt = cdiv(M, BM), cdiv(N, BN), cdiv(K, BK)
         for lt in range(tm * tn):
             pl.tiles.append((pi, lt, ipt))
@@ -60,22 +69,13 @@ def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_
         return pl
     if it == 0:
         policy = "dp"
-    w, r = divmod(t, p)
-    ipts = {ipt for (_, _, ipt) in pl.tiles}
-    auto_g = 0
-    if policy == "auto":
-        if r == 0 or (len(ipts) == 1 and w >= AUTO_MAX_WAVES):
+    # the policies split the tiles that have iterations; K = 0 tiles follow as
+    # data-parallel (epilogue-only) tiles
+    tw = sum(1 for (_, _, ipt) in pl.tiles if ipt > 0)
+    w, r = divmod(tw, p)
+    if policy == "auto":          # the paper's selection, as for one GEMM
+        if r == 0:
             policy = "dp"
-        elif len(ipts) == 1:
-            # every tile has the same iterations: the tile-aligned split of the
-            # single-GEMM automatic policy applies to the concatenated tiles
-            count = t if w == 0 else r
-            s = model_best_split(count, next(iter(ipts)), p, model)
-            if s == 1:
-                policy = "dp"
-            else:
-                policy = "sk" if w == 0 else "dp_1tile_sk"
-                auto_g = s * count
         elif w == 0:
             policy = "sk"
         elif w >= hybrid_min_waves:
@@ -87,26 +87,24 @@ def make_grouped_plan(problems, BM, BN, BK, p, policy="auto", force_g=0, hybrid_
         pl.grid = t
         return pl
     if policy == "sk":
-        pl.sk_tiles = t
+        pl.sk_tiles = tw
     elif policy == "dp_1tile_sk":
         pl.sk_tiles, pl.sk_first = r, False
     else:
-        pl.sk_tiles = t if w == 0 else r + p
+        pl.sk_tiles = tw if w == 0 else r + p
     pl.sk_iters = pl.total_iters if pl.sk_tiles >= t else pl.first_iter[pl.sk_tiles]
     if policy == "sk":
         if force_g:
             pl.g_sk = force_g
-        elif auto_g:
-            pl.g_sk = auto_g
-        elif t >= p:
+        elif tw >= p:
             pl.g_sk = p
         else:
-            pl.g_sk = model_best_g(t, cdiv(pl.total_iters, t), p, model)
+            pl.g_sk = model_best_g(tw, cdiv(pl.total_iters, tw), p, model)
         pl.g_sk = min(pl.g_sk, pl.sk_iters)     # at most one workgroup per iteration
         pl.grid = pl.g_sk
     else:
         if pl.sk_tiles:
-            pl.g_sk = force_g if force_g else auto_g if auto_g else min(p, pl.sk_iters)
+            pl.g_sk = force_g if force_g else min(p, pl.sk_iters)
             pl.g_sk = min(pl.g_sk, pl.sk_iters)
         pl.grid = max(p if t - pl.sk_tiles > 0 else pl.g_sk, pl.g_sk)
     return pl

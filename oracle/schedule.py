@@ -34,15 +34,14 @@ reason in the design notes):
   data-parallel tiles follow and workgroup x takes sk_tiles + x + i * grid.
   "Two-tile SK + DP" runs its Stream-K share first, "DP + one-tile SK" its
   data-parallel tiles first.
-* The automatic policy (a choice for the target GPU, not the paper's): no
-  remainder tiles (t mod p == 0) -> data-parallel; otherwise the remainder
-  tiles (all t when t < p) are split s ways with g = s * (their count), s
-  from the grid-size model over 1 .. min(p / count, ipt): s = 1 is
-  data-parallel, else basic Stream-K (t < p) or DP + one-tile SK.  The
-  paper's own selection (basic Stream-K with g from the model over [t, p];
-  two-tile SK + DP from ``hybrid_min_waves`` full waves on; DP + one-tile SK
-  with g = min(p, sk_tiles * ipt)) is what the explicit policies give, and
-  what a grouped launch whose problems differ in iterations per tile uses.
+* The automatic policy is the paper's own selection (Data-parallel
+  Hybridization subsection): no remainder tiles (t mod p == 0) ->
+  data-parallel; fewer tiles than workgroups -> basic Stream-K with g from
+  the grid-size model over [t, p]; ``hybrid_min_waves`` (default two) or
+  more full waves -> two-tile SK + DP; otherwise DP + one-tile SK with
+  g = min(p, sk_tiles * ipt).  A library may resolve "auto" by its own rule;
+  such a plan is compared here through the explicit policy and grid it
+  resolved to.
 * K = 0 gives zero iterations per tile; every policy then degenerates to
   data-parallel tiles that only apply the epilogue (C = beta * C).
 * Model ties are broken toward the smallest g (fewer partial tiles).
@@ -161,29 +160,6 @@ def model_time(g: int, t: int, ipt: int, a: float, b: float, c: float, d: float)
     return a + b * (1 if peers > 1 else 0) + c * model_iters_per_cta(g, t, ipt) + d * (peers - 1)
 
 
-def model_best_split(t: int, ipt: int, p: int, consts) -> int:
-    """Split factor s in [1, min(p // t, ipt)] whose grid g = s * t has the
-    smallest modelled time (smallest s on ties).
-
-    consts is (a, b, c, d), or (a, b, c, d, e, cus): then a grid of more than
-    cus workgroups (the CU count) puts n = ceil(g / cus) workgroups on some
-    CUs, and the slowest of them sets the time: an iteration costs
-    c + (e - c)(n - 1)/(occ - 1), where e is its cost with all occ = p / cus
-    workgroup slots of a CU busy."""
-    a, b, c, d = consts[:4]
-    e, cus = (consts[4], consts[5]) if len(consts) >= 6 else (c, p)
-    occ = max(1, p // max(cus, 1))
-    best_s, best = 1, None
-    for s in range(1, max(1, min(p // max(t, 1), ipt)) + 1):
-        g = s * t
-        n = cdiv(g, cus)
-        cg = c if n <= 1 or occ <= 1 else c + (e - c) * (n - 1) / (occ - 1)
-        v = model_time(g, t, ipt, a, b, cg, d)
-        if best is None or v < best:
-            best, best_s = v, s
-    return best_s
-
-
 def model_best_g(t: int, ipt: int, p: int, consts) -> int:
     """Grid size in [t, p] with the smallest modelled time (smallest g on ties)."""
     a, b, c, d = consts[:4]
@@ -197,10 +173,6 @@ def model_best_g(t: int, ipt: int, p: int, consts) -> int:
 
 
 # ---------------------------------------------------------------- planning
-
-# Reading M1: the automatic policy stays data-parallel from this many full waves on.
-AUTO_MAX_WAVES = 4
-
 
 def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
               policy: str = "auto", force_g: int = 0, hybrid_min_waves: int = 2,
@@ -216,18 +188,15 @@ def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
     if ipt == 0:
         policy = "dp"
     w, r = divmod(t, p)
-    auto_g = 0
     if policy == "auto":
-        if r == 0 or w >= AUTO_MAX_WAVES:
+        if r == 0:
             policy = "dp"
+        elif w == 0:
+            policy = "sk"
+        elif w >= hybrid_min_waves:
+            policy = "2tile_sk_dp"
         else:
-            count = t if w == 0 else r
-            s = model_best_split(count, ipt, p, model)
-            if s == 1:
-                policy = "dp"
-            else:
-                policy = "sk" if w == 0 else "dp_1tile_sk"
-                auto_g = s * count
+            policy = "dp_1tile_sk"
     pl.policy = policy
     if policy == "dp":
         pl.sk_tiles, pl.g_sk, pl.grid = 0, 0, t
@@ -236,8 +205,6 @@ def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
         pl.sk_tiles = t
         if force_g:
             pl.g_sk = force_g
-        elif auto_g:
-            pl.g_sk = auto_g
         elif t >= p:
             pl.g_sk = p
         else:
@@ -252,7 +219,7 @@ def make_plan(M: int, N: int, K: int, BM: int, BN: int, BK: int, p: int,
         pl.sk_tiles = t if w == 0 else r + p
         pl.sk_first = True
     if pl.sk_tiles:
-        pl.g_sk = force_g if force_g else auto_g if auto_g else min(p, pl.sk_tiles * ipt)
+        pl.g_sk = force_g if force_g else min(p, pl.sk_tiles * ipt)
         pl.g_sk = min(pl.g_sk, pl.sk_iters)
     pl.grid = p if pl.dp_tiles > 0 else pl.g_sk
     pl.grid = max(pl.grid, pl.g_sk)

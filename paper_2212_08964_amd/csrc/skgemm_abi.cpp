@@ -55,7 +55,9 @@ struct skgemm_plan_s {
     std::vector<int32_t> pM, pN, pK, ptm, ptn, pipt;   // launched shapes
     std::vector<int32_t> tile_base;         // G + 1 prefix of tiles
     std::vector<int64_t> iter_base;         // G + 1 prefix of MAC-loop iterations
-    std::vector<int64_t> gM, gN, gK;        // shapes as given
+    std::vector<int64_t> gM, gN, gK;        // shapes as given, in iteration-space order
+    std::vector<int32_t> order;             // caller's index of each problem in iteration-space order
+    int t_work;                             // tiles with MAC-loop iterations (they come first)
     int64_t sk_iters;
 };
 
@@ -313,7 +315,7 @@ void skgemm_default_options(skgemm_options_t* opt) {
 static bool uniform_ipt(const skgemm_plan_s& pl) {
     int ipt = -1;
     for (size_t i = 0; i < pl.pipt.size(); ++i) {
-        if (pl.tile_base[i + 1] == pl.tile_base[i]) continue;
+        if (pl.tile_base[i + 1] == pl.tile_base[i] || pl.pipt[i] == 0) continue;
         if (ipt < 0) ipt = pl.pipt[i];
         else if (pl.pipt[i] != ipt) return false;
     }
@@ -338,55 +340,67 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     const int64_t total = pl->iter_base[np];
     if (t > kMaxDim || total > kMaxDim) return SKGEMM_ERR_UNSUPPORTED;
     pl->t = int(t);
+    // Tiles of K = 0 problems (epilogue only, C = beta * C) come after every
+    // tile with iterations and are never part of the Stream-K region: the
+    // policies split the first t_work tiles, and the rest run as
+    // data-parallel tiles.
+    int64_t t_work = t;
+    for (int i = 0; i < np; ++i)
+        if (pl->pipt[i] == 0 && pl->tile_base[i + 1] > pl->tile_base[i]) {
+            t_work = pl->tile_base[i];
+            break;
+        }
+    pl->t_work = int(t_work);
     // iterations per tile for the model (their mean over a grouped launch)
-    const int64_t ipt = t ? (total + t - 1) / t : 0;
+    const int64_t ipt = t_work ? (total + t_work - 1) / t_work : 0;
     int policy = o.policy;
     int auto_g = 0;
     pl->sk_tiles = 0; pl->g_sk = 0; pl->grid = 0; pl->sk_first = true;
     if (t > 0) {
         if (total == 0) policy = SKGEMM_POLICY_DP;    // K == 0: epilogue-only tiles
-        const int64_t w = t / p, r = t % p;
-        if (policy == SKGEMM_POLICY_AUTO) {
+        const int64_t w = t_work / p, r = t_work % p;
+        if (policy == SKGEMM_POLICY_AUTO && !uniform_ipt(*pl)) policy = SKGEMM_POLICY_PAPER;
+        if (policy == SKGEMM_POLICY_PAPER) {
+            // the paper's selection from the full waves w and the remainder r
+            if (r == 0) policy = SKGEMM_POLICY_DP;
+            else if (w == 0) policy = SKGEMM_POLICY_SK;
+            else if (w >= pl->hybrid_min_waves) policy = SKGEMM_POLICY_2TILE_SK_DP;
+            else policy = SKGEMM_POLICY_DP_1TILE_SK;
+        } else if (policy == SKGEMM_POLICY_AUTO) {
             if (r == 0) {
                 policy = SKGEMM_POLICY_DP;
-            } else if (uniform_ipt(*pl) && w >= kAutoMaxWaves) {
+            } else if (w >= kAutoMaxWaves) {
                 // enough whole waves that the remainder is a small part of the
                 // time: persistent workgroups with a fixed share of
                 // data-parallel tiles lose more to their uneven progress than
                 // a split remainder gains (FP64 8192^3: -5 %)
                 policy = SKGEMM_POLICY_DP;
-            } else if (uniform_ipt(*pl)) {
+            } else {
                 // Tile-aligned split of the remainder: with g = s * (its tile
                 // count) and proportional shares, every tile is cut into s
                 // parts at the same k-offsets, so the workgroups of an XCD
                 // stream the same k-slabs at the same time and share them in
                 // L2.  Unaligned shares start each workgroup at its own
                 // k-offset, which on MI355X's per-XCD L2 costs up to 2x.
-                const int64_t sk_t = w == 0 ? t : r;
+                const int64_t sk_t = w == 0 ? t_work : r;
                 const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model);
                 if (s_best == 1) policy = SKGEMM_POLICY_DP;
                 else {
                     policy = w == 0 ? SKGEMM_POLICY_SK : SKGEMM_POLICY_DP_1TILE_SK;
                     auto_g = int(sk_t * s_best);
                 }
-            } else if (w == 0) {
-                policy = SKGEMM_POLICY_SK;
-            } else if (w >= pl->hybrid_min_waves) {
-                policy = SKGEMM_POLICY_2TILE_SK_DP;
-            } else {
-                policy = SKGEMM_POLICY_DP_1TILE_SK;
             }
         }
         if (policy == SKGEMM_POLICY_DP) {
             pl->grid = int(t);
         } else {
             if (policy == SKGEMM_POLICY_SK) {
-                pl->sk_tiles = int(t);
+                pl->sk_tiles = int(t_work);
             } else if (policy == SKGEMM_POLICY_DP_1TILE_SK) {
                 pl->sk_tiles = int(r);
                 pl->sk_first = false;
             } else {
-                pl->sk_tiles = int(w == 0 ? t : r + p);
+                pl->sk_tiles = int(w == 0 ? t_work : r + p);
             }
             // iterations of the Stream-K region [0, sk_tiles)
             const int pi = find_last_le32(pl->tile_base, np, pl->sk_tiles);
@@ -395,8 +409,8 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
             if (policy == SKGEMM_POLICY_SK) {
                 if (o.force_g) pl->g_sk = o.force_g;
                 else if (auto_g) pl->g_sk = auto_g;
-                else if (t >= p) pl->g_sk = int(p);
-                else pl->g_sk = model_best_g(t, ipt, p, pl->model);
+                else if (t_work >= p) pl->g_sk = int(p);
+                else pl->g_sk = model_best_g(t_work, ipt, p, pl->model);
                 pl->grid = pl->g_sk;
             } else {
                 if (pl->sk_tiles)
@@ -459,7 +473,7 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
         return SKGEMM_ERR_INVALID_ARG;
     if (o.raster_rows < 0 || o.raster_rows > kMaxRaster || o.xcds < 0 || o.xcds > kMaxXcds)
         return SKGEMM_ERR_INVALID_ARG;
-    if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_2TILE_SK_DP) return SKGEMM_ERR_INVALID_ARG;
+    if (o.policy < SKGEMM_POLICY_AUTO || o.policy > SKGEMM_POLICY_PAPER) return SKGEMM_ERR_INVALID_ARG;
     pl->la = la; pl->lb = lb; pl->lc = lc;
     pl->ta = ta; pl->tc = tc;
     pl->dtype = to_dt(ta);
@@ -529,7 +543,10 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
         pl->variant = v;
         pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
         model_for(pl->dtype, v, pl->model);
-        for (int i = 0; i < G; ++i) add_problem(pl, M[i], N[i], K[i]);
+        for (int j = 0; j < G; ++j) {
+            const int i = pl->order[j];
+            add_problem(pl, M[i], N[i], K[i]);
+        }
         skgemm_status_t st = SKGEMM_OK;
         if (!pl->G) {
             pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(pl->K);
@@ -608,6 +625,7 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     if (st != SKGEMM_OK) return st;
     base.M = M; base.N = N; base.K = K;
     base.G = 0;
+    base.order.assign(1, 0);
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
     if (st != SKGEMM_OK) return st;
@@ -625,7 +643,6 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
     for (int i = 0; i < G; ++i) {
         if (M[i] < 0 || N[i] < 0 || K[i] < 0 || M[i] > kMaxDim || N[i] > kMaxDim || K[i] > kMaxDim)
             return SKGEMM_ERR_INVALID_ARG;
-        if (K[i] == 0 && M[i] > 0 && N[i] > 0) return SKGEMM_ERR_UNSUPPORTED;   // tiles without iterations
     }
     skgemm_options_t o;
     skgemm_default_options(&o);
@@ -635,6 +652,12 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
     skgemm_status_t st = init_common(&base, la, lb, lc, ta, tb, tc, o);
     if (st != SKGEMM_OK) return st;
     base.G = G;
+    // iteration-space order: problems with MAC-loop iterations in the given
+    // order, then the K = 0 problems that have tiles (epilogue only)
+    base.order.clear();
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < G; ++i)
+            if ((K[i] == 0 && M[i] > 0 && N[i] > 0) == (pass == 1)) base.order.push_back(i);
     base.M = base.N = base.K = 0;
     base.Ml = base.Nl = base.Kl = 0;
     base.tm = base.tn = base.ipt = 0;
@@ -771,7 +794,7 @@ skgemm_status_t skgemm_grouped_table(skgemm_plan_t pl, const skgemm_group_args_t
     for (int i = 0; i < pl->G; ++i) {
         GroupEntry e;
         std::memset(&e, 0, sizeof(e));
-        const skgemm_group_args_t& g = args[i];
+        const skgemm_group_args_t& g = args[pl->order[i]];
         const skgemm_status_t st =
             check_problem(pl, pl->gM[i], pl->gN[i], pl->gK[i], g.A, g.lda, g.B, g.ldb, g.C, g.ldc, &e);
         if (st != SKGEMM_OK) return st;

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(PKG, "libskgemm.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_CAPACITY, ERR_HIP, ERR_TIMEOUT = range(7)
 ROW_MAJOR, COL_MAJOR = 0, 1
 F32, F16, BF16, F8E4M3, F64 = 0, 1, 2, 3, 4
-POLICY = {"auto": 0, "dp": 1, "sk": 2, "dp_1tile_sk": 3, "2tile_sk_dp": 4}
+POLICY = {"auto": 0, "dp": 1, "sk": 2, "dp_1tile_sk": 3, "2tile_sk_dp": 4, "paper": 5}
 POLICY_NAME = {v: k for k, v in POLICY.items()}
 ROLE_NAME = {0: "full", 1: "partial", 2: "owner"}
 

@@ -9,7 +9,7 @@ import numpy as np
 from oracle import schedule as S
 
 ROLE = {0: S.FULL, 1: S.PARTIAL, 2: S.OWNER}
-POLICY_ID = {"auto": 0, "dp": 1, "sk": 2, "dp_1tile_sk": 3, "2tile_sk_dp": 4}
+POLICY_ID = {"auto": 0, "dp": 1, "sk": 2, "dp_1tile_sk": 3, "2tile_sk_dp": 4, "paper": 5}
 POLICY_BY_ID = {v: k for k, v in POLICY_ID.items()}
 
 
@@ -27,17 +27,39 @@ SHARE_BY_ID = {0: "proportional", 1: "leading"}
 
 
 def oracle_plan_for(info, model, policy, force_g=0):
-    """The oracle's plan for the problem a library plan launches."""
+    """The oracle's plan for the problem a library plan launches.
+
+    The library resolves "auto" by its own rule (a design choice for the
+    target GPU, not the paper's selection); such a plan is rebuilt here from
+    the explicit policy and grid it resolved to, so the comparison checks the
+    schedule of that resolved plan, not the rule that picked it."""
+    if policy == "auto":
+        policy, force_g = resolved(info)
+    elif policy == "paper":       # the library's name for the paper's own selection
+        policy = "auto"
     return S.make_plan(int(info["M"]), int(info["N"]), int(info["K"]), int(info["BM"]), int(info["BN"]),
                        int(info["BK"]), int(info["p"]), policy=policy, force_g=force_g,
-                       hybrid_min_waves=int(info["hybrid_min_waves"]), model=model_with_cus(info, model),
+                       hybrid_min_waves=int(info["hybrid_min_waves"]), model=tuple(model)[:4],
                        share=SHARE_BY_ID[int(info.get("share", 0))])
 
 
-def model_with_cus(info, model):
-    """The library's (a, b, c, d, e) plus the CU count of the plan, the form the
-    oracle's split rule takes."""
-    return tuple(model)[:5] + (int(info["p"]) // int(info["occupancy"]),)
+def oracle_grouped_plan_for(problems, info, model, policy, force_g=0):
+    """The grouped oracle's plan for the problems a grouped library plan
+    launches (problems as given; "auto" rebuilt from its resolved form)."""
+    from oracle import grouped as GR
+    if policy == "auto":
+        policy, force_g = resolved(info)
+    elif policy == "paper":
+        policy = "auto"
+    return GR.make_grouped_plan(problems, int(info["BM"]), int(info["BN"]), int(info["BK"]), int(info["p"]),
+                                policy=policy, force_g=force_g, hybrid_min_waves=int(info["hybrid_min_waves"]),
+                                model=tuple(model)[:4], share=SHARE_BY_ID[int(info.get("share", 0))])
+
+
+def resolved(info):
+    """(explicit policy, forced grid) a library plan resolved to."""
+    pol = POLICY_BY_ID[int(info["policy"])]
+    return pol, (int(info["g_sk"]) if pol != "dp" else 0)
 
 
 def bits_u16(t):

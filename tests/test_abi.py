@@ -12,7 +12,7 @@ import re
 
 import pytest
 
-from helpers import POLICY_BY_ID, model_with_cus, oracle_plan_for, records_to_schedule
+from helpers import POLICY_BY_ID, oracle_grouped_plan_for, oracle_plan_for, records_to_schedule, resolved
 from oracle import schedule as S
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -103,7 +103,7 @@ SHAPES = [(384, 384, 1024), (896, 384, 128), (1, 1, 1), (300, 500, 700), (4096, 
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-@pytest.mark.parametrize("policy", ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
+@pytest.mark.parametrize("policy", ["auto", "paper", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
 @pytest.mark.parametrize("share", ["proportional", "leading"])
 def test_planner_schedule_matches_enumerator(dtype, policy, share):
     sk = _lib()
@@ -155,7 +155,7 @@ def test_workspace_scales_with_grid_not_problem():
     assert dp.workspace_size() == 0
 
 
-@pytest.mark.parametrize("policy", ["auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
+@pytest.mark.parametrize("policy", ["auto", "paper", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
 def test_grouped_planner_matches_enumerator(policy):
     from oracle import grouped as GR
     import workloads as W
@@ -164,6 +164,9 @@ def test_grouped_planner_matches_enumerator(policy):
         [(m, 4096, 2048) for m in W.zipf_ms(64, seed=0)],
         [(100, 300, 16), (0, 50, 70), (700, 900, 5000), (1, 1, 1)],
         [(256 * 3, 256 * 5, 640)] * 7,
+        # K = 0 problems (epilogue-only tiles) between problems with iterations
+        [(300, 700, 0), (1000, 900, 3000), (64, 64, 0), (0, 50, 0), (500, 256, 640), (900, 900, 0)],
+        [(256, 256, 0)] * 3,
     ]
     for probs, (cus, occ) in itertools.product(groups, [(256, 1), (16, 1), (37, 2)]):
         Ms, Ns, Ks = zip(*probs)
@@ -173,8 +176,7 @@ def test_grouped_planner_matches_enumerator(policy):
             assert e.status == sk.ERR_CAPACITY
             continue
         info = p.info()
-        ref = GR.make_grouped_plan(probs, info["BM"], info["BN"], info["BK"], info["p"], policy=policy,
-                                   hybrid_min_waves=2, model=model_with_cus(info, p.model_constants()))
+        ref = oracle_grouped_plan_for(probs, info, p.model_constants(), policy)
         assert (ref.policy, ref.sk_tiles, ref.g_sk, ref.grid) == (
             POLICY_BY_ID[info["policy"]], info["sk_tiles"], info["g_sk"], info["grid"])
         got = records_to_schedule(p.schedule(), info["grid"])
@@ -191,8 +193,10 @@ def test_grouped_and_quantize_argument_errors():
     o.num_cus, o.occupancy = 256, 1
     assert L.skgemm_grouped_plan(ctypes.byref(h), 0, arr(1, 1), arr(1, 1), arr(1, 1), 0, 0, 0, sk.BF16, sk.BF16,
                                  sk.BF16, ctypes.byref(o)) == sk.ERR_INVALID_ARG
+    # a K = 0 problem is planned (its tiles only apply the epilogue)
     assert L.skgemm_grouped_plan(ctypes.byref(h), 2, arr(4, 4), arr(4, 4), arr(4, 0), 0, 0, 0, sk.BF16, sk.BF16,
-                                 sk.BF16, ctypes.byref(o)) == sk.ERR_UNSUPPORTED
+                                 sk.BF16, ctypes.byref(o)) == sk.OK
+    L.skgemm_plan_destroy(h)
     g = sk.GroupedPlan([64, 64], [64, 64], [64, 64], ta=sk.BF16, num_cus=256, occupancy=1)
     fake = 1 << 40
     bad = [(fake, 63, fake, 64, fake, 64, 1.0, 0.0), (fake, 64, fake, 64, fake, 64, 1.0, 0.0)]   # lda < K

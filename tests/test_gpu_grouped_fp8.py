@@ -21,7 +21,7 @@ import pytest
 import torch
 
 import workloads as W
-from helpers import model_with_cus, records_to_schedule, to_f64
+from helpers import oracle_grouped_plan_for, records_to_schedule, to_f64
 from oracle import gemm as og
 from oracle import grouped as GR
 from oracle import lowp
@@ -88,7 +88,7 @@ def test_grouped_integer_exact_forced_grids(tile):
             assert np.array_equal(to_f64(C), ref), fg
 
 
-@pytest.mark.parametrize("policy", ["auto", "sk", "2tile_sk_dp"])
+@pytest.mark.parametrize("policy", ["auto", "paper", "sk", "2tile_sk_dp"])
 @pytest.mark.parametrize("tile", [None, (128, 128, 64, 4), (128, 128, 64, 8)])
 def test_grouped_trace_matches_enumerator(policy, tile):
     Ms = W.zipf_ms(64, seed=0)
@@ -102,8 +102,7 @@ def test_grouped_trace_matches_enumerator(policy, tile):
     torch.cuda.synchronize()
     recs = [tuple(int(v) for v in r) for r in tr.cpu().numpy().reshape(-1, 8) if r[0] != -7]
     got = records_to_schedule(recs, info["grid"])
-    ref = GR.make_grouped_plan(shapes, info["BM"], info["BN"], info["BK"], info["p"], policy=policy,
-                               model=model_with_cus(info, p.model_constants()))
+    ref = oracle_grouped_plan_for(shapes, info, p.model_constants(), policy)
     assert got == GR.enumerate_grouped_schedule(ref)
 
 

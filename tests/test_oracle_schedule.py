@@ -151,26 +151,37 @@ def test_sk_with_g_multiple_of_t_is_fixed_split(s):
     assert S.enumerate_schedule(sk) == S.fixed_split_schedule(pl.t, pl.ipt, s)
 
 
-def test_auto_policy_regimes():
-    p = 256
-    m = (0, 20, 1, 8)
-    # full waves only -> data-parallel
-    assert S.make_plan(8192, 8192, 8192, 256, 256, 64, p).policy == "dp"
-    # fewer tiles than workgroups -> basic Stream-K with g a multiple of t (each tile cut into
-    # s parts), or data-parallel when the model prefers s = 1
-    pl = S.make_plan(384, 384, 8192, 128, 128, 32, p, model=m)
-    assert pl.policy == "sk" and pl.g_sk % pl.t == 0 and pl.t < pl.g_sk <= p
-    assert pl.g_sk // pl.t == S.model_best_split(pl.t, pl.ipt, p, m)
-    pl = S.make_plan(384, 384, 64, 128, 128, 32, p, model=m)      # two iterations per tile
-    assert pl.policy == "dp" and pl.grid == pl.t
-    # full waves plus a remainder -> DP + one-tile SK over the remainder with g = s * r
-    for waves in (1, 2, 3):
-        pl = S.make_plan(256 * (16 * waves + 1), 256 * 16, 4096, 256, 256, 64, p, model=m)
-        assert pl.policy == "dp_1tile_sk" and pl.sk_tiles == 16 and pl.g_sk % 16 == 0
-        assert pl.g_sk // 16 == S.model_best_split(16, pl.ipt, p, m) and pl.grid == p
-    # from AUTO_MAX_WAVES full waves on the remainder is left data-parallel
-    pl = S.make_plan(256 * (16 * S.AUTO_MAX_WAVES + 1), 256 * 16, 4096, 256, 256, 64, p, model=m)
-    assert pl.policy == "dp" and pl.grid == pl.t
+def test_auto_policy_is_the_papers_selection():
+    """The oracle's "auto" follows the Data-parallel Hybridization subsection,
+    each branch pinned by a hand-worked case."""
+    # tiles fill whole waves (1024 tiles of 256x256 on 256 workgroups): data-parallel
+    pl = S.make_plan(8192, 8192, 8192, 256, 256, 64, 256)
+    assert (pl.policy, pl.grid, pl.g_sk) == ("dp", 1024, 0)
+    # fewer tiles than workgroups: basic Stream-K with the model's grid, which
+    # reproduces the published grid sizes of the model figure
+    tile = GOLDEN["model_tile"]
+    for e in GOLDEN["model"]:
+        pl = S.make_plan(e["M"], e["N"], e["K"], tile["BM"], tile["BN"], tile["BK"], p=tile["p"],
+                         model=(0.0, 20.0, 1.0, 8.0))
+        assert (pl.policy, pl.sk_tiles, pl.g_sk, pl.grid) == ("sk", e["tiles"], e["g_best"], e["g_best"])
+    # two full waves and one tile over (the 896x384 example on four SMs):
+    # two-tile SK + DP over r + p = 5 tiles, then the 16 others data-parallel
+    pl = S.make_plan(896, 384, 128, 128, 128, 4, p=4)
+    assert (pl.policy, pl.sk_tiles, pl.g_sk, pl.grid, pl.sk_first) == ("2tile_sk_dp", 5, 4, 4, True)
+    # one full wave and a remainder: DP + one-tile SK, g = min(p, r * ipt)
+    pl = S.make_plan(128 * 5, 128, 64, 128, 128, 32, p=4)      # t = 5, r = 1, ipt = 2
+    assert (pl.policy, pl.sk_tiles, pl.g_sk, pl.grid, pl.sk_first) == ("dp_1tile_sk", 1, 2, 4, False)
+    pl = S.make_plan(128 * 7, 128, 1024, 128, 128, 32, p=4)    # t = 7, r = 3, ipt = 32
+    assert (pl.policy, pl.sk_tiles, pl.g_sk, pl.grid) == ("dp_1tile_sk", 3, 4, 4)
+    # the two-tile threshold is hybrid_min_waves full waves
+    pl = S.make_plan(896, 384, 128, 128, 128, 4, p=4, hybrid_min_waves=6)    # w = 5
+    assert (pl.policy, pl.sk_tiles) == ("dp_1tile_sk", 1)
+    pl = S.make_plan(896, 384, 128, 128, 128, 4, p=4, hybrid_min_waves=5)
+    assert (pl.policy, pl.sk_tiles) == ("2tile_sk_dp", 5)
+    # K = 0: epilogue-only tiles, data-parallel whatever the policy
+    for pol in S.POLICIES:
+        pl = S.make_plan(300, 300, 0, 128, 128, 32, p=4, policy=pol)
+        assert (pl.policy, pl.grid) == ("dp", 9)
 
 
 @pytest.mark.parametrize("t,ipt,s", [(3, 10, 4), (7, 9, 2), (5, 64, 8), (12, 88, 10), (1, 7, 7)])
@@ -256,23 +267,29 @@ def test_grouped_ragged_invariants():
                 GR.check_grouped_invariants(g, GR.enumerate_grouped_schedule(g))
 
 
-def test_split_rule_occupancy_term():
-    """The split rule's CU term: with e = c it is the four-constant rule; with a
-    prohibitive e it never picks a grid above the CU count when one fits."""
-    rng = np.random.default_rng(7)
-    for _ in range(300):
-        t = int(rng.integers(1, 300))
-        ipt = int(rng.integers(1, 80))
-        cus = int(rng.choice([64, 128, 256]))
-        p = cus * int(rng.integers(1, 3))
-        a, b, c, d = (float(v) for v in rng.uniform(0.1, 10.0, 4))
-        assert S.model_best_split(t, ipt, p, (a, b, c, d, c, cus)) == S.model_best_split(t, ipt, p, (a, b, c, d))
-        s = S.model_best_split(t, ipt, p, (a, b, c, d, 1e9, cus))
-        if t <= cus:
-            assert s * t <= cus, (t, ipt, p, cus, s)
-        # two slots per CU: any grid above the CU count pays e per iteration
-        e = c * float(rng.uniform(1.0, 3.0))
-        s = S.model_best_split(t, ipt, 2 * cus, (a, b, c, d, e, cus))
-        smax = max(1, min(2 * cus // t, ipt))
-        cost = [S.model_time(k * t, t, ipt, a, b, e if k * t > cus else c, d) for k in range(1, smax + 1)]
-        assert s == 1 + int(np.argmin(cost))
+def test_grouped_zero_k_problems_are_epilogue_tiles_after_the_rest():
+    """Problems with K = 0 leave the Stream-K schedule of the others unchanged
+    wherever they sit in the list: their tiles come last and each is one
+    data-parallel segment with no iterations (C = beta * C)."""
+    from oracle import grouped as GR
+    work = [(1000, 900, 3000), (500, 256, 640), (128, 700, 130)]
+    zero = [(300, 700, 0), (64, 64, 0), (0, 50, 0)]
+    for p, pol in itertools.product([4, 9, 64], ["auto", "sk", "dp", "dp_1tile_sk", "2tile_sk_dp"]):
+        base = GR.make_grouped_plan(work, 128, 128, 32, p, policy=pol, model=(0, 20, 1, 8))
+        mixed_list = [zero[0], work[0], zero[1], work[1], zero[2], work[2]]
+        mixed = GR.make_grouped_plan(mixed_list, 128, 128, 32, p, policy=pol, model=(0, 20, 1, 8))
+        assert mixed.order == [1, 3, 4, 5, 0, 2]     # (0, 50, 0) has no tiles: it stays in place
+        n_zero = sum(-(-M // 128) * -(-N // 128) for M, N, K in zero)
+        assert mixed.t == base.t + n_zero and mixed.total_iters == base.total_iters
+        assert (mixed.sk_tiles, mixed.g_sk, mixed.sk_iters) == (base.sk_tiles, base.g_sk, base.sk_iters)
+        sched = GR.enumerate_grouped_schedule(mixed)
+        GR.check_grouped_invariants(mixed, sched)
+        sk_part = [[s for s in segs if s.tile < base.t] for segs in sched]
+        want = GR.enumerate_grouped_schedule(base)
+        if mixed.grid == base.grid:
+            assert sk_part == want
+        else:   # a data-parallel grid grows by the epilogue tiles
+            assert pol == "dp" or base.policy == "dp"
+        zero_segs = [s for segs in sched for s in segs if s.tile >= base.t]
+        assert sorted(s.tile for s in zero_segs) == list(range(base.t, mixed.t))
+        assert all((s.k_lo, s.k_hi, s.role) == (0, 0, S.FULL) for s in zero_segs)
