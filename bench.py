@@ -17,7 +17,10 @@ Printed JSON line (rank 0):
                per tile) over the same shapes: the paper's baseline
   sk_over_dp_* per-shape speedups (geomean / min / median / max), over all
                shapes and over the quantisation-bound subset (tiles fill
-               less than 90% of the last wave)
+               less than 90% of the last wave), warm (resident caches) and
+               cold (L2 and MALL flushed before each launch)
+  large_shapes BF16 4096^3 and 8192^3 with the automatic policy (TFLOP/s,
+               % of the dense BF16 peak)
   cpu_baseline the FP64 oracle on the host cores over a bounded sample of
                the sweep
 """
@@ -74,6 +77,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-shape", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the BF16 4096^3 and 8192^3 timings")
+    ap.add_argument("--no-waits", action="store_true", help="skip the timed pass that measures fix-up waits")
     ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many Stream-K steps (for profiler runs) and print timings")
@@ -87,7 +92,7 @@ def parse():
 
 
 class Case:
-    __slots__ = ("M", "N", "K", "A", "B", "C", "sk", "dp", "flops", "bytes", "t", "p")
+    __slots__ = ("M", "N", "K", "A", "B", "C", "sk", "dp", "flops", "bytes", "fixup_bytes", "t", "p")
 
 
 def build_cases(shapes, torch, sk):
@@ -109,6 +114,10 @@ def build_cases(shapes, torch, sk):
         c.t, c.p = info["t"], info["p"]
         c.flops = 2.0 * M * N * K
         c.bytes = 2 * (M * K + K * N + M * N)       # read A and B once, write C once (bf16)
+        # the method's own traffic: every partial segment writes one FP32 tile
+        # and its reducer reads it back
+        n_partials = sum(1 for r in c.sk.schedule() if r[5] == 1)
+        c.fixup_bytes = 2 * n_partials * info["BM"] * info["BN"] * 4
         cases.append(c)
     return cases
 
@@ -129,6 +138,63 @@ def make_launcher(c, plan, ws, stream):
         if st != 0:
             raise sk.SkgemmError(st, "skgemm_run")
     return launch
+
+
+def fixup_waits(cases, ws, stream, torch, np):
+    """Time spent in the fix-up waits over the sweep's Stream-K plans, from
+    one timed run each (segment stamps of the device's real-time clock): the
+    share of the Stream-K workgroups' time spent waiting for peers' partial
+    tiles, split by how many workgroups share a tile (the paper expects the
+    waits to be negligible when at most two do, and not when three or more
+    finish their shares of one tile together)."""
+    from paper_2212_08964_amd import skgemm as sk
+    hz = sk.realtime_hz()
+    agg = {"le2": [0.0, 0.0, 0], "ge3": [0.0, 0.0, 0]}
+    waits_us = []
+    for c in cases:
+        info = c.sk.info()
+        if not info["g_sk"]:
+            continue
+        cap = c.sk.trace_capacity()
+        tr = torch.full((cap * 8,), -1, dtype=torch.int32, device="cuda:0")
+        tm = torch.zeros((cap * 5,), dtype=torch.int64, device="cuda:0")
+        args = (c.A.data_ptr(), c.K, c.B.data_ptr(), c.N, c.C.data_ptr(), c.N, 1.0, 0.0, None, None,
+                ws.data_ptr(), c.sk.workspace_size())
+        c.sk.run(*args, stream=stream)
+        c.sk.run_timed(*args, tr.data_ptr(), tm.data_ptr(), cap, stream=stream)
+        torch.cuda.synchronize()
+        recs = tr.cpu().numpy().reshape(-1, 8)
+        st = tm.cpu().numpy().reshape(-1, 5).astype(np.float64) / hz * 1e6
+        used = recs[:, 0] >= 0
+        recs, st = recs[used], st[used]
+        contrib = {}
+        for r in recs:
+            if r[0] < info["g_sk"] and r[2] < info["sk_tiles"]:
+                contrib.setdefault(int(r[2]), set()).add(int(r[0]))
+        key = "le2" if max((len(v) for v in contrib.values()), default=1) <= 2 else "ge3"
+        busy = wait = 0.0
+        for wg in range(info["g_sk"]):
+            m = recs[:, 0] == wg
+            if not m.any():
+                continue
+            busy += st[m, 4].max() - st[m, 0].min()
+            w = float((st[m, 3] - st[m, 2]).sum())
+            wait += w
+            if w > 0:
+                waits_us.append(w)
+        agg[key][0] += wait
+        agg[key][1] += busy
+        agg[key][2] += 1
+    out = {"plans": sum(v[2] for v in agg.values()),
+           "clock_hz": hz,
+           "note": "wait = stamps between the partial stores and the end of the fix-up waits, summed over the "
+                   "Stream-K workgroups; share = wait / (their first-segment start to last-segment end)"}
+    for k, (w, b, n) in agg.items():
+        out[f"share_{k}_contributors"] = round(w / b, 4) if b else None
+        out[f"plans_{k}_contributors"] = n
+    if waits_us:
+        out["median_wait_us_of_waiting_workgroups"] = round(float(np.median(waits_us)), 3)
+    return out
 
 
 def cpu_baseline(shapes, budget_s):
@@ -404,8 +470,8 @@ def main():
             dst.copy_(src)
             torch.cuda.synchronize()
             print(f"copy probe: {nb} bytes read, {nb} bytes written", flush=True)
-        print(f"algorithmic bytes per step: {sum(c.bytes for c in cases)}; launches per step: {len(cases)}",
-              flush=True)
+        print(f"algorithmic bytes per step: {sum(c.bytes + c.fixup_bytes for c in cases)} "
+              f"(fix-up {sum(c.fixup_bytes for c in cases)}); launches per step: {len(cases)}", flush=True)
         return
 
     for _ in range(args.warmup):
@@ -442,48 +508,106 @@ def main():
     dp_ms_per_step = start.elapsed_time(end) / args.steps
     dp_value = total_flops / (dp_ms_per_step * 1e-3) / 1e12
 
-    # ---- per-shape times (both policies, back-to-back launches, best-of events)
+    # ---- per-shape times, both policies in alternating rounds (no policy
+    # always runs first).  Warm: median over 5 rounds of back-to-back launches
+    # on resident buffers.  Cold: median over 5 single launches, each after a
+    # 512 MiB write that evicts the L2 caches and the MALL.
     ratios = None
     if not args.no_per_shape:
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        t_sk = np.zeros(n)
-        t_dp = np.zeros(n)
+        flush = torch.empty(512 << 18, dtype=torch.float32, device="cuda:0")
+        rounds = 5
+        w_sk, w_dp = np.zeros((n, rounds)), np.zeros((n, rounds))
+        c_sk, c_dp = np.zeros((n, rounds)), np.zeros((n, rounds))
         for i in range(n):
-            t_sk[i] = t_dp[i] = float("inf")
-            # alternating rounds, best of each: no policy always runs first (colder)
-            for _ in range(3):
-                for arr, f in ((t_sk, sk_launch[i]), (t_dp, dp_launch[i])):
+            for r in range(rounds):
+                for arr, f in ((w_sk, sk_launch[i]), (w_dp, dp_launch[i])):
                     f()
                     e0.record(stream)
                     for _ in range(args.reps):
                         f()
                     e1.record(stream)
                     e1.synchronize()
-                    arr[i] = min(arr[i], e0.elapsed_time(e1) / args.reps)
+                    arr[i, r] = e0.elapsed_time(e1) / args.reps
+                for arr, f in ((c_sk, sk_launch[i]), (c_dp, dp_launch[i])):
+                    flush.fill_(float(r))
+                    e0.record(stream)
+                    f()
+                    e1.record(stream)
+                    e1.synchronize()
+                    arr[i, r] = e0.elapsed_time(e1)
+        t_sk, t_dp = np.median(w_sk, axis=1), np.median(w_dp, axis=1)
+        tc_sk, tc_dp = np.median(c_sk, axis=1), np.median(c_dp, axis=1)
+        del flush
         ratios = t_dp / t_sk
+        ratios_cold = tc_dp / tc_sk
         qb = np.array([c.t / (c.p * math.ceil(c.t / c.p)) < 0.9 for c in cases])
         if args.dump:
             with open(args.dump, "w") as fh:
-                for c, a_, b_ in zip(cases, t_sk, t_dp):
+                for c, a_, b_, ac, bc in zip(cases, t_sk, t_dp, tc_sk, tc_dp):
                     info = c.sk.info()
                     fh.write(json.dumps({"M": c.M, "N": c.N, "K": c.K, "t": c.t, "ipt": info["ipt"],
-                                         "tile": info["BM"], "policy": info["policy_name"], "g": info["g_sk"],
-                                         "sk_us": a_ * 1e3,
-                                         "dp_us": b_ * 1e3, "gflop": c.flops / 1e9}) + "\n")
+                                         "tile": info["BM"], "waves": info["waves"], "policy": info["policy_name"],
+                                         "g": info["g_sk"], "sk_us": a_ * 1e3, "dp_us": b_ * 1e3,
+                                         "sk_cold_us": ac * 1e3, "dp_cold_us": bc * 1e3,
+                                         "gflop": c.flops / 1e9}) + "\n")
 
         def stats(r):
             return {"geomean": float(np.exp(np.mean(np.log(r)))), "min": float(r.min()),
                     "median": float(np.median(r)), "max": float(r.max()), "n": int(r.size)}
         flops_arr = np.array([c.flops for c in cases])
         per_shape = {
+            "timing": f"warm: median of {rounds} rounds of {args.reps} back-to-back launches; cold: median of "
+                      f"{rounds} single launches each after a 512 MiB write (L2 and MALL evicted)",
             "all": stats(ratios),
             "quantization_bound": stats(ratios[qb]) if qb.any() else None,
+            "cold_all": stats(ratios_cold),
+            "cold_quantization_bound": stats(ratios_cold[qb]) if qb.any() else None,
             "sk_tflops_geomean": float(np.exp(np.mean(np.log(flops_arr / (t_sk * 1e-3) / 1e12)))),
             "dp_tflops_geomean": float(np.exp(np.mean(np.log(flops_arr / (t_dp * 1e-3) / 1e12)))),
             "sk_tflops_max": float((flops_arr / (t_sk * 1e-3) / 1e12).max()),
         }
     torch.cuda.synchronize()
+
+    waits = None if args.no_waits else fixup_waits(cases, ws, sptr, torch, np)
+
+    # ---- the large-shape target: BF16 4096^3 and 8192^3 (automatic policy)
+    large = {}
+    if not args.no_large:
+        for L_ in (4096, 8192):
+            lc = Case()
+            lc.M = lc.N = lc.K = L_
+            lc.A = torch.randn((L_, L_), device="cuda:0", dtype=torch.float32).to(torch.bfloat16)
+            lc.B = torch.randn((L_, L_), device="cuda:0", dtype=torch.float32).to(torch.bfloat16)
+            lc.C = torch.empty((L_, L_), device="cuda:0", dtype=torch.bfloat16)
+            plan = sk.Plan(L_, L_, L_, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="auto")
+            lws = torch.zeros(max(plan.workspace_size(), 256), dtype=torch.uint8, device="cuda:0")
+            f = make_launcher(lc, plan, lws, sptr)
+            for _ in range(3):
+                f()
+            reps = 20 if L_ == 4096 else 8
+            times = []
+            for _ in range(5):
+                start.record(stream)
+                for _ in range(reps):
+                    f()
+                end.record(stream)
+                end.synchronize()
+                times.append(start.elapsed_time(end) / reps)
+            ms = float(np.median(times))
+            tf = 2.0 * L_ ** 3 / (ms * 1e-3) / 1e12
+            info = plan.info()
+            large[f"bf16_{L_}"] = {"tflops": round(tf, 1), "pct_peak": round(100.0 * tf / PEAK_BF16_TFLOPS, 2),
+                                   "us": round(ms * 1e3, 2), "policy": info["policy_name"],
+                                   "tile": list(info["tile"])}
+            del lc, lws
+        torch.cuda.synchronize()
+
+    sk_bytes = [c.bytes + c.fixup_bytes for c in cases]
+    # per-shape roofline: each GEMM at max(flops / MFMA peak, algorithmic bytes / HBM bandwidth)
+    roof_ms = sum(max(c.flops / (PEAK_BF16_TFLOPS * 1e12), b / (HBM_GBS * 1e9)) for c, b in zip(cases, sk_bytes))
+    roof_ms *= 1e3
 
     out = {
         "metric": METRIC,
@@ -511,13 +635,20 @@ def main():
         "dp_ms_per_step": round(dp_ms_per_step, 4),
         "sk_over_dp_aggregate": round(value / dp_value, 4),
         "sk_over_dp_per_shape": ratios is not None and per_shape or None,
+        "large_shapes": large or None,
+        "fixup_waits": waits,
         "plan_us_per_gemm": round(plan_us, 2),
         "setup_s": round(plan_s, 2),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
                      "traffic": TRAFFIC_BYTES_PER_LAUNCH if kernel_sources_hash() == TRAFFIC_SOURCES_SHA256 else None,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "algorithmic_bytes_per_launch": round(sum(c.bytes for c in cases) / n),
+                     "algorithmic_bytes_per_launch": round(sum(sk_bytes) / n),
+                     "algorithmic_bytes_note": "A and B read once, C written once (bf16), plus the fix-up: "
+                                               "2 x partial segments x BM x BN x 4 bytes",
+                     "fixup_bytes_per_launch": round(sum(c.fixup_bytes for c in cases) / n),
+                     "per_shape_roofline_ms": round(roof_ms, 4),
+                     "per_shape_roofline_frac": round(roof_ms / ms_per_step, 4),
                      "kernel": "skgemm_kernel<BF16, A K-contiguous, B N-contiguous>",
                      "avg_launch_us": round(avg_launch_us, 3),
                      "flops_per_launch": round(total_flops / n, 1)},

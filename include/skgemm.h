@@ -195,6 +195,25 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
                                   void* workspace, size_t ws_bytes,
                                   int32_t* trace, size_t trace_records, hipStream_t stream);
 
+/* Same as skgemm_run_traced, and each traced segment also gets five
+ * timestamps of the device's constant-rate real-time clock
+ * (skgemm_realtime_hz ticks per second), taken by the workgroup's first
+ * thread: {segment start, MAC loop done, partial stores and ready flags
+ * done, fix-up waits done, segment done}.  times is device memory of
+ * 5 * trace_records uint64 values, laid out like the records (record i's
+ * stamps at 5 * i).  The gap between the third and fourth stamp is the time
+ * a workgroup spent waiting for its peers' partial tiles (the Wait of the
+ * basic Stream-K algorithm); it is zero for segments that wait for nobody. */
+skgemm_status_t skgemm_run_timed(skgemm_plan_t plan,
+                                 const void* A, int64_t lda, const void* B, int64_t ldb,
+                                 void* C, int64_t ldc, float alpha, float beta,
+                                 const float* scale_a, const float* scale_b,
+                                 void* workspace, size_t ws_bytes,
+                                 int32_t* trace, uint64_t* times, size_t trace_records, hipStream_t stream);
+
+/* Ticks per second of the real-time clock skgemm_run_timed reads (current device). */
+skgemm_status_t skgemm_realtime_hz(int64_t* hz);
+
 /* Resolved plan, for logging and for comparing with an independent
  * enumerator of the schedule.  info[] receives, in order:
  *   0 M', 1 N', 2 K (problem as launched: M' = N and N' = M when C is
@@ -206,8 +225,10 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
  *   grouped plan, 0 for one GEMM; fields 0-2, 7, 8 and 10 are 0 then and
  *   field 9 is the total tile count), 21 share (skgemm_share_t), 22 shares per
  * tile under the split fix-up (0 = owner fix-up), 23 workgroups per CU
- * (p = CUs * field 23), 24 wavefronts per workgroup.
- * n is the capacity of info; up to 25 values are written. */
+ * (p = CUs * field 23), 24 wavefronts per workgroup, 25 batch (1 unless a
+ * strided batched plan, whose fields 7 and 8 describe one problem and
+ * field 9 counts the tiles of the whole batch).
+ * n is the capacity of info; up to 26 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)
@@ -265,18 +286,55 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
                                           size_t ws_bytes, int32_t* trace, size_t trace_records,
                                           hipStream_t stream);
 
+/* ---------------------------------------------------------------- strided batched GEMM
+ * batch equal problems C_i = alpha * s_A * s_B * A_i * B_i + beta * C_i,
+ * i = 0 .. batch-1, whose operands lie at fixed element strides from the
+ * first problem's (A_i = A + i * stride_a, and so on): one persistent launch
+ * over the concatenated iteration space (problem 0's tiles first), split by
+ * the same policies as one GEMM (the generalisation of Stream-K to other
+ * GEMM-like problems the conclusion of the Stream-K chapter points to).  No
+ * table: the kernel finds a tile's problem by one division.  Layouts, types,
+ * options and workspace as for skgemm_plan / skgemm_run; plan_info field 25
+ * is the batch.  Strides are non-negative element counts; stride_c must keep
+ * consecutive C matrices apart (at least one C's extent) when batch > 1. */
+skgemm_status_t skgemm_batched_plan(skgemm_plan_t* out, int64_t batch, int64_t M, int64_t N, int64_t K,
+                                    skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc,
+                                    skgemm_dtype_t ta, skgemm_dtype_t tb, skgemm_dtype_t tc,
+                                    const skgemm_options_t* opt);
+skgemm_status_t skgemm_batched_run(skgemm_plan_t plan,
+                                   const void* A, int64_t lda, int64_t stride_a,
+                                   const void* B, int64_t ldb, int64_t stride_b,
+                                   void* C, int64_t ldc, int64_t stride_c, float alpha, float beta,
+                                   const float* scale_a, const float* scale_b,
+                                   void* workspace, size_t ws_bytes, hipStream_t stream);
+/* Same, writing schedule records as skgemm_run_traced does (tile = global
+ * tile index: problem i's tiles are i * tiles_per_problem onwards). */
+skgemm_status_t skgemm_batched_run_traced(skgemm_plan_t plan,
+                                          const void* A, int64_t lda, int64_t stride_a,
+                                          const void* B, int64_t ldb, int64_t stride_b,
+                                          void* C, int64_t ldc, int64_t stride_c, float alpha, float beta,
+                                          const float* scale_a, const float* scale_b,
+                                          void* workspace, size_t ws_bytes,
+                                          int32_t* trace, size_t trace_records, hipStream_t stream);
+
 /* ---------------------------------------------------------------- FP8 front end
  * Per-tensor E4M3 quantisation of a rows x cols matrix X (FP32, BF16 or
  * FP16, layout lx, leading dimension ldx) into Q (E4M3FN bytes, layout lq,
  * leading dimension ldq; lq may differ from lx, e.g. to produce the
  * column-major B the FP8 GEMM needs):
- *   *scale = absmax(X) / 448 rounded to FP32 (1 if X is all zero),
+ *   *scale = absmax(X) / 448 rounded to FP32, the maximum taken over the
+ *            finite entries (1 if none of them is nonzero),
  *   Q = round-to-nearest-even E4M3 of clamp(X / scale, -448, 448), the
- *       quotient rounded to FP32.
+ *       quotient rounded to FP32; a NaN or infinite entry gives the NaN
+ *       code 0x7f with the entry's sign (E4M3FN has no infinity), so it
+ *       reaches the product as NaN.
  * scale is one FP32 on the device, to be passed as scale_a / scale_b of the
  * FP8 GEMM.  workspace: device scratch of skgemm_quantize_workspace_size
- * bytes, 4-byte aligned, no initialisation needed.  Inputs must be finite.
- * Asynchronous on stream (three kernel launches). */
+ * bytes, 4-byte aligned, no initialisation needed.  Asynchronous on stream:
+ * two kernel launches (an absmax pass, then a quantising pass that reduces
+ * the maxima itself), or three when the quantising grid exceeds 4096
+ * workgroups (a one-workgroup reduction between them); an empty X gives
+ * scale = 1 (two launches). */
 skgemm_status_t skgemm_quantize_workspace_size(size_t* bytes);
 skgemm_status_t skgemm_quantize_e4m3(const void* X, skgemm_dtype_t tx, int64_t rows, int64_t cols,
                                      skgemm_layout_t lx, int64_t ldx, void* Q, skgemm_layout_t lq, int64_t ldq,

@@ -114,12 +114,17 @@ def f64_to_f16_rne(x: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------- quantisation
 
 def e4m3_scale(x_f32: np.ndarray) -> np.float32:
-    """Per-tensor scale s = absmax / 448 in binary32 (1 when the tensor is all zero)."""
+    """Per-tensor scale s = absmax / 448 in binary32 over the finite entries
+    (1 when none of them is nonzero)."""
     x = np.asarray(x_f32, dtype=np.float32)
-    amax = np.float32(np.max(np.abs(x))) if x.size else np.float32(0)
+    fin = np.abs(x[np.isfinite(x)])
+    amax = np.float32(np.max(fin)) if fin.size else np.float32(0)
     if amax == 0:
         return np.float32(1.0)
     return np.float32(amax) / np.float32(E4M3_MAX)
+
+
+E4M3_NAN = 0x7F     # E4M3FN has no infinity; S.1111.111 is its NaN
 
 
 def quantize_e4m3(x_f32: np.ndarray, scale: np.float32 | None = None):
@@ -127,12 +132,20 @@ def quantize_e4m3(x_f32: np.ndarray, scale: np.float32 | None = None):
 
     The quotient x / s is rounded to binary32 (numpy's float32 division is the
     correctly rounded IEEE operation), clamped to [-448, 448], then rounded to
-    E4M3 with ties to even."""
+    E4M3 with ties to even.  A NaN or infinite entry (which the format cannot
+    hold; the paper's inputs are finite) becomes the NaN code with the
+    entry's sign, and the scale is taken over the finite entries only, so
+    such an entry shows up as NaN in the product instead of as a finite
+    value."""
     x = np.asarray(x_f32, dtype=np.float32)
     s = e4m3_scale(x) if scale is None else np.float32(scale)
-    y = (x / s).astype(np.float32)
+    fin = np.isfinite(x)
+    with np.errstate(invalid="ignore", over="ignore"):
+        y = (np.where(fin, x, np.float32(0)) / s).astype(np.float32)
     y = np.clip(y, np.float32(-E4M3_MAX), np.float32(E4M3_MAX))
-    return f64_to_e4m3_bits(y.astype(np.float64)), s
+    q = f64_to_e4m3_bits(y.astype(np.float64))
+    nan_code = (E4M3_NAN | (np.signbit(x).astype(np.uint8) << 7)).astype(np.uint8)
+    return np.where(fin, q, nan_code).astype(np.uint8), s
 
 
 def decode(bits: np.ndarray, dtype: str) -> np.ndarray:

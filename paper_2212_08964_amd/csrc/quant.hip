@@ -40,6 +40,13 @@ __device__ __forceinline__ float elem(const void* x, int64_t i) {
     else return float(reinterpret_cast<const _Float16*>(x)[i]);
 }
 
+// |v| for finite v, 0 for NaN and infinities: the scale is taken over the
+// finite entries (a non-finite entry is encoded as NaN, see to_e4m3x2).
+__device__ __forceinline__ float fin_abs(float v) {
+    const float a = fabsf(v);
+    return a <= 3.40282347e38f ? a : 0.0f;
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
@@ -77,13 +84,13 @@ __global__ void __launch_bounds__(kQThreads) absmax_partial(const void* x, int64
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if constexpr (DT == DT_F32) {
-                    m = fmaxf(m, fabsf(__builtin_bit_cast(float, w[e])));
+                    m = fmaxf(m, fin_abs(__builtin_bit_cast(float, w[e])));
                 } else if constexpr (DT == DT_BF16) {
-                    m = fmaxf(m, fabsf(__builtin_bit_cast(float, w[e] << 16)));
-                    m = fmaxf(m, fabsf(__builtin_bit_cast(float, w[e] & 0xffff0000u)));
+                    m = fmaxf(m, fin_abs(__builtin_bit_cast(float, w[e] << 16)));
+                    m = fmaxf(m, fin_abs(__builtin_bit_cast(float, w[e] & 0xffff0000u)));
                 } else {
-                    m = fmaxf(m, fabsf(float(__builtin_bit_cast(_Float16, uint16_t(w[e])))));
-                    m = fmaxf(m, fabsf(float(__builtin_bit_cast(_Float16, uint16_t(w[e] >> 16)))));
+                    m = fmaxf(m, fin_abs(float(__builtin_bit_cast(_Float16, uint16_t(w[e])))));
+                    m = fmaxf(m, fin_abs(float(__builtin_bit_cast(_Float16, uint16_t(w[e] >> 16)))));
                 }
             }
         }
@@ -91,7 +98,7 @@ __global__ void __launch_bounds__(kQThreads) absmax_partial(const void* x, int64
         const int64_t n = outer * inner;
         for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
             const int64_t o = i / inner, c = i % inner;
-            m = fmaxf(m, fabsf(elem<DT>(x, o * ld + c)));
+            m = fmaxf(m, fin_abs(elem<DT>(x, o * ld + c)));
         }
     }
     m = block_max(m, red);
@@ -130,11 +137,19 @@ __device__ __forceinline__ float scale_of(const float* partial, int n, float* sc
 
 // X / s rounded to FP32, clamped to the E4M3 range, rounded to E4M3 (nearest
 // even) by the hardware conversion; two codes per call.
+// A NaN or infinite input (E4M3FN has no infinity) becomes the NaN code
+// 0x7f with the input's sign, so it reaches the product as NaN rather than
+// as a clamped finite value.
 template <bool HI>
 __device__ __forceinline__ uint32_t to_e4m3x2(float a, float b, float s, uint32_t old) {
-    a = fminf(fmaxf(a / s, -kE4M3Max), kE4M3Max);
-    b = fminf(fmaxf(b / s, -kE4M3Max), kE4M3Max);
-    return uint32_t(__builtin_amdgcn_cvt_pk_fp8_f32(a, b, int(old), HI));
+    const float qa = fminf(fmaxf(a / s, -kE4M3Max), kE4M3Max);
+    const float qb = fminf(fmaxf(b / s, -kE4M3Max), kE4M3Max);
+    uint32_t r = uint32_t(__builtin_amdgcn_cvt_pk_fp8_f32(qa, qb, int(old), HI));
+    constexpr int SA = HI ? 16 : 0, SB = SA + 8;
+    const uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
+    if ((ua & 0x7f800000u) == 0x7f800000u) r = (r & ~(0xffu << SA)) | ((0x7fu | ((ua >> 24) & 0x80u)) << SA);
+    if ((ub & 0x7f800000u) == 0x7f800000u) r = (r & ~(0xffu << SB)) | ((0x7fu | ((ub >> 24) & 0x80u)) << SB);
+    return r;
 }
 
 // One 64 x 64 tile of the logical rows x cols matrix per workgroup.  x_col /

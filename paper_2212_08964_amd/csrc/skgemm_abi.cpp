@@ -58,6 +58,7 @@ struct skgemm_plan_s {
     std::vector<int64_t> gM, gN, gK;        // shapes as given, in iteration-space order
     std::vector<int32_t> order;             // caller's index of each problem in iteration-space order
     int t_work;                             // tiles with MAC-loop iterations (they come first)
+    int64_t batch;                          // strided batch of equal problems (1 = one GEMM)
     int64_t sk_iters;
 };
 
@@ -551,8 +552,15 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
         if (!pl->G) {
             pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(pl->K);
             pl->tm = pl->ptm[0]; pl->tn = pl->ptn[0]; pl->ipt = pl->pipt[0];
-            if (int64_t(pl->tm) * pl->tn > kMaxDim || int64_t(pl->tm) * pl->tn * pl->ipt > kMaxDim)
+            const int64_t tiles = int64_t(pl->tm) * pl->tn * pl->batch;
+            if (tiles > kMaxDim || tiles * pl->ipt > kMaxDim) {
                 st = SKGEMM_ERR_UNSUPPORTED;
+            } else if (pl->batch > 1) {
+                // a strided batch is one iteration space of batch * t1 tiles
+                // (problem after problem), each with the same iterations
+                pl->tile_base[1] = int32_t(tiles);
+                pl->iter_base[1] = tiles * pl->ipt;
+            }
         }
         if (st == SKGEMM_OK) st = finish_plan(pl, o);
         if (st != SKGEMM_OK) {
@@ -625,6 +633,7 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     if (st != SKGEMM_OK) return st;
     base.M = M; base.N = N; base.K = K;
     base.G = 0;
+    base.batch = 1;
     base.order.assign(1, 0);
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
@@ -652,6 +661,7 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
     skgemm_status_t st = init_common(&base, la, lb, lc, ta, tb, tc, o);
     if (st != SKGEMM_OK) return st;
     base.G = G;
+    base.batch = 1;
     // iteration-space order: problems with MAC-loop iterations in the given
     // order, then the K = 0 problems that have tiles (epilogue only)
     base.order.clear();
@@ -708,7 +718,8 @@ static skgemm_status_t check_problem(const skgemm_plan_s* pl, int64_t M, int64_t
     return SKGEMM_OK;
 }
 
-static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspace, int32_t* trace) {
+static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspace, int32_t* trace,
+                               uint64_t* times) {
     a->t = pl->t;
     a->sk_tiles = pl->sk_tiles; a->g_sk = pl->g_sk;
     a->sk_iters = int32_t(pl->sk_iters);
@@ -726,19 +737,23 @@ static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspac
         a->partials = reinterpret_cast<float*>(ws + pl->partials_off);
     }
     a->trace = trace;
+    a->times = trace ? times : nullptr;
     a->trace_per_wg = trace ? pl->max_segs : 0;
     a->spin_limit = pl->spin_limit;
     a->sk_prop = pl->share_prop ? 1 : 0;
     a->raster = pl->raster;
     a->xcds = pl->xcds;
     a->coop_s = pl->coop_s;
+    a->batch = int32_t(pl->batch);
+    a->t1 = pl->tm * pl->tn;
 }
 
 static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                                 int64_t ldc, float alpha, float beta, const float* scale_a, const float* scale_b,
-                                void* workspace, size_t ws_bytes, int32_t* trace, size_t trace_records,
-                                hipStream_t stream) {
+                                void* workspace, size_t ws_bytes, int32_t* trace, uint64_t* times,
+                                size_t trace_records, hipStream_t stream, const int64_t* strides = nullptr) {
     if (!pl || pl->G) return SKGEMM_ERR_INVALID_ARG;
+    if ((pl->batch > 1) != (strides != nullptr)) return SKGEMM_ERR_INVALID_ARG;
     GroupEntry e;
     std::memset(&e, 0, sizeof(e));
     skgemm_status_t st = check_problem(pl, pl->M, pl->N, pl->K, A, lda, B, ldb, C, ldc, &e);
@@ -759,7 +774,13 @@ static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, co
     a.tm = pl->tm; a.tn = pl->tn; a.ipt = pl->ipt;
     a.alpha = alpha;
     a.beta = beta;
-    fill_schedule_args(pl, &a, workspace, trace);
+    fill_schedule_args(pl, &a, workspace, trace, times);
+    if (strides) {
+        const int64_t eb = elem_bytes(pl->ta), ec = elem_bytes(pl->tc);
+        a.stride_a = (pl->swapped ? strides[1] : strides[0]) * eb;
+        a.stride_b = (pl->swapped ? strides[0] : strides[1]) * eb;
+        a.stride_c = strides[2] * ec;
+    }
     if (pl->grid == 0) return SKGEMM_OK;
     const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, pl->variant, a, pl->grid, stream);
     return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
@@ -768,8 +789,8 @@ static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, co
 skgemm_status_t skgemm_run(skgemm_plan_t plan, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                            int64_t ldc, float alpha, float beta, const float* scale_a, const float* scale_b,
                            void* workspace, size_t ws_bytes, hipStream_t stream) {
-    return run_impl(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes, nullptr, 0,
-                    stream);
+    return run_impl(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes, nullptr,
+                    nullptr, 0, stream);
 }
 
 skgemm_status_t skgemm_run_traced(skgemm_plan_t plan, const void* A, int64_t lda, const void* B, int64_t ldb,
@@ -778,7 +799,87 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan, const void* A, int64_t lda
                                   size_t trace_records, hipStream_t stream) {
     if (!trace) return SKGEMM_ERR_INVALID_ARG;
     return run_impl(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes, trace,
-                    trace_records, stream);
+                    nullptr, trace_records, stream);
+}
+
+skgemm_status_t skgemm_run_timed(skgemm_plan_t plan, const void* A, int64_t lda, const void* B, int64_t ldb,
+                                 void* C, int64_t ldc, float alpha, float beta, const float* scale_a,
+                                 const float* scale_b, void* workspace, size_t ws_bytes, int32_t* trace,
+                                 uint64_t* times, size_t trace_records, hipStream_t stream) {
+    if (!trace || !times) return SKGEMM_ERR_INVALID_ARG;
+    return run_impl(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes, trace,
+                    times, trace_records, stream);
+}
+
+skgemm_status_t skgemm_realtime_hz(int64_t* hz) {
+    if (!hz) return SKGEMM_ERR_INVALID_ARG;
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        return SKGEMM_ERR_HIP;
+    *hz = int64_t(khz) * 1000;
+    return SKGEMM_OK;
+}
+
+skgemm_status_t skgemm_batched_plan(skgemm_plan_t* out, int64_t batch, int64_t M, int64_t N, int64_t K,
+                                    skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc, skgemm_dtype_t ta,
+                                    skgemm_dtype_t tb, skgemm_dtype_t tc, const skgemm_options_t* opt) {
+    if (!out) return SKGEMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (batch < 1 || batch > kMaxDim || M < 0 || N < 0 || K < 0 || M > kMaxDim || N > kMaxDim || K > kMaxDim)
+        return SKGEMM_ERR_INVALID_ARG;
+    skgemm_options_t o;
+    skgemm_default_options(&o);
+    if (opt) o = *opt;
+    if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
+    skgemm_plan_s base{};
+    skgemm_status_t st = init_common(&base, la, lb, lc, ta, tb, tc, o);
+    if (st != SKGEMM_OK) return st;
+    base.M = M; base.N = N; base.K = K;
+    base.G = 0;
+    base.batch = batch;
+    base.order.assign(1, 0);
+    skgemm_plan_s* pl = nullptr;
+    st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
+    if (st != SKGEMM_OK) return st;
+    *out = pl;
+    return SKGEMM_OK;
+}
+
+static skgemm_status_t batched_impl(skgemm_plan_t plan, const void* A, int64_t lda, int64_t stride_a, const void* B,
+                                    int64_t ldb, int64_t stride_b, void* C, int64_t ldc, int64_t stride_c,
+                                    float alpha, float beta, const float* scale_a, const float* scale_b,
+                                    void* workspace, size_t ws_bytes, int32_t* trace, size_t trace_records,
+                                    hipStream_t stream) {
+    if (!plan || plan->G || plan->batch < 1) return SKGEMM_ERR_INVALID_ARG;
+    if (stride_a < 0 || stride_b < 0 || stride_c < 0) return SKGEMM_ERR_INVALID_ARG;
+    // consecutive C matrices must not overlap (each problem writes its whole C)
+    const int64_t c_extent = plan->lc == SKGEMM_ROW_MAJOR ? (plan->M - 1) * ldc + plan->N : (plan->N - 1) * ldc + plan->M;
+    if (plan->batch > 1 && plan->M > 0 && plan->N > 0 && stride_c < c_extent) return SKGEMM_ERR_INVALID_ARG;
+    if (plan->batch == 1)
+        return run_impl(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes, trace,
+                        nullptr, trace_records, stream);
+    const int64_t strides[3] = {stride_a, stride_b, stride_c};
+    return run_impl(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes, trace,
+                    nullptr, trace_records, stream, strides);
+}
+
+skgemm_status_t skgemm_batched_run(skgemm_plan_t plan, const void* A, int64_t lda, int64_t stride_a, const void* B,
+                                   int64_t ldb, int64_t stride_b, void* C, int64_t ldc, int64_t stride_c, float alpha,
+                                   float beta, const float* scale_a, const float* scale_b, void* workspace,
+                                   size_t ws_bytes, hipStream_t stream) {
+    return batched_impl(plan, A, lda, stride_a, B, ldb, stride_b, C, ldc, stride_c, alpha, beta, scale_a, scale_b,
+                        workspace, ws_bytes, nullptr, 0, stream);
+}
+
+skgemm_status_t skgemm_batched_run_traced(skgemm_plan_t plan, const void* A, int64_t lda, int64_t stride_a,
+                                          const void* B, int64_t ldb, int64_t stride_b, void* C, int64_t ldc,
+                                          int64_t stride_c, float alpha, float beta, const float* scale_a,
+                                          const float* scale_b, void* workspace, size_t ws_bytes, int32_t* trace,
+                                          size_t trace_records, hipStream_t stream) {
+    if (!trace) return SKGEMM_ERR_INVALID_ARG;
+    return batched_impl(plan, A, lda, stride_a, B, ldb, stride_b, C, ldc, stride_c, alpha, beta, scale_a, scale_b,
+                        workspace, ws_bytes, trace, trace_records, stream);
 }
 
 skgemm_status_t skgemm_grouped_table_size(skgemm_plan_t pl, size_t* bytes) {
@@ -821,7 +922,7 @@ static skgemm_status_t grouped_impl(skgemm_plan_t pl, const void* table_dev, voi
     std::memset(&a, 0, sizeof(a));
     a.group = reinterpret_cast<const GroupEntry*>(table_dev);
     a.G = pl->G;
-    fill_schedule_args(pl, &a, workspace, trace);
+    fill_schedule_args(pl, &a, workspace, trace, nullptr);
     if (pl->grid == 0) return SKGEMM_OK;
     const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, pl->variant, a, pl->grid, stream);
     return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
@@ -841,12 +942,12 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[25] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[26] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
                            pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
                            pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s,
-                           pl->occ, kernel_threads(pl->dtype, pl->variant) / 64};
-    for (int i = 0; i < n && i < 25; ++i) info[i] = v[i];
+                           pl->occ, kernel_threads(pl->dtype, pl->variant) / 64, pl->batch};
+    for (int i = 0; i < n && i < 26; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 

@@ -19,6 +19,9 @@ constexpr int kMaxFlagLines = 4096;        // Stream-K workgroups a plan may hav
 // The automatic policy stays data-parallel from this many full waves on.
 constexpr int kAutoMaxWaves = 4;
 constexpr int kTraceFields = 8;
+// Timestamps per traced segment (device real-time clock): start, MAC loop
+// done, partial stores and flags done, fix-up waits done, segment done.
+constexpr int kTimeFields = 5;
 constexpr int32_t kErrTimeout = 6;
 
 // Compiled tile configurations per input type (BM x BN x BK).
@@ -68,6 +71,7 @@ struct KArgs {
     int32_t* flags;
     int32_t* err;
     int32_t* trace;
+    uint64_t* times;           // kTimeFields per trace record, or null
     int32_t trace_per_wg;
     int32_t spin_limit;
     const GroupEntry* group;   // grouped launch: G problem entries (else null)
@@ -77,6 +81,11 @@ struct KArgs {
     int32_t xcds;              // XCDs the workgroups are spread over (1 = no remapping)
     int32_t coop_s;            // >= 2: every Stream-K tile has coop_s one-segment shares and the
                                // split fix-up reduces it (0 = owner fix-up)
+    // Strided batch of equal problems (batch > 1): tile index x is tile
+    // x mod t1 of problem x / t1, whose operands start stride_* bytes after
+    // the previous problem's.
+    int32_t batch, t1;
+    int64_t stride_a, stride_b, stride_c;
 };
 
 // Tile variants: 0 = the type's default tile, 1 = the small 16-bit / FP8 tile

@@ -3,7 +3,7 @@
 Argument marshalling only: every step of the GEMM runs in the library's HIP
 kernels.  The functions mirror the C entry points by name; ``matmul`` adds
 the torch-tensor convenience layer (layouts from strides, the current HIP
-stream, a cached zero-filled workspace per device).
+stream, a cached zero-filled workspace per device and stream).
 
 Loading fails loudly when the library has not been built: there is no other
 execution path.
@@ -31,11 +31,13 @@ EXPORTED = [
     "skgemm_schedule", "skgemm_check_device_error", "skgemm_plan_destroy", "skgemm_status_string",
     "skgemm_grouped_plan", "skgemm_grouped_table_size", "skgemm_grouped_table", "skgemm_grouped_run",
     "skgemm_grouped_run_traced", "skgemm_quantize_workspace_size", "skgemm_quantize_e4m3",
+    "skgemm_run_timed", "skgemm_realtime_hz",
+    "skgemm_batched_plan", "skgemm_batched_run", "skgemm_batched_run_traced",
 ]
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
                "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
-               "share", "coop_s", "occupancy", "waves"]
+               "share", "coop_s", "occupancy", "waves", "batch"]
 SHARE = {"proportional": 0, "leading": 1}
 SHARE_NAME = {v: k for k, v in SHARE.items()}
 FIXUP = {"auto": 0, "owner": 1}
@@ -86,6 +88,15 @@ def lib():
                 L.skgemm_trace_capacity.argtypes = [vp, P(sz)]
                 L.skgemm_run_traced.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_float, ctypes.c_float,
                                                 vp, vp, vp, sz, vp, sz, vp]
+                L.skgemm_run_timed.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_float, ctypes.c_float,
+                                               vp, vp, vp, sz, vp, vp, sz, vp]
+                L.skgemm_realtime_hz.argtypes = [P(i64)]
+                L.skgemm_batched_plan.argtypes = [P(vp), i64, i64, i64, i64, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(Options)]
+                L.skgemm_batched_run.argtypes = [vp, vp, i64, i64, vp, i64, i64, vp, i64, i64, ctypes.c_float,
+                                                 ctypes.c_float, vp, vp, vp, sz, vp]
+                L.skgemm_batched_run_traced.argtypes = [vp, vp, i64, i64, vp, i64, i64, vp, i64, i64,
+                                                        ctypes.c_float, ctypes.c_float, vp, vp, vp, sz, vp, sz, vp]
                 L.skgemm_plan_info.argtypes = [vp, P(i64), i32]
                 L.skgemm_model_constants.argtypes = [vp, P(ctypes.c_double)]
                 L.skgemm_schedule.argtypes = [vp, vp, sz, P(sz)]
@@ -212,6 +223,67 @@ class Plan:
                                        int(trace_records), stream), "skgemm_run_traced")
 
 
+    def run_timed(self, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes,
+                  trace, times, trace_records, stream=None):
+        _check(lib().skgemm_run_timed(self._h, A, int(lda), B, int(ldb), C, int(ldc), float(alpha),
+                                      float(beta), scale_a, scale_b, workspace, int(ws_bytes), trace, times,
+                                      int(trace_records), stream), "skgemm_run_timed")
+
+
+def realtime_hz() -> int:
+    """Ticks per second of the device clock the timed runs read."""
+    v = ctypes.c_int64()
+    _check(lib().skgemm_realtime_hz(ctypes.byref(v)), "skgemm_realtime_hz")
+    return v.value
+
+
+class BatchedPlan(Plan):
+    """Owns one strided batched skgemm_plan_t (batch equal problems, one launch)."""
+
+    def __init__(self, batch, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto", spin_limit=0):
+        self._h = ctypes.c_void_p()
+        o = _options(policy, force_g, hybrid_min_waves, num_cus, occupancy, tile, raster_rows, xcds, share, fixup,
+                     spin_limit)
+        tc = ta if tc is None else tc
+        _check(lib().skgemm_batched_plan(ctypes.byref(self._h), int(batch), int(M), int(N), int(K), la, lb, lc, ta,
+                                         ta, tc, ctypes.byref(o)), "skgemm_batched_plan")
+        self.batch, self.M, self.N, self.K = int(batch), int(M), int(N), int(K)
+        self.la, self.lb, self.lc, self.ta, self.tc = la, lb, lc, ta, tc
+
+    def batched_run(self, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha=1.0, beta=0.0, scale_a=None, scale_b=None,
+                    workspace=None, ws_bytes=0, stream=None, trace=None, trace_records=0):
+        if trace is None:
+            _check(lib().skgemm_batched_run(self._h, A, int(lda), int(sa), B, int(ldb), int(sb), C, int(ldc),
+                                            int(sc), float(alpha), float(beta), scale_a, scale_b, workspace,
+                                            int(ws_bytes), stream), "skgemm_batched_run")
+        else:
+            _check(lib().skgemm_batched_run_traced(self._h, A, int(lda), int(sa), B, int(ldb), int(sb), C,
+                                                   int(ldc), int(sc), float(alpha), float(beta), scale_a, scale_b,
+                                                   workspace, int(ws_bytes), trace, int(trace_records), stream),
+                   "skgemm_batched_run_traced")
+
+
+def _options(policy, force_g, hybrid_min_waves, num_cus, occupancy, tile, raster_rows, xcds, share, fixup,
+             spin_limit):
+    o = default_options()
+    if tile:
+        o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile[:3])
+        if len(tile) > 3:
+            o.tile_waves = int(tile[3])
+    o.raster_rows, o.xcds = int(raster_rows), int(xcds)
+    o.share = SHARE[share] if isinstance(share, str) else int(share)
+    o.fixup = FIXUP[fixup] if isinstance(fixup, str) else int(fixup)
+    o.policy = POLICY[policy] if isinstance(policy, str) else int(policy)
+    o.force_g = int(force_g)
+    o.hybrid_min_waves = int(hybrid_min_waves)
+    o.num_cus = int(num_cus)
+    o.spin_limit = int(spin_limit)
+    o.occupancy = int(occupancy)
+    return o
+
+
 class GroupedPlan(Plan):
     """Owns one grouped skgemm_plan_t (several problems, one launch)."""
 
@@ -322,28 +394,70 @@ def _pick(tensors, prefer):
     return lay, [dict(_layouts(t))[lay] for t in tensors]
 
 
-_ws_cache = {}
+_ws_cache = {}      # (device index, stream handle) -> zero-filled workspace tensor
+_ws_retired = []    # replaced workspaces, kept alive: a captured graph may still use them
 _plan_cache = {}
+_check_runs = False
 
 
-def workspace(nbytes: int, device):
-    """A zero-filled, 256-byte aligned device workspace of at least nbytes,
-    cached per device (runs on one device must not overlap in time)."""
+def workspace(nbytes: int, device, stream=None):
+    """A zero-filled, 256-byte aligned device workspace of at least nbytes for
+    runs on `stream` (a hipStream_t handle; None = the device's current
+    stream).  One per (device, stream): runs on one stream are ordered, so
+    they may share it, while runs on different streams each get their own.
+    A workspace that is outgrown is replaced and the old one is kept alive
+    until the process ends (a HIP graph captured earlier may still hold its
+    address)."""
     import torch
-    key = device.index if isinstance(device, torch.device) else torch.device(device).index
+    dev = device if isinstance(device, torch.device) else torch.device(device)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev.index, int(stream or 0))
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        if buf is not None:
+            _ws_retired.append(buf)
+        with torch.cuda.stream(torch.cuda.ExternalStream(stream, device=dev)) if stream else \
+                torch.cuda.device(dev):
+            buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
         _ws_cache[key] = buf
     return buf
 
 
-def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2, tile=None, fixup="auto"):
-    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves, tuple(tile) if tile else None, fixup)
+def set_error_checks(on: bool) -> None:
+    """When on, matmul and grouped_matmul synchronise their stream after each
+    launch and read the workspace's error word (check_workspace)."""
+    global _check_runs
+    _check_runs = bool(on)
+
+
+def check_workspace(ws, stream=None) -> None:
+    """Raise SkgemmError(ERR_TIMEOUT) if a fix-up wait of a run on workspace
+    tensor `ws` expired (synchronises `stream`).  The workspace is zero-filled
+    again first, so the next run on it starts from clear flags."""
+    st = lib().skgemm_check_device_error(ws.data_ptr(), stream)
+    if st == ERR_TIMEOUT:
+        ws.zero_()
+        import torch
+        torch.cuda.synchronize(ws.device)
+    _check(st, "skgemm_check_device_error")
+
+
+def check_device_errors() -> None:
+    """Check every cached workspace (see check_workspace); raises on the first
+    one whose error word is set, after clearing it."""
+    for (_, stream), ws in list(_ws_cache.items()):
+        check_workspace(ws, stream or None)
+
+
+def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_waves=2, tile=None, fixup="auto",
+             spin_limit=0):
+    key = (M, N, K, la, lb, lc, ta, tc, policy, force_g, hybrid_min_waves, tuple(tile) if tile else None, fixup,
+           spin_limit)
     p = _plan_cache.get(key)
     if p is None:
         p = Plan(M, N, K, la, lb, lc, ta, tc, policy=policy, force_g=force_g, hybrid_min_waves=hybrid_min_waves,
-                 tile=tile, fixup=fixup)
+                 tile=tile, fixup=fixup, spin_limit=spin_limit)
         if len(_plan_cache) > 4096:
             _plan_cache.clear()
         _plan_cache[key] = p
@@ -351,13 +465,18 @@ def get_plan(M, N, K, la, lb, lc, ta, tc, policy="auto", force_g=0, hybrid_min_w
 
 
 def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None, scale_b=None,
-           policy="auto", force_g=0, hybrid_min_waves=2, trace=None, tile=None, fixup="auto"):
+           policy="auto", force_g=0, hybrid_min_waves=2, trace=None, tile=None, fixup="auto", spin_limit=0,
+           check=None, times=None):
     """C = alpha * s_A * s_B * A @ B + beta * C on torch tensors (2-D, on one GPU).
 
     Layouts come from the strides (a non-contiguous operand is copied).  When
     ``out`` is given it receives the result and supplies C for beta != 0.
     ``trace``, when given, is an int32 device tensor of at least
-    8 * plan.trace_capacity() elements that receives the schedule records."""
+    8 * plan.trace_capacity() elements that receives the schedule records;
+    ``times`` (int64, 5 per record) adds each segment's timestamps.
+    ``check`` (default: set_error_checks) synchronises after the launch and
+    raises SkgemmError(ERR_TIMEOUT), with the workspace cleared, if a fix-up
+    wait expired."""
     import torch
     dts = _torch_dtypes()
     if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
@@ -387,10 +506,10 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     if lc is None or out.shape != (M, N):
         raise ValueError("out must be an M x N tensor with one contiguous dimension")
     plan = get_plan(M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy, force_g, hybrid_min_waves,
-                    tile, fixup)
+                    tile, fixup, spin_limit)
     nws = plan.workspace_size()
-    ws = workspace(nws, A.device) if nws else None
     stream = torch.cuda.current_stream(A.device).cuda_stream
+    ws = workspace(nws, A.device, stream) if nws else None
     args = (A.data_ptr() if A.numel() else None, la[1], B.data_ptr() if B.numel() else None, lb[1],
             out.data_ptr() if out.numel() else None, lc[1], alpha, beta,
             scale_a.data_ptr() if scale_a is not None else None,
@@ -398,8 +517,13 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
             ws.data_ptr() if ws is not None else None, nws)
     if trace is None:
         plan.run(*args, stream=stream)
-    else:
+    elif times is None:
         plan.run_traced(*args, trace.data_ptr(), trace.numel() // 8, stream=stream)
+    else:
+        n = min(trace.numel() // 8, times.numel() // 5)
+        plan.run_timed(*args, trace.data_ptr(), times.data_ptr(), n, stream=stream)
+    if ws is not None and (_check_runs if check is None else check):
+        check_workspace(ws, stream)
     return out
 
 
@@ -414,7 +538,7 @@ _gplan_cache = {}
 
 
 def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, policy="auto", force_g=0,
-                   hybrid_min_waves=2, trace=None, table=None, tile=None):
+                   hybrid_min_waves=2, trace=None, table=None, tile=None, spin_limit=0, check=None):
     """C_i = alpha * A_i @ B_i + beta * C_i for every i, in ONE persistent launch.
 
     All A_i share a layout, all B_i share a layout, all C_i share a layout
@@ -441,11 +565,11 @@ def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, poli
     Ns = [B.shape[1] for B in Bs]
     Ks = [A.shape[1] for A in As]
     key = (tuple(Ms), tuple(Ns), tuple(Ks), la, lb, lc, dts[As[0].dtype], dts[Cs[0].dtype], policy, force_g,
-           hybrid_min_waves, tuple(tile) if tile else None)
+           hybrid_min_waves, tuple(tile) if tile else None, spin_limit)
     plan = _gplan_cache.get(key)
     if plan is None:
         plan = GroupedPlan(Ms, Ns, Ks, la, lb, lc, dts[As[0].dtype], dts[Cs[0].dtype], policy=policy,
-                           force_g=force_g, hybrid_min_waves=hybrid_min_waves, tile=tile)
+                           force_g=force_g, hybrid_min_waves=hybrid_min_waves, tile=tile, spin_limit=spin_limit)
         if len(_gplan_cache) > 256:
             _gplan_cache.clear()
         _gplan_cache[key] = plan
@@ -458,14 +582,85 @@ def grouped_matmul(As, Bs, Cs=None, *, out_dtype=None, alpha=1.0, beta=0.0, poli
         host = plan.table(args)
         table = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(dev)
     nws = plan.workspace_size()
-    ws = workspace(nws, dev) if nws else None
     stream = torch.cuda.current_stream(dev).cuda_stream
+    ws = workspace(nws, dev, stream) if nws else None
     if trace is None:
         plan.grouped_run(table.data_ptr(), ws.data_ptr() if ws is not None else None, nws, stream)
     else:
         plan.grouped_run_traced(table.data_ptr(), ws.data_ptr() if ws is not None else None, nws,
                                 trace.data_ptr(), trace.numel() // 8, stream)
+    if ws is not None and (_check_runs if check is None else check):
+        check_workspace(ws, stream)
     return Cs, table
+
+
+_bplan_cache = {}
+
+
+def _layout3(t, prefer):
+    """(layout, ld, batch stride) of a 3-D tensor whose matrices have one
+    contiguous dimension, or None."""
+    lay = _layout(t[0] if t.shape[0] else t.new_empty(t.shape[1:]), prefer)
+    if t.shape[0] == 0 or lay is None:
+        return None
+    if t.shape[1] * t.shape[2] and t.shape[0] > 1:
+        # every matrix has the same strides as the first
+        s0, s1, s2 = t.stride()
+        m = t[0]
+        if m.stride() != (s1, s2):
+            return None
+    return lay[0], lay[1], t.stride(0)
+
+
+def batched_matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, policy="auto", force_g=0,
+                   hybrid_min_waves=2, tile=None, trace=None):
+    """C[i] = alpha * A[i] @ B[i] + beta * C[i] for 3-D tensors (batch, M, K) and
+    (batch, K, N) in one persistent launch (strided batched Stream-K GEMM)."""
+    import torch
+    dts = _torch_dtypes()
+    if A.dim() != 3 or B.dim() != 3 or A.shape[0] != B.shape[0] or A.shape[2] != B.shape[1]:
+        raise ValueError("batched_matmul needs A (batch x M x K) and B (batch x K x N)")
+    if A.dtype != B.dtype or A.dtype not in dts:
+        raise ValueError(f"unsupported input dtypes {A.dtype}, {B.dtype}")
+    batch, M, K = A.shape
+    N = B.shape[2]
+    la = _layout3(A, ROW_MAJOR)
+    if la is None:
+        A = A.contiguous()
+        la = _layout3(A, ROW_MAJOR)
+    lb = _layout3(B, COL_MAJOR)
+    if lb is None:
+        B = B.contiguous()
+        lb = _layout3(B, COL_MAJOR)
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        if out_dtype is None:
+            out_dtype = torch.float32 if A.dtype in (torch.float32, torch.float8_e4m3fn) else A.dtype
+        out = torch.empty((batch, M, N), dtype=out_dtype, device=A.device)
+    lc = _layout3(out, ROW_MAJOR)
+    if lc is None or tuple(out.shape) != (batch, M, N):
+        raise ValueError("out must be batch x M x N with one contiguous dimension per matrix")
+    key = (batch, M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy, force_g, hybrid_min_waves,
+           tuple(tile) if tile else None)
+    plan = _bplan_cache.get(key)
+    if plan is None:
+        plan = BatchedPlan(batch, M, N, K, la[0], lb[0], lc[0], dts[A.dtype], dts[out.dtype], policy=policy,
+                           force_g=force_g, hybrid_min_waves=hybrid_min_waves, tile=tile)
+        if len(_bplan_cache) > 256:
+            _bplan_cache.clear()
+        _bplan_cache[key] = plan
+    nws = plan.workspace_size()
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    ws = workspace(nws, A.device, stream) if nws else None
+    plan.batched_run(A.data_ptr() if A.numel() else None, la[1], la[2], B.data_ptr() if B.numel() else None, lb[1],
+                     lb[2], out.data_ptr() if out.numel() else None, lc[1], lc[2], alpha, beta,
+                     workspace=ws.data_ptr() if ws is not None else None, ws_bytes=nws, stream=stream,
+                     trace=trace.data_ptr() if trace is not None else None,
+                     trace_records=trace.numel() // 8 if trace is not None else 0)
+    if ws is not None and _check_runs:
+        check_workspace(ws, stream)
+    return out
 
 
 _qws = {}

@@ -329,3 +329,50 @@ def test_f64_plans():
         assert e.value.status == sk.ERR_UNSUPPORTED
     ref = oracle_plan_for(info, p.model_constants(), "sk", force_g=100)
     assert records_to_schedule(p.schedule(), info["grid"]) == S.enumerate_schedule(ref)
+
+
+@pytest.mark.parametrize("policy", ["auto", "paper", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp"])
+def test_batched_planner_matches_enumerator(policy):
+    """A strided batch of equal problems is one iteration space, problem after
+    problem: the planner's schedule equals the grouped enumerator's for the
+    list of equal problems (and so, by the equal-ipt pin, one GEMM with the
+    tile count summed)."""
+    sk = _lib()
+    for (batch, M, N, K), (cus, occ) in itertools.product(
+            [(4, 300, 500, 700), (16, 128, 256, 2048), (3, 1000, 130, 5), (7, 64, 64, 64), (2, 513, 257, 0)],
+            [(256, 1), (16, 1), (37, 2)]):
+        try:
+            p = sk.BatchedPlan(batch, M, N, K, ta=sk.BF16, policy=policy, num_cus=cus, occupancy=occ)
+        except sk.SkgemmError as e:
+            assert e.status == sk.ERR_CAPACITY
+            continue
+        info = p.info()
+        assert info["batch"] == batch and info["t"] == batch * info["tm"] * info["tn"]
+        ref = oracle_grouped_plan_for([(M, N, K)] * batch, info, p.model_constants(), policy)
+        assert (ref.policy, ref.sk_tiles, ref.g_sk, ref.grid) == (
+            POLICY_BY_ID[info["policy"]], info["sk_tiles"], info["g_sk"], info["grid"])
+        from oracle import grouped as GR
+        got = records_to_schedule(p.schedule(), info["grid"])
+        assert got == GR.enumerate_grouped_schedule(ref), (batch, M, N, K, cus, occ)
+        if info["t"]:
+            GR.check_grouped_invariants(ref, got)
+
+
+def test_batched_argument_errors():
+    sk = _lib()
+    L = sk.lib()
+    h = ctypes.c_void_p()
+    o = sk.default_options()
+    o.num_cus, o.occupancy = 256, 1
+    assert L.skgemm_batched_plan(ctypes.byref(h), 0, 4, 4, 4, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                                 ctypes.byref(o)) == sk.ERR_INVALID_ARG
+    p = sk.BatchedPlan(3, 64, 64, 64, ta=sk.BF16, num_cus=256, occupancy=1, policy="dp")
+    fake = 1 << 40
+    # overlapping C matrices, negative strides: refused before launch
+    assert L.skgemm_batched_run(p.handle, fake, 64, 4096, fake, 64, 4096, fake, 64, 4000, 1.0, 0.0, None, None,
+                                None, 0, None) == sk.ERR_INVALID_ARG
+    assert L.skgemm_batched_run(p.handle, fake, 64, -1, fake, 64, 4096, fake, 64, 4096, 1.0, 0.0, None, None,
+                                None, 0, None) == sk.ERR_INVALID_ARG
+    # a batched plan needs the batched run (strides), and a single plan runs through either
+    assert L.skgemm_run(p.handle, fake, 64, fake, 64, fake, 64, 1.0, 0.0, None, None, None, 0,
+                        None) == sk.ERR_INVALID_ARG

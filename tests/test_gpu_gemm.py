@@ -470,3 +470,147 @@ def test_occupancy_per_dtype_and_tile_is_sane_and_stable():
         info = sk().Plan(512, 512, 512, 0, 1, 0, sk().F8E4M3, sk().F32, policy="dp", tile=tile).info()
         assert 1 <= info["occupancy"] <= 8
     assert [occ(ta, tile) for ta, tile in cases] == first
+
+
+@pytest.mark.parametrize("fixup", ["auto", "owner"])
+def test_matmul_reports_timeout_and_clears_its_workspace(fixup):
+    """Through the torch layer: with a one-poll spin limit a fix-up wait
+    expires, matmul(check=True) raises ERR_TIMEOUT and leaves its cached
+    workspace zero-filled, so the next run (default limit) is exact."""
+    M, N, K = 1000, 700, 900
+    g = W.rng(37)
+    a = W.integer_f32(g, (M, K))
+    b = W.integer_f32(g, (K, N))
+    A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+    ref = og.gemm_f64(a.astype(np.float64), b.astype(np.float64))
+    tile = (256, 256, 64)
+    t = sk().Plan(M, N, K, ta=sk().BF16, tc=sk().F32, policy="dp", tile=tile).info()["t"]
+    kw = dict(policy="sk", force_g=3 * t, tile=tile, fixup=fixup, out_dtype=torch.float32)
+    seen = 0
+    for _ in range(3):
+        try:
+            sk().matmul(A, B, spin_limit=1, check=True, **kw)
+        except sk().SkgemmError as e:
+            assert e.status == sk().ERR_TIMEOUT
+            seen += 1
+    assert seen > 0
+    stream = torch.cuda.current_stream().cuda_stream
+    ws = sk()._ws_cache[(dev().index, stream)]
+    assert int(ws.count_nonzero().item()) == 0 or seen < 3
+    C = sk().matmul(A, B, check=True, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_f64(C), ref)
+
+
+def test_workspaces_are_per_stream():
+    """Runs on two streams use two workspaces (their flags and partials must
+    not meet); each stream's results match the oracle."""
+    M, N, K = 700, 900, 2048
+    a, b = W.normal_pair(M, N, K, seed=41)
+    A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+    ref = oracle(A, B)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for s in (s1, s2):
+        s.wait_stream(torch.cuda.current_stream())
+    for it in range(10):
+        for s in (s1, s2):
+            with torch.cuda.stream(s):
+                outs.append(sk().matmul(A, B, policy="sk", out_dtype=torch.float32, tile=(128, 128, 64, 4)))
+    torch.cuda.synchronize()
+    k1 = (dev().index, s1.cuda_stream)
+    k2 = (dev().index, s2.cuda_stream)
+    assert sk()._ws_cache[k1].data_ptr() != sk()._ws_cache[k2].data_ptr()
+    for C in outs:
+        assert rel(C, ref) <= TOL_16_OUT32
+
+
+def test_graph_keeps_its_workspace_when_an_eager_run_outgrows_it():
+    """A grouped launch captured in a HIP graph holds its stream's workspace;
+    an eager run on that stream that needs a larger one replaces it in the
+    cache, and the graph's replays (which still use the old one) stay equal
+    to the eager result."""
+    Ms, N, K = [300, 200, 100], 512, 1024
+    As = [torch.randn((m, K), device=dev()).to(torch.bfloat16) for m in Ms]
+    Bs = [torch.randn((K, N), device=dev()).to(torch.bfloat16) for _ in Ms]
+    S_ = torch.cuda.Stream()
+    S_.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(S_):
+        Cs = [torch.empty((m, N), dtype=torch.float32, device=dev()) for m in Ms]
+        _, table = sk().grouped_matmul(As, Bs, Cs, policy="sk", force_g=6)
+        want = [C.clone() for C in Cs]
+    torch.cuda.synchronize()
+    key = (dev().index, S_.cuda_stream)
+    old = sk()._ws_cache[key]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=S_):
+        sk().grouped_matmul(As, Bs, Cs, policy="sk", force_g=6, table=table)
+    # an eager run on the same stream with a much larger Stream-K grid
+    M2, N2, K2 = 2048, 2048, 4096
+    A2 = torch.randn((M2, K2), device=dev()).to(torch.bfloat16)
+    B2 = torch.randn((K2, N2), device=dev()).to(torch.bfloat16)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(S_):
+        C2 = sk().matmul(A2, B2, policy="sk", force_g=128, tile=(256, 256, 64), out_dtype=torch.float32)
+    torch.cuda.synchronize()
+    assert sk()._ws_cache[key].data_ptr() != old.data_ptr()
+    assert any(r is old for r in sk()._ws_retired)
+    for rep in range(4):
+        for C in Cs:
+            C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for C, w in zip(Cs, want):
+            assert torch.equal(C, w), rep
+    rows = np.arange(0, M2, 97)
+    ref = og.gemm_rows_f64(to_f64(A2), to_f64(B2), rows)
+    assert og.rel_frobenius(to_f64(C2[torch.from_numpy(rows).to(dev())]), ref) <= TOL_16_OUT32
+
+
+@pytest.mark.parametrize("shape,policy,g,fixup", [((1024, 1024, 1024), "sk", 0, "auto"),
+                                                   ((384, 384, 1024), "sk", 36, "owner"),
+                                                   ((2000, 1500, 333), "dp_1tile_sk", 0, "owner"),
+                                                   ((2000, 1500, 333), "2tile_sk_dp", 0, "owner")])
+def test_timed_run_stamps_and_schedule(shape, policy, g, fixup):
+    """skgemm_run_timed: the schedule records equal the enumerator's, each
+    segment's five stamps are in order, a workgroup's segments follow one
+    another, only segments that wait for peers show a wait, and C is bitwise
+    the untimed run's."""
+    M, N, K = shape
+    gen = W.rng(3)
+    A = torch.from_numpy(W.integer_f32(gen, (M, K))).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(W.integer_f32(gen, (K, N))).to(torch.bfloat16).to(dev())
+    kw = dict(policy=policy, force_g=g, fixup=fixup, out_dtype=torch.float32)
+    p = sk().get_plan(M, N, K, 0, 0, 0, sk().BF16, sk().F32, policy, g, 2, None, fixup)
+    cap = p.trace_capacity()
+    tr = torch.full((cap * 8,), -7, dtype=torch.int32, device=dev())
+    ts = torch.zeros((cap * 5,), dtype=torch.int64, device=dev())
+    C = mm(A, B, trace=tr, times=ts, **kw)
+    C0 = mm(A, B, **kw)
+    assert torch.equal(C, C0)
+    info = p.info()
+    recs = tr.cpu().numpy().reshape(-1, 8)
+    stamps = ts.cpu().numpy().reshape(-1, 5)
+    used = recs[:, 0] != -7
+    got = records_to_schedule([tuple(int(v) for v in r) for r in recs[used]], info["grid"])
+    assert got == S.enumerate_schedule(oracle_plan_for(info, p.model_constants(), policy, force_g=g))
+    st = stamps[used]
+    assert np.all(st > 0) and np.all(np.diff(st, axis=1) >= 0)
+    hz = sk().realtime_hz()
+    assert 1e6 <= hz <= 1e10
+    per_wg = {}
+    for r, s_ in zip(recs[used], st):
+        per_wg.setdefault(int(r[0]), []).append((int(r[1]), s_))
+    for segs in per_wg.values():
+        segs.sort(key=lambda x: x[0])
+        for (_, a_), (_, b_) in zip(segs, segs[1:]):
+            assert b_[0] >= a_[4]
+    # a full tile with no split waits for nobody
+    for r, s_ in zip(recs[used], st):
+        if r[5] == 0 and info["coop_s"] == 0:
+            assert (s_[3] - s_[2]) / hz < 2e-6
+    span = (st[:, 4].max() - st[:, 0].min()) / hz
+    assert 0 < span < 1.0

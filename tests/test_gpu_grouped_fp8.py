@@ -175,6 +175,29 @@ def test_quantize_edge_cases():
     assert np.array_equal(Q.cpu().view(torch.uint8).numpy(), qref)
 
 
+@pytest.mark.parametrize("shape", [(333, 517), (320, 512), (80, 208)])
+@pytest.mark.parametrize("layout_out", ["row", "col"])
+def test_quantize_non_finite_bit_exact(shape, layout_out):
+    """NaN and infinite entries give the NaN code with their sign; the scale
+    comes from the finite entries (all three kernel forms)."""
+    rows, cols = shape
+    g = W.rng(11 + rows)
+    x32 = W.normal_f32(g, (rows, cols)).astype(np.float32)
+    idx = g.choice(rows * cols, size=8, replace=False)
+    x32.ravel()[idx[:2]] = np.nan
+    x32.ravel()[idx[2:4]] = -np.nan
+    x32.ravel()[idx[4:6]] = np.inf
+    x32.ravel()[idx[6:]] = -np.inf
+    X = torch.from_numpy(x32).to(dev())
+    Q, s = sk().quantize_e4m3(X, layout_out)
+    torch.cuda.synchronize()
+    qref, sref = lowp.quantize_e4m3(x32)
+    assert np.float32(s.item()) == sref and np.isfinite(sref)
+    codes = Q.cpu().contiguous().view(torch.uint8).numpy() if layout_out == "row" else \
+        Q.t().contiguous().t().cpu().contiguous().view(torch.uint8).numpy()
+    assert np.array_equal(codes, qref)
+
+
 @pytest.mark.parametrize("tile", [None, (256, 256, 128), (128, 128, 128)])
 @pytest.mark.parametrize("shape", [(256, 256, 128), (300, 500, 700), (1024, 1024, 1024), (128, 2048, 4096),
                                    (1, 1, 1), (513, 257, 131)])
@@ -236,3 +259,36 @@ def test_fp8_integer_exact_split_fixup(tile):
         C = sk().matmul(qa, qb, out_dtype=torch.float32, policy=pol, force_g=fg, tile=tile)
         torch.cuda.synchronize()
         assert np.array_equal(to_f64(C), ref), (pol, fg)
+
+
+@pytest.mark.parametrize("policy", ["auto", "paper", "sk", "dp", "2tile_sk_dp", "dp_1tile_sk"])
+def test_grouped_zero_k_problems(policy):
+    """Problems with K = 0 get C = beta * C (epilogue-only tiles after the
+    others) in the same launch; the others match the oracle and the trace
+    matches the enumerator."""
+    probs = [(300, 700, 0), (1000, 900, 3000), (64, 64, 0), (0, 50, 0), (500, 256, 640), (900, 900, 0)]
+    g = W.rng(5)
+    As, Bs, Cin = [], [], []
+    for (M, N, K) in probs:
+        As.append(torch.from_numpy(W.normal_f32(g, (M, K))).to(torch.bfloat16).to(dev()))
+        Bs.append(torch.from_numpy(W.normal_f32(g, (K, N))).to(torch.bfloat16).to(dev()))
+        Cin.append(torch.from_numpy(W.normal_f32(g, (M, N))).to(dev()))
+    Cs = [c.clone() for c in Cin]
+    Ms, Ns, Ks = zip(*probs)
+    p = sk().GroupedPlan(Ms, Ns, Ks, ta=sk().BF16, tc=sk().F32, policy=policy)
+    info = p.info()
+    tr = torch.full((max(p.trace_capacity(), 1) * 8,), -7, dtype=torch.int32, device=dev())
+    sk().grouped_matmul(As, Bs, Cs, alpha=1.5, beta=0.5, policy=policy, trace=tr)
+    torch.cuda.synchronize()
+    for (M, N, K), A, B, C, C0 in zip(probs, As, Bs, Cs, Cin):
+        if M * N == 0:
+            continue
+        if K == 0:
+            assert np.array_equal(to_f64(C), np.float32(0.5) * to_f64(C0).astype(np.float32)), (M, N)
+        else:
+            ref = og.gemm_f64(to_f64(A), to_f64(B), 1.5, 0.5, to_f64(C0))
+            assert og.rel_frobenius(to_f64(C), ref) <= 1e-5, (M, N, K)
+    recs = [tuple(int(v) for v in r) for r in tr.cpu().numpy().reshape(-1, 8) if r[0] != -7]
+    got = records_to_schedule(recs, info["grid"])
+    ref = oracle_grouped_plan_for(probs, info, p.model_constants(), policy)
+    assert got == GR.enumerate_grouped_schedule(ref)

@@ -108,3 +108,23 @@ def test_quantize_properties():
     # all-zero tensor: scale 1, codes 0
     qz, sz = lowp.quantize_e4m3(np.zeros((3, 3), np.float32))
     assert sz == 1.0 and np.all(qz == 0)
+
+
+def test_quantize_non_finite_entries():
+    """NaN and infinite entries become the NaN code with their sign (the
+    format has no infinity); the finite entries keep the codes and the scale
+    they would have without them."""
+    g = np.random.default_rng(3)
+    x = g.standard_normal((16, 9)).astype(np.float32)
+    q0, s0 = lowp.quantize_e4m3(x)
+    y = x.copy()
+    y[1, 2], y[3, 4], y[5, 6], y[7, 8] = np.nan, np.inf, -np.inf, -np.nan
+    q, s = lowp.quantize_e4m3(y)
+    assert s == s0
+    bad = ~np.isfinite(y)
+    assert np.array_equal(q[~bad], q0[~bad])
+    assert [int(v) for v in q[bad]] == [0x7F, 0x7F, 0xFF, 0xFF]
+    assert np.all(np.isnan(lowp.e4m3_bits_to_f64(q[bad])))
+    # a tensor with no finite nonzero entry keeps scale 1
+    qn, sn = lowp.quantize_e4m3(np.array([[np.nan, 0.0], [np.inf, -0.0]], np.float32))
+    assert sn == 1.0 and [int(v) for v in qn.ravel()] == [0x7F, 0x00, 0x7F, 0x80]
