@@ -33,7 +33,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
 #include <utility>
 
 #include "skgemm_internal.h"
@@ -73,15 +72,6 @@ template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.b
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
-
-// Cfg::PP (where present and true): the MAC loop runs the two halves of the
-// workgroup's waves out of phase ("ping-pong"): while one group issues the
-// MFMAs of a k-slab from fragments already in registers, the other reads its
-// fragments of the next slab from LDS (and group 0 issues the global loads),
-// so each SIMD's matrix core is fed by one wave while the other wave waits on
-// memory.
-template <class C, class = void> struct PPOf { static constexpr bool value = false; };
-template <class C> struct PPOf<C, std::void_t<decltype(C::PP)>> { static constexpr bool value = C::PP; };
 
 template <int DT, int V>
 constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
@@ -849,127 +839,6 @@ struct Gemm {
                 return;
     }
 
-    // ---------------------------------------------------------------- ping-pong MAC loop
-    // Two wave groups of NW / 2 waves (group 0: waves 0 .. NW/2-1, the top
-    // half of the tile's rows; group 1 the bottom half), one wave of each on
-    // every SIMD.  Between consecutive workgroup barriers one group is in its
-    // memory phase (LDS fragment reads of one k-slab into registers; group 0
-    // also issues the next slab's global loads) while the other is in its
-    // compute phase (the slab's MFMAs from registers).  Group 1 runs one
-    // barrier behind group 0; group 0 adds one barrier at the end, so both
-    // pass the same number.  Slab j lives in stage j mod 2; group 0 loads
-    // slab j + 1 during its memory phase of slab j (both groups have read
-    // slab j - 1 from that stage by then) and waits for it at the end of its
-    // compute phase, before the barrier after which it is read.
-    static constexpr bool PP = PPOf<C_>::value;
-    using SAg = Slab<EB, BM, BK, AKC, PP ? THREADS / 2 : THREADS>;
-    using SBg = Slab<EB, BN, BK, BKC, PP ? THREADS / 2 : THREADS>;
-    // k16 steps per phase: a phase holds the fragments of half a k-slab (all
-    // of them would not fit beside the accumulators)
-    static constexpr int KSP = 2, PHASES = BK / 16 / KSP;
-
-    struct Frags { u32x4 a[KSP][FM], b[KSP][FN]; };
-
-    // Fragments of k16 steps h * KSP .. h * KSP + KSP - 1 of the staged slab.
-    static __device__ __forceinline__ void read_frags(const unsigned char* As, const unsigned char* Bs, Frags& f,
-                                                      int h, int wm, int wn, int lane) {
-        const int g = lane >> 5, l32 = lane & 31;
-#pragma unroll
-        for (int q = 0; q < KSP; ++q) {
-            const int s = h * KSP + q;
-#pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                if constexpr (AKC) f.a[q][i] = lds_row_chunk<SA::ROWB>(As, wm * WTM + i * 32 + l32, 2 * s + g);
-                else f.a[q][i] = lds_tr16<SA::ROWB>(As, 16 * s + 8 * g, wm * WTM + i * 32, lane);
-            }
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                if constexpr (BKC) f.b[q][j] = lds_row_chunk<SB::ROWB>(Bs, wn * WTN + j * 32 + l32, 2 * s + g);
-                else f.b[q][j] = lds_tr16<SB::ROWB>(Bs, 16 * s + 8 * g, wn * WTN + j * 32, lane);
-            }
-        }
-    }
-
-    static __device__ __forceinline__ void mfma_frags(const Frags& f, Acc& acc) {
-        if constexpr (DT == DT_BF16 || DT == DT_F16) {
-#pragma unroll
-            for (int q = 0; q < KSP; ++q)
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) acc.v[i][j] = mfma16<DT>(f.a[q][i], f.b[q][j], acc.v[i][j]);
-        }
-    }
-
-    // Group 0's loads of slab `it` (absolute k-iteration) into stage `lds`.
-    static __device__ __forceinline__ void pp_issue(const Prob& a, const SAg& sa, const SBg& sb, int it, int kbeg,
-                                                    int kedge, int m0, int n0, unsigned char* lds, int tid) {
-        if (it < kedge) {
-            sa.template issue<false>(it - kbeg, it * BK, a.K, m0, a.M, lds, tid);
-            sb.template issue<false>(it - kbeg, it * BK, a.K, n0, a.N, lds + SA::BYTES, tid);
-        } else {
-            sa.template issue<true>(it - kbeg, it * BK, a.K, m0, a.M, lds, tid);
-            sb.template issue<true>(it - kbeg, it * BK, a.K, n0, a.N, lds + SA::BYTES, tid);
-        }
-    }
-
-    static __device__ __forceinline__ void pp_land(const Prob& a, const SAg& sa, const SBg& sb, int it, int kbeg,
-                                                   int kedge, int m0, int n0, unsigned char* lds, int tid) {
-        wait_vmem();
-        if (it >= kedge) {
-            sa.fix_edge(it - kbeg, it * BK, a.K, m0, a.M, lds, tid);
-            sb.fix_edge(it - kbeg, it * BK, a.K, n0, a.N, lds + SA::BYTES, tid);
-        }
-    }
-
-    // One slab j of the ping-pong loop on stage `cur` (the other stage `nxt`).
-    static __device__ __forceinline__ void pp_slab(const Prob& a, const SAg& sa, const SBg& sb, int j, int kbeg,
-                                                   int kend, int kedge, int m0, int n0, unsigned char* cur,
-                                                   unsigned char* nxt, Acc& acc, int tid, bool grp0) {
-        const int lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
-        const int it = kbeg + j;
-        const bool more = it + 1 < kend;
-#pragma unroll
-        for (int h = 0; h < PHASES; ++h) {
-            Frags f;
-            read_frags(cur, cur + SA::BYTES, f, h, wm, wn, lane);              // memory phase
-            if (h == 0 && grp0 && more) pp_issue(a, sa, sb, it + 1, kbeg, kedge, m0, n0, nxt, tid);
-            step_barrier();
-            mfma_frags(f, acc);                                                // compute phase
-            if (h == PHASES - 1 && grp0 && more) pp_land(a, sa, sb, it + 1, kbeg, kedge, m0, n0, nxt, tid);
-            step_barrier();
-        }
-    }
-
-    static __device__ __forceinline__ void loop_pp(const Prob& a, const Stages& st, int m0, int n0, int kbeg,
-                                                   int kend, int kedge, Acc& acc, int tid) {
-        static_assert(NS == 2 && WM == 2, "ping-pong: two stages, two wave groups");
-        tid = opaque(tid);
-        const bool grp0 = uni(tid >> 6) < NW / 2;
-        SAg sa;
-        SBg sb;
-        if (grp0) {
-            sa.init(a.A, a.lda, m0, a.M, kbeg, a.K, tid);
-            sb.init(a.B, a.ldb, n0, a.N, kbeg, a.K, tid);
-        }
-        __syncthreads();   // LDS may still be in use (previous epilogue or loop)
-        if (grp0) {
-            pp_issue(a, sa, sb, kbeg, kbeg, kedge, m0, n0, st.template at<0>(), tid);
-            pp_land(a, sa, sb, kbeg, kbeg, kedge, m0, n0, st.template at<0>(), tid);
-        }
-        step_barrier();
-        if (!grp0) step_barrier();          // group 1 runs one barrier behind
-        const int n = kend - kbeg;
-        for (int j = 0; j < n; j += 2) {
-            pp_slab(a, sa, sb, j, kbeg, kend, kedge, m0, n0, st.template at<0>(), st.template at<1>(), acc, tid,
-                    grp0);
-            if (j + 1 < n)
-                pp_slab(a, sa, sb, j + 1, kbeg, kend, kedge, m0, n0, st.template at<1>(), st.template at<0>(), acc,
-                        tid, grp0);
-        }
-        if (grp0) step_barrier();           // ... and group 0 catches up at the end
-    }
-
     // MAC-loop iterations [klo, khi) of one tile into acc (zeroed first).
     // Only the tile's last k-iteration can need per-chunk checks: there a
     // K-contiguous operand's chunks may straddle k = K (the elements past it
@@ -1000,8 +869,7 @@ struct Gemm {
         // rows shorter than a chunk: chunks of earlier rows can reach the end too
         const bool check_all = (a_edge && a.lda * EB < 16) || (b_edge && a.ldb * EB < 16);
         const int kedge = check_all ? klo : check_last ? klast : khi;
-        if constexpr (PP) loop_pp(a, st, m0, n0, klo, khi, kedge, acc, tid);
-        else loop(a, st, m0, n0, klo, khi, kedge, acc, tid);
+        loop(a, st, m0, n0, klo, khi, kedge, acc, tid);
     }
 
     // Partial tiles are stored in fragment order: 16-byte chunk q of thread

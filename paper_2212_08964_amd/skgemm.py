@@ -478,6 +478,14 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     raises SkgemmError(ERR_TIMEOUT), with the workspace cleared, if a fix-up
     wait expired."""
     import torch
+    fast = (out is None and trace is None and scale_a is None and scale_b is None and beta == 0.0
+            and not (check or (check is None and _check_runs)))
+    if fast:
+        key = (A.shape, A.stride(), B.shape, B.stride(), A.dtype, B.dtype, A.device, out_dtype, policy, force_g,
+               hybrid_min_waves, tuple(tile) if tile else None, fixup, spin_limit)
+        ent = _fast_cache.get(key)
+        if ent is not None:
+            return _fast_run(ent, A, B, alpha)
     dts = _torch_dtypes()
     if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
         raise ValueError("matmul needs A (M x K) and B (K x N)")
@@ -492,10 +500,12 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     if la is None:
         A = A.contiguous()
         la = _layout(A)
+        fast = False          # the layout is the copy's, not the caller's tensor's
     lb = _layout(B, prefer=COL_MAJOR)
     if lb is None:
         B = B.contiguous()
         lb = _layout(B)
+        fast = False
     if out is None:
         if out_dtype is None:
             out_dtype = torch.float32 if A.dtype in (torch.float32, torch.float8_e4m3fn) else A.dtype
@@ -524,6 +534,43 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
         plan.run_timed(*args, trace.data_ptr(), times.data_ptr(), n, stream=stream)
     if ws is not None and (_check_runs if check is None else check):
         check_workspace(ws, stream)
+    if fast and M * N * K > 0 and len(_fast_cache) < 4096:
+        # everything this call derived from the tensors' shapes, strides and
+        # types, for the next call with the same signature
+        _fast_cache[key] = (lib().skgemm_run, plan.handle, la[1], lb[1], lc[1], nws, M, N, out.dtype, A.device,
+                            plan)
+    return out
+
+
+_fast_cache = {}
+
+
+def _raw_stream(device):
+    """hipStream_t of the device's current stream (torch's raw accessor when it
+    has one: it skips building a Stream object)."""
+    import torch
+    get = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if get is not None:
+        return get(device.index)
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _fast_run(ent, A, B, alpha):
+    """matmul for a signature seen before: no layout inference, no plan lookup."""
+    import torch
+    fn, handle, lda, ldb, ldc, nws, M, N, odt, dev, _plan = ent
+    out = torch.empty((M, N), dtype=odt, device=dev)
+    stream = _raw_stream(dev)
+    wsp = None
+    if nws:
+        ws = _ws_cache.get((dev.index, int(stream or 0)))
+        if ws is None or ws.numel() < nws:
+            ws = workspace(nws, dev, stream)
+        wsp = ws.data_ptr()
+    st = fn(handle, A.data_ptr(), lda, B.data_ptr(), ldb, out.data_ptr(), ldc, float(alpha), 0.0, None, None, wsp,
+            nws, stream)
+    if st != OK:
+        raise SkgemmError(st, "skgemm_run")
     return out
 
 

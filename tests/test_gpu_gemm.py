@@ -614,3 +614,35 @@ def test_timed_run_stamps_and_schedule(shape, policy, g, fixup):
             assert (s_[3] - s_[2]) / hz < 2e-6
     span = (st[:, 4].max() - st[:, 0].min()) / hz
     assert 0 < span < 1.0
+
+
+def test_matmul_fast_path_repeated_signatures():
+    """Repeated matmul calls with one tensor signature take the cached path
+    (no layout inference or plan lookup): results equal the first call's; a
+    transposed view, a strided view and a non-contiguous operand (copied by
+    the slow path, so never cached) stay correct on every call."""
+    M, N, K = 300, 700, 900
+    a, b = W.normal_pair(M, N, K, seed=51)
+    A = torch.from_numpy(a).to(torch.bfloat16).to(dev())
+    B = torch.from_numpy(b).to(torch.bfloat16).to(dev())
+    ref = oracle(A, B)
+    sk()._fast_cache.clear()
+    first = mm(A, B, out_dtype=torch.float32)
+    for _ in range(3):
+        assert torch.equal(mm(A, B, out_dtype=torch.float32), first)
+    assert len(sk()._fast_cache) >= 1
+    assert rel(first, ref) <= TOL_16_OUT32
+    Bt = B.t().contiguous().t()                        # column-major B: another signature
+    for _ in range(3):
+        assert rel(mm(A, Bt, out_dtype=torch.float32), ref) <= TOL_16_OUT32
+    big = torch.zeros((M, 2 * K), dtype=torch.bfloat16, device=dev())
+    big[:, ::2] = A                                    # neither dimension contiguous: copied
+    As = big[:, ::2]
+    n0 = len(sk()._fast_cache)
+    for _ in range(3):
+        assert rel(mm(As, B, out_dtype=torch.float32), ref) <= TOL_16_OUT32
+    assert len(sk()._fast_cache) == n0
+    pad = torch.zeros((M, K + 64), dtype=torch.bfloat16, device=dev())
+    pad[:, :K] = A                                     # leading dimension K + 64
+    for _ in range(3):
+        assert rel(mm(pad[:, :K], B, out_dtype=torch.float32), ref) <= TOL_16_OUT32
