@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--no-per-shape", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the BF16 4096^3 and 8192^3 timings")
     ap.add_argument("--no-waits", action="store_true", help="skip the timed pass that measures fix-up waits")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the passes")
+    ap.add_argument("--profile-shape", default="",
+                    help="MxNxK: run only this BF16 GEMM (automatic policy) --profile-steps times, for profilers")
     ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many Stream-K steps (for profiler runs) and print timings")
@@ -420,6 +423,37 @@ def suite(args):
               "three_gemms_ms": round(us_k / 1e3, 4), "three_gemms_tflops": round(fl / us_k / 1e6, 1)})
 
 
+def profile_shape(args):
+    """One BF16 GEMM (A, B, C row-major, N(0,1) inputs, automatic policy) run
+    --profile-steps times back to back, for rocprofv3 kernel traces and
+    counters of a single shape."""
+    import torch
+    from paper_2212_08964_amd import skgemm as sk
+    M, N, K = (int(x) for x in args.profile_shape.lower().split("x"))
+    c = Case()
+    c.M, c.N, c.K = M, N, K
+    c.A = torch.randn((M, K), device="cuda:0", dtype=torch.float32).to(torch.bfloat16)
+    c.B = torch.randn((K, N), device="cuda:0", dtype=torch.float32).to(torch.bfloat16)
+    c.C = torch.empty((M, N), device="cuda:0", dtype=torch.bfloat16)
+    plan = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="auto")
+    ws = torch.zeros(max(plan.workspace_size(), 256), dtype=torch.uint8, device="cuda:0")
+    f = make_launcher(c, plan, ws, torch.cuda.current_stream().cuda_stream)
+    steps = max(1, args.profile_steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    info = plan.info()
+    print(json.dumps({"shape": [M, N, K], "plan": {k: info[k] for k in ("policy_name", "tile", "g_sk", "grid")},
+                      "launches": steps, "us_per_launch": round(us, 2),
+                      "tflops": round(2.0 * M * N * K / (us * 1e-6) / 1e12, 1)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -427,6 +461,9 @@ def main():
         sys.exit(2)
     if args.suite:
         suite(args)
+        return
+    if args.profile_shape:
+        profile_shape(args)
         return
     import numpy as np
     import torch
@@ -507,6 +544,40 @@ def main():
     torch.cuda.synchronize()
     dp_ms_per_step = start.elapsed_time(end) / args.steps
     dp_value = total_flops / (dp_ms_per_step * 1e-3) / 1e12
+
+    # ---- the same passes replayed from HIP graphs (one graph of n launches per
+    # policy, captured on a side stream; the replays run the same kernels with
+    # the same arguments, without per-launch host work)
+    graph = None
+    if not args.no_graph:
+        cap = torch.cuda.Stream()
+        gl_sk = [make_launcher(c, c.sk, ws, cap.cuda_stream) for c in cases]
+        gl_dp = [make_launcher(c, c.dp, ws, cap.cuda_stream) for c in cases]
+        cap.wait_stream(stream)
+        graphs = {}
+        for name, ls in (("sk", gl_sk), ("dp", gl_dp)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                run_pass(ls)
+            graphs[name] = g
+        torch.cuda.synchronize()
+        gms = {}
+        for name in ("sk", "dp", "sk", "dp"):
+            graphs[name].replay()
+            torch.cuda.synchronize()
+            start.record(stream)
+            for _ in range(args.steps):
+                graphs[name].replay()
+            end.record(stream)
+            torch.cuda.synchronize()
+            t = start.elapsed_time(end) / args.steps
+            gms[name] = min(gms.get(name, t), t)
+        graph = {"ms_per_step": round(gms["sk"], 4), "value": round(total_flops / (gms["sk"] * 1e-3) / 1e12, 3),
+                 "dp_ms_per_step": round(gms["dp"], 4),
+                 "dp_value": round(total_flops / (gms["dp"] * 1e-3) / 1e12, 3),
+                 "note": "one pass per policy captured in a HIP graph and replayed (best of two timed blocks of "
+                         "K replays)"}
+        del graphs
 
     # ---- per-shape times, both policies in alternating rounds (no policy
     # always runs first).  Warm: median over 5 rounds of back-to-back launches
@@ -635,6 +706,7 @@ def main():
         "dp_ms_per_step": round(dp_ms_per_step, 4),
         "sk_over_dp_aggregate": round(value / dp_value, 4),
         "sk_over_dp_per_shape": ratios is not None and per_shape or None,
+        "graph_replay": graph,
         "large_shapes": large or None,
         "fixup_waits": waits,
         "plan_us_per_gemm": round(plan_us, 2),

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "skgemm_internal.h"
@@ -62,8 +63,8 @@ template <int DT, int V> struct Cfg;
 // NS is the number of LDS stages of the MAC-loop pipeline (NS - 1 k-slabs in
 // flight while one is consumed).
 template <> struct Cfg<DT_F32, 0> { static constexpr int EB = 4, BM = kTileF32.bm, BN = kTileF32.bn, BK = kTileF32.bk, WM = 2, WN = 2, NS = kTileF32.ns; };
-template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
-template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; };
+template <> struct Cfg<DT_F16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; static constexpr bool PRIO = true; };
+template <> struct Cfg<DT_BF16, 0> { static constexpr int EB = 2, BM = kTile16.bm, BN = kTile16.bn, BK = kTile16.bk, WM = 2, WN = 4, NS = kTile16.ns; static constexpr bool PRIO = true; };
 template <> struct Cfg<DT_F8, 0> { static constexpr int EB = 1, BM = kTileF8.bm, BN = kTileF8.bn, BK = kTileF8.bk, WM = 2, WN = 4, NS = kTileF8.ns; };
 template <> struct Cfg<DT_F8, 1> { static constexpr int EB = 1, BM = kTileF8S.bm, BN = kTileF8S.bn, BK = kTileF8S.bk, WM = 2, WN = 2, NS = kTileF8S.ns; };
 template <> struct Cfg<DT_F64, 0> { static constexpr int EB = 8, BM = kTileF64.bm, BN = kTileF64.bn, BK = kTileF64.bk, WM = 2, WN = 2, NS = kTileF64.ns; };
@@ -73,6 +74,12 @@ template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.
 template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 
+// Optional tile traits: PRIO raises the waves' priority through the MFMA
+// section of each k-slab; WPE overrides the waves per SIMD the register
+// budget is sized for.
+template <class C, class = void> struct PrioOf { static constexpr bool value = false; };
+template <class C> struct PrioOf<C, std::void_t<decltype(C::PRIO)>> { static constexpr bool value = C::PRIO; };
+
 template <int DT, int V>
 constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
 
@@ -80,8 +87,11 @@ constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
 // the 4-wave tiles (the 8-wave tiles get two waves per SIMD from one, and the
 // 8-wave small tile two workgroups); three for the 64x64 FP64 tile, whose
 // accumulators take a quarter of the others', two for the 128x128 one.
+template <class C, class = void> struct WpeOf { static constexpr int value = 0; };
+template <class C> struct WpeOf<C, std::void_t<decltype(C::WPE)>> { static constexpr int value = C::WPE; };
 template <int DT, int V>
-constexpr int kWavesPerEU = DT == DT_F64 ? (V == 1 ? 2 : 3) : V == 2 ? 4 : 2;
+constexpr int kWavesPerEU = WpeOf<Cfg<DT, V>>::value ? WpeOf<Cfg<DT, V>>::value
+                            : DT == DT_F64 ? (V == 1 ? 2 : 3) : V == 2 ? 4 : 2;
 
 // Buffer descriptor word 3 for untyped buffer loads on gfx9-family targets.
 constexpr int kBufferFlags = 0x00020000;
@@ -586,12 +596,12 @@ struct Gemm {
             constexpr int READS = FM * (AKC ? 1 : 2) + FN * (BKC ? 1 : 2);
             constexpr int MFMAS = FM * FN;
             load(0, 0);
-            // The 256x256 tile runs two waves per SIMD from one workgroup:
+            // PRIO (the 256x256 tile: two waves per SIMD from one workgroup):
             // a raised priority while a wave is in its MFMA section lets it
             // keep the matrix core busy ahead of the other wave's loads and
             // barrier (measured +1.5-2.5 % on large shapes; neutral on the
             // small tiles, which keep the default).
-            if constexpr (V == 0) __builtin_amdgcn_s_setprio(1);
+            if constexpr (PrioOf<C_>::value) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const int cur = s & 1;
@@ -614,7 +624,7 @@ struct Gemm {
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if constexpr (V == 0) __builtin_amdgcn_s_setprio(0);
+            if constexpr (PrioOf<C_>::value) __builtin_amdgcn_s_setprio(0);
         } else if constexpr (DT == DT_F64) {
             // v_mfma_f64_16x16x4f64: lane l holds A[row l%16][k l/16] and
             // B[k l/16][col l%16] of the k4 step; each 32x32 block is four
@@ -1017,7 +1027,7 @@ struct Gemm {
     static constexpr int EPI_BYTES = 32 * EPI_LD * 4;
     static constexpr int EPI_PER_STAGE = STAGE / EPI_BYTES;    // waves staging in one LDS stage
     static_assert(EPI_PER_STAGE >= 1 && NW <= EPI_PER_STAGE * NS, "epilogue staging must fit in the stages");
-    static_assert(UNITS <= 8, "unit masks and flag words");
+    static_assert(UNITS <= 16 && REDUCERS <= 8, "unit masks and flag words");
 
     static __device__ __forceinline__ __amdgpu_buffer_rsrc_t peer_slot(const KArgs& ka, int k, bool valid) {
         return __builtin_amdgcn_make_buffer_rsrc(ka.partials + (size_t)uni(k) * SLOT, (short)0,
