@@ -178,6 +178,23 @@ skgemm_status_t skgemm_run(skgemm_plan_t plan,
                            const float* scale_a, const float* scale_b,
                            void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* skgemm_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc): the fix-up
+ * workspace is a 64 MiB device array the library holds on every GPU it runs
+ * on until the process ends, so the caller passes no workspace.  Plans whose
+ * skgemm_workspace_size exceeds 64 MiB are refused with
+ * SKGEMM_ERR_WORKSPACE (e.g. more than 254 Stream-K workgroups with
+ * 256x256 FP32 partial tiles).  Allocates nothing: before the GEMM it
+ * clears the error word and the plan's flag lines with a small kernel on
+ * `stream` (capturable), then runs skgemm_run on the array.  All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (on
+ * different streams) race and give wrong results; a fix-up timeout of one
+ * call is not reported (the next call clears the error word). */
+skgemm_status_t skgemm_run_noalloc(skgemm_plan_t plan,
+                                   const void* A, int64_t lda, const void* B, int64_t ldb,
+                                   void* C, int64_t ldc, float alpha, float beta,
+                                   const float* scale_a, const float* scale_b, hipStream_t stream);
+
 /* Number of schedule records a traced run of this plan can write: the number
  * of launched workgroups times the most segments any of them performs. */
 skgemm_status_t skgemm_trace_capacity(skgemm_plan_t plan, size_t* n_records);

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libskgemm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "kernels_f16.hip", "kernels_bf16.hip", "kernels_f8.hip",
-           "dispatch.hip", "quant.hip", "skgemm_abi.cpp"]
+           "dispatch.hip", "quant.hip", "noalloc.hip", "skgemm_abi.cpp"]
 
 ARCH = "gfx950"
 

@@ -31,7 +31,7 @@ EXPORTED = [
     "skgemm_schedule", "skgemm_check_device_error", "skgemm_plan_destroy", "skgemm_status_string",
     "skgemm_grouped_plan", "skgemm_grouped_table_size", "skgemm_grouped_table", "skgemm_grouped_run",
     "skgemm_grouped_run_traced", "skgemm_quantize_workspace_size", "skgemm_quantize_e4m3",
-    "skgemm_run_timed", "skgemm_realtime_hz",
+    "skgemm_run_timed", "skgemm_realtime_hz", "skgemm_run_noalloc",
     "skgemm_batched_plan", "skgemm_batched_run", "skgemm_batched_run_traced",
 ]
 
@@ -97,6 +97,8 @@ def lib():
                                                  ctypes.c_float, vp, vp, vp, sz, vp]
                 L.skgemm_batched_run_traced.argtypes = [vp, vp, i64, i64, vp, i64, i64, vp, i64, i64,
                                                         ctypes.c_float, ctypes.c_float, vp, vp, vp, sz, vp, sz, vp]
+                L.skgemm_run_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_float, ctypes.c_float,
+                                                 vp, vp, vp]
                 L.skgemm_plan_info.argtypes = [vp, P(i64), i32]
                 L.skgemm_model_constants.argtypes = [vp, P(ctypes.c_double)]
                 L.skgemm_schedule.argtypes = [vp, vp, sz, P(sz)]
@@ -222,6 +224,11 @@ class Plan:
                                        float(beta), scale_a, scale_b, workspace, int(ws_bytes), trace,
                                        int(trace_records), stream), "skgemm_run_traced")
 
+
+    def run_noalloc(self, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0, scale_a=None, scale_b=None, stream=None):
+        """skgemm_run on the library's own device array (no workspace argument)."""
+        _check(lib().skgemm_run_noalloc(self._h, A, int(lda), B, int(ldb), C, int(ldc), float(alpha),
+                                        float(beta), scale_a, scale_b, stream), "skgemm_run_noalloc")
 
     def run_timed(self, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, workspace, ws_bytes,
                   trace, times, trace_records, stream=None):
