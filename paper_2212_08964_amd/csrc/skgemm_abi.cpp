@@ -150,8 +150,14 @@ int model_best_g(int64_t t, int64_t ipt, int64_t p, const double* m) {
 // larger than the CU count puts n = ceil(g / cus) workgroups on some CUs, and
 // those run an iteration in c + (e - c)(n - 1)/(occ - 1) rather than c (e,
 // m[4], with all occ = p / cus slots of a CU busy): the slowest workgroup
-// sets the time.
-int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const double* m) {
+// sets the time.  On problems without ragged edges (M, N, K multiples of 64)
+// a grid above the CU count with three or more shares per tile needs at
+// least 8 iterations per share: there the data-parallel tiles run at their
+// calibrated speed, and short shares on CUs holding two workgroups lost to
+// data-parallel in every measured case (BF16 sweep: 0.81-0.97x at 100-165
+// tiles of 128x128 with 4-6 iterations per share), a cost of the fix-up
+// traffic and co-residency the per-workgroup model does not see.
+int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const double* m, bool aligned) {
     const int64_t smax = std::max<int64_t>(1, std::min(p / std::max<int64_t>(t, 1), ipt));
     const int64_t occ = std::max<int64_t>(1, p / std::max<int64_t>(cus, 1));
     auto time_at = [&](int64_t g) {
@@ -163,6 +169,7 @@ int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const doubl
     int best_s = 1;
     double best = time_at(t);
     for (int64_t sp = 2; sp <= smax; ++sp) {
+        if (aligned && sp > 2 && t * sp > cus && cdiv(ipt, sp) < 8) break;
         const double v = time_at(t * sp);
         if (v < best) {
             best = v;
@@ -384,7 +391,10 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
                 // L2.  Unaligned shares start each workgroup at its own
                 // k-offset, which on MI355X's per-XCD L2 costs up to 2x.
                 const int64_t sk_t = w == 0 ? t_work : r;
-                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model);
+                bool aligned = true;
+                for (size_t i = 0; i < pl->pM.size(); ++i)
+                    aligned = aligned && pl->pM[i] % 64 == 0 && pl->pN[i] % 64 == 0 && pl->pK[i] % 64 == 0;
+                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model, aligned);
                 if (s_best == 1) policy = SKGEMM_POLICY_DP;
                 else {
                     policy = w == 0 ? SKGEMM_POLICY_SK : SKGEMM_POLICY_DP_1TILE_SK;

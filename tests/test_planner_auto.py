@@ -8,7 +8,9 @@ selection), checked through the C ABI against the properties it is defined by:
 * s minimises the documented cost a + b[s > 1] + c_n ceil(ipt / s) + d (s - 1)
   over 1 <= s <= min(p / count, ipt), where c_n is c for grids of at most one
   workgroup per CU and c + (e - c)(n - 1)/(occ - 1) for n = ceil(g / CUs)
-  workgroups on a CU (ties to the smaller s);
+  workgroups on a CU (ties to the smaller s); when M, N and K are multiples
+  of 64, the search stops at the first s >= 3 whose grid exceeds the CU
+  count with fewer than 8 iterations per share;
 * its plans use the split fix-up (every Stream-K tile cut into s one-segment
   shares).
 The schedules these plans launch are compared with the oracle's enumerator in
@@ -55,6 +57,12 @@ def test_auto_policy_properties(dtype):
             continue
         count = t if w == 0 else r
         smax = max(1, min(p // count, ipt))
+        aligned = M % 64 == 0 and N % 64 == 0 and K % 64 == 0
+        if aligned:
+            for s_ in range(3, smax + 1):
+                if s_ * count > cus and -(-ipt // s_) < 8:
+                    smax = s_ - 1
+                    break
         costs = [_cost(s, count, ipt, p, cus, m) for s in range(1, smax + 1)]
         best = 1 + min(range(len(costs)), key=lambda i: (costs[i], i))
         if best == 1:
