@@ -11,5 +11,9 @@ Modules:
 * ``lowp``     - BF16 / FP16 / FP8-E4M3 decoding, rounding and per-tensor
                  FP8 quantisation, written from the format definitions.
 * ``schedule`` - enumerator of the data-parallel, fixed-split, basic Stream-K
-                 and hybrid schedules, and the analytical grid-size model.
+                 and hybrid schedules, the analytical grid-size model and the
+                 paper's own policy selection.
+* ``grouped``  - the schedule of grouped (and strided batched) launches.
+* ``conv``     - 2-D convolution from its definition (the implicit-GEMM
+                 extension's result).
 """
