@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the BF16 4096^3 and 8192^3 timings")
     ap.add_argument("--no-waits", action="store_true", help="skip the timed pass that measures fix-up waits")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay of the passes")
+    ap.add_argument("--profile-policy", default="auto", choices=["auto", "dp"],
+                    help="with --profile-steps: which pass to run (the automatic policy or the DP baseline)")
     ap.add_argument("--profile-shape", default="",
                     help="MxNxK: run only this BF16 GEMM (automatic policy) --profile-steps times, for profilers")
     ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
@@ -494,9 +496,10 @@ def main():
             f()
 
     if args.profile_steps:
+        passes = dp_launch if args.profile_policy == "dp" else sk_launch
         for s in range(args.profile_steps):
             t1 = time.perf_counter()
-            run_pass(sk_launch)
+            run_pass(passes)
             torch.cuda.synchronize()
             print(f"profile step {s}: {(time.perf_counter() - t1) * 1e3:.2f} ms", flush=True)
         if args.copy_probe_mib:
@@ -507,8 +510,9 @@ def main():
             dst.copy_(src)
             torch.cuda.synchronize()
             print(f"copy probe: {nb} bytes read, {nb} bytes written", flush=True)
-        print(f"algorithmic bytes per step: {sum(c.bytes + c.fixup_bytes for c in cases)} "
-              f"(fix-up {sum(c.fixup_bytes for c in cases)}); launches per step: {len(cases)}", flush=True)
+        fix = 0 if args.profile_policy == "dp" else sum(c.fixup_bytes for c in cases)
+        print(f"{args.profile_policy} pass: algorithmic bytes per step: {sum(c.bytes for c in cases) + fix} "
+              f"(fix-up {fix}); launches per step: {len(cases)}", flush=True)
         return
 
     for _ in range(args.warmup):

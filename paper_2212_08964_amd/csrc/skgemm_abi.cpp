@@ -126,6 +126,10 @@ void model_for(int dt, int v, double* m) {
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// HBM bytes per microsecond a kernel of this library can stream: 6 TB/s, 75 %
+// of MI355X's 8 TB/s, the rate its HBM-bound FP8 quantising passes reach.
+constexpr double kHbmBytesPerUs = 6.0e6;
+
 double model_time(int64_t g, int64_t t, int64_t ipt, const double* m) {
     const int64_t ipc = cdiv(t * ipt, g);
     const int64_t peers = cdiv(ipt, ipc);
@@ -157,14 +161,21 @@ int model_best_g(int64_t t, int64_t ipt, int64_t p, const double* m) {
 // data-parallel in every measured case (BF16 sweep: 0.81-0.97x at 100-165
 // tiles of 128x128 with 4-6 iterations per share), a cost of the fix-up
 // traffic and co-residency the per-workgroup model does not see.
-int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const double* m, bool aligned) {
+//
+// Memory-bound regime: no split can run faster than its HBM traffic allows,
+// the operands' bytes plus the partial tiles the split writes and reads back
+// (2 (s - 1) t tile_bytes), at kHbmBytesPerUs; the modelled time of a split is
+// the larger of the two (ties still go to the smallest s).
+int model_best_split(int64_t t, int64_t ipt, int64_t p, int64_t cus, const double* m, bool aligned,
+                     double op_bytes, double tile_bytes) {
     const int64_t smax = std::max<int64_t>(1, std::min(p / std::max<int64_t>(t, 1), ipt));
     const int64_t occ = std::max<int64_t>(1, p / std::max<int64_t>(cus, 1));
     auto time_at = [&](int64_t g) {
         const int64_t n = cdiv(g, cus);
         const double c = n <= 1 || occ <= 1 ? m[2] : m[2] + (m[4] - m[2]) * double(n - 1) / double(occ - 1);
         const double mg[4] = {m[0], m[1], c, m[3]};
-        return model_time(g, t, ipt, mg);
+        const double partials = 2.0 * double(g - t) * tile_bytes;
+        return std::max(model_time(g, t, ipt, mg), (op_bytes + partials) / kHbmBytesPerUs);
     };
     int best_s = 1;
     double best = time_at(t);
@@ -330,6 +341,16 @@ static bool uniform_ipt(const skgemm_plan_s& pl) {
     return true;
 }
 
+// Algorithmic HBM bytes of a plan's problems: A and B read once, C written
+// once (a strided batch counts every problem).
+static double operand_bytes(const skgemm_plan_s& pl) {
+    const double eb = elem_bytes(pl.ta), ec = elem_bytes(pl.tc);
+    double sum = 0.0;
+    for (size_t i = 0; i < pl.pM.size(); ++i)
+        sum += (double(pl.pM[i]) * pl.pK[i] + double(pl.pK[i]) * pl.pN[i]) * eb + double(pl.pM[i]) * pl.pN[i] * ec;
+    return sum * double(pl.batch > 0 ? pl.batch : 1);
+}
+
 static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o) {
     int cus = o.num_cus, occ = o.occupancy;
     if (cus == 0 || occ == 0) {
@@ -394,7 +415,8 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
                 bool aligned = true;
                 for (size_t i = 0; i < pl->pM.size(); ++i)
                     aligned = aligned && pl->pM[i] % 64 == 0 && pl->pN[i] % 64 == 0 && pl->pK[i] % 64 == 0;
-                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model, aligned);
+                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model, aligned, operand_bytes(*pl),
+                                                    double(pl->BM) * pl->BN * (pl->dtype == DT_F64 ? 8 : 4));
                 if (s_best == 1) policy = SKGEMM_POLICY_DP;
                 else {
                     policy = w == 0 ? SKGEMM_POLICY_SK : SKGEMM_POLICY_DP_1TILE_SK;
@@ -511,7 +533,20 @@ static void add_problem(skgemm_plan_s* pl, int64_t M, int64_t N, int64_t K);
 // of the Analytical Modeling subsection extended to the hybrids: a
 // workgroup's Stream-K share plus its data-parallel tiles, each tile paying
 // the fixed cost a; pure data-parallel plans run in ceil(t / p) waves.
-static double plan_estimate(const skgemm_plan_s* pl) {
+static double plan_estimate_compute(const skgemm_plan_s* pl);
+
+// The larger of the compute model's time and the plan's HBM time (operand
+// bytes plus partial tiles written and read back).
+static double plan_estimate(const skgemm_plan_s* pl, double* compute) {
+    const double tc = plan_estimate_compute(pl);
+    if (compute) *compute = tc;
+    if (pl->t == 0) return 0.0;
+    const double partials = 2.0 * double(pl->g_sk > pl->sk_tiles ? pl->g_sk - pl->sk_tiles : 0) * pl->BM * pl->BN *
+                            (pl->dtype == DT_F64 ? 8.0 : 4.0);
+    return std::max(tc, (operand_bytes(*pl) + partials) / kHbmBytesPerUs);
+}
+
+static double plan_estimate_compute(const skgemm_plan_s* pl) {
     if (pl->t == 0) return 0.0;
     const int np = int(pl->pipt.size());
     const double ipt = double(pl->iter_base[np]) / pl->t;
@@ -594,15 +629,19 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
             cand[2] = nullptr;
         }
     }
+    // smallest estimate; between plans the HBM bound makes equal, the smaller
+    // compute-model time
     skgemm_plan_s* best = nullptr;
-    double best_t = 0.0;
+    double best_t = 0.0, best_c = 0.0;
     for (skgemm_plan_s* c : cand) {
         if (!c) continue;
-        const double t = plan_estimate(c);
-        if (!best || t < best_t) {
+        double tc = 0.0;
+        const double t = plan_estimate(c, &tc);
+        if (!best || t < best_t || (t == best_t && tc < best_c)) {
             delete best;
             best = c;
             best_t = t;
+            best_c = tc;
         } else {
             delete c;
         }

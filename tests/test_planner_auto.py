@@ -5,8 +5,9 @@ selection), checked through the C ABI against the properties it is defined by:
 * otherwise the remainder tiles (all tiles below one wave) are cut into s equal
   shares with g = s * (their count): basic Stream-K below one wave, DP +
   one-tile SK above, data-parallel when s = 1;
-* s minimises the documented cost a + b[s > 1] + c_n ceil(ipt / s) + d (s - 1)
-  over 1 <= s <= min(p / count, ipt), where c_n is c for grids of at most one
+* s minimises the documented cost max(a + b[s > 1] + c_n ceil(ipt / s) +
+  d (s - 1), (operand bytes + 2 (s - 1) count BM BN 4) / 6 TB/s) over
+  1 <= s <= min(p / count, ipt), where c_n is c for grids of at most one
   workgroup per CU and c + (e - c)(n - 1)/(occ - 1) for n = ceil(g / CUs)
   workgroups on a CU (ties to the smaller s); when M, N and K are multiples
   of 64, the search stops at the first s >= 3 whose grid exceeds the CU
@@ -27,12 +28,16 @@ def _sk():
     return skgemm
 
 
-def _cost(s, count, ipt, p, cus, m):
+HBM_BYTES_PER_US = 6.0e6     # the rate the rule assumes for its memory-bound bound
+
+
+def _cost(s, count, ipt, p, cus, m, op_bytes=0.0, tile_bytes=0.0):
     a, b, c, d, e = m
     occ = max(1, p // cus)
     n = -(-(s * count) // cus)
     cn = c if n <= 1 or occ <= 1 else c + (e - c) * (n - 1) / (occ - 1)
-    return a + (b if s > 1 else 0.0) + cn * -(-ipt // s) + d * (s - 1)
+    compute = a + (b if s > 1 else 0.0) + cn * -(-ipt // s) + d * (s - 1)
+    return max(compute, (op_bytes + 2.0 * (s - 1) * count * tile_bytes) / HBM_BYTES_PER_US)
 
 
 SHAPES = [(384, 384, 1024), (1024, 1024, 1024), (300, 500, 700), (4096, 4096, 64), (128, 8192, 8192),
@@ -63,7 +68,10 @@ def test_auto_policy_properties(dtype):
                 if s_ * count > cus and -(-ipt // s_) < 8:
                     smax = s_ - 1
                     break
-        costs = [_cost(s, count, ipt, p, cus, m) for s in range(1, smax + 1)]
+        eb = {sk.F32: 4, sk.BF16: 2, sk.F64: 8}[ta]
+        op = float((M * K + K * N) * eb + M * N * eb)
+        tb = float(info["BM"] * info["BN"] * (8 if ta == sk.F64 else 4))
+        costs = [_cost(s, count, ipt, p, cus, m, op, tb) for s in range(1, smax + 1)]
         best = 1 + min(range(len(costs)), key=lambda i: (costs[i], i))
         if best == 1:
             assert pol == "dp" and info["grid"] == t, (M, N, K, cus, occ)
