@@ -415,7 +415,10 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
                 bool aligned = true;
                 for (size_t i = 0; i < pl->pM.size(); ++i)
                     aligned = aligned && pl->pM[i] % 64 == 0 && pl->pN[i] % 64 == 0 && pl->pK[i] % 64 == 0;
-                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model, aligned, operand_bytes(*pl),
+                // the HBM bound of the split region: its tiles' share of the
+                // operand bytes (the data-parallel waves before it stream theirs)
+                const double op_sk = operand_bytes(*pl) * double(sk_t) / double(t_work);
+                const int s_best = model_best_split(sk_t, ipt, p, cus, pl->model, aligned, op_sk,
                                                     double(pl->BM) * pl->BN * (pl->dtype == DT_F64 ? 8 : 4));
                 if (s_best == 1) policy = SKGEMM_POLICY_DP;
                 else {

@@ -6,12 +6,13 @@ selection), checked through the C ABI against the properties it is defined by:
   shares with g = s * (their count): basic Stream-K below one wave, DP +
   one-tile SK above, data-parallel when s = 1;
 * s minimises the documented cost max(a + b[s > 1] + c_n ceil(ipt / s) +
-  d (s - 1), (operand bytes + 2 (s - 1) count BM BN 4) / 6 TB/s) over
+  d (s - 1), (B + 2 (s - 1) count BM BN 4) / 6 TB/s) over
   1 <= s <= min(p / count, ipt), where c_n is c for grids of at most one
   workgroup per CU and c + (e - c)(n - 1)/(occ - 1) for n = ceil(g / CUs)
   workgroups on a CU (ties to the smaller s); when M, N and K are multiples
   of 64, the search stops at the first s >= 3 whose grid exceeds the CU
-  count with fewer than 8 iterations per share;
+  count with fewer than 8 iterations per share; B is the split tiles' share
+  (count / t) of the operand bytes (A, B read once, C written once);
 * its plans use the split fix-up (every Stream-K tile cut into s one-segment
   shares).
 The schedules these plans launch are compared with the oracle's enumerator in
@@ -69,7 +70,7 @@ def test_auto_policy_properties(dtype):
                     smax = s_ - 1
                     break
         eb = {sk.F32: 4, sk.BF16: 2, sk.F64: 8}[ta]
-        op = float((M * K + K * N) * eb + M * N * eb)
+        op = float((M * K + K * N) * eb + M * N * eb) * count / t     # the split region's share
         tb = float(info["BM"] * info["BN"] * (8 if ta == sk.F64 else 4))
         costs = [_cost(s, count, ipt, p, cus, m, op, tb) for s in range(1, smax + 1)]
         best = 1 + min(range(len(costs)), key=lambda i: (costs[i], i))
