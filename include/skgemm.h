@@ -334,6 +334,36 @@ skgemm_status_t skgemm_batched_run_traced(skgemm_plan_t plan,
                                           void* workspace, size_t ws_bytes,
                                           int32_t* trace, size_t trace_records, hipStream_t stream);
 
+/* ---------------------------------------------------------------- implicit-GEMM convolution
+ * 2-D convolution (cross-correlation, as deep-learning frameworks define it)
+ *   y[n,p,q,k] = alpha * sum_{r,s,c} x[n, p*stride_h + r*dil_h - pad_h, q*stride_w + s*dil_w - pad_w, c]
+ *                        * w[k,r,s,c] + beta * y[n,p,q,k]
+ * with x NHWC, w KRSC and y NPQK (channels innermost, dense), zero outside
+ * the image, P = (h + 2 pad_h - dil_h (r - 1) - 1) / stride_h + 1 and Q
+ * likewise: the GEMM with M = n P Q output pixels, N = k output channels and
+ * K = r s c, whose A is gathered from x on the fly (implicit GEMM), split by
+ * the same Stream-K schedules (the conclusion of the Stream-K chapter names
+ * convolution among the GEMM-like problems the decomposition extends to).
+ * 16-bit inputs, FP32 accumulation, output 16-bit (the input type) or FP32;
+ * c must be a multiple of 64 and x at most 2^31 - 1 bytes
+ * (SKGEMM_ERR_UNSUPPORTED otherwise).  plan_info describes the GEMM view;
+ * workspace and options as for skgemm_plan / skgemm_run (the tile options
+ * name 256x256x64 or 128x128x64). */
+typedef struct {
+    int32_t n, h, w, c;                       /* input */
+    int32_t k, r, s;                          /* filters: k output channels, r x s window */
+    int32_t pad_h, pad_w, stride_h, stride_w, dil_h, dil_w;
+} skgemm_conv_t;
+
+skgemm_status_t skgemm_conv_plan(skgemm_plan_t* out, const skgemm_conv_t* conv, skgemm_dtype_t t_in,
+                                 skgemm_dtype_t t_out, const skgemm_options_t* opt);
+skgemm_status_t skgemm_conv_run(skgemm_plan_t plan, const void* x, const void* w, void* y, float alpha, float beta,
+                                void* workspace, size_t ws_bytes, hipStream_t stream);
+/* Same, writing schedule records as skgemm_run_traced does (tiles of the GEMM view). */
+skgemm_status_t skgemm_conv_run_traced(skgemm_plan_t plan, const void* x, const void* w, void* y, float alpha,
+                                       float beta, void* workspace, size_t ws_bytes, int32_t* trace,
+                                       size_t trace_records, hipStream_t stream);
+
 /* ---------------------------------------------------------------- FP8 front end
  * Per-tensor E4M3 quantisation of a rows x cols matrix X (FP32, BF16 or
  * FP16, layout lx, leading dimension ldx) into Q (E4M3FN bytes, layout lq,

@@ -6,4 +6,5 @@ hand-written HIP kernels behind the C ABI of include/skgemm.h.  This package
 is the thin Python layer over that library.
 """
 from . import skgemm  # noqa: F401
-from .skgemm import GroupedPlan, Plan, grouped_matmul, matmul, matmul_fp8, quantize_e4m3  # noqa: F401
+from .skgemm import (BatchedPlan, ConvPlan, GroupedPlan, Plan, batched_matmul, conv2d, grouped_matmul,  # noqa: F401
+                     matmul, matmul_fp8, quantize_e4m3)

@@ -23,11 +23,15 @@ const void* kernel_fn_f16(bool akc, bool bkc, int v) {
         return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_F16, false, true, 2>)
                    : reinterpret_cast<const void*>(&skgemm_kernel<DT_F16, false, false, 2>);
     }
+    // implicit-GEMM convolution: A gathered, filters K-contiguous
+    if (v == 3 && akc && bkc) return reinterpret_cast<const void*>(&skgemm_kernel<DT_F16, true, true, 3>);
+    if (v == 4 && akc && bkc) return reinterpret_cast<const void*>(&skgemm_kernel<DT_F16, true, true, 4>);
     return nullptr;
 }
 
 int kernel_threads_f16(int v) {
-    return v == 0 ? kThreadsOf<DT_F16, 0> : v == 1 ? kThreadsOf<DT_F16, 1> : v == 2 ? kThreadsOf<DT_F16, 2> : 0;
+    return v == 0 ? kThreadsOf<DT_F16, 0> : v == 1 ? kThreadsOf<DT_F16, 1> : v == 2 ? kThreadsOf<DT_F16, 2>
+           : v == 3 ? kThreadsOf<DT_F16, 3> : v == 4 ? kThreadsOf<DT_F16, 4> : 0;
 }
 
 }  // namespace skg

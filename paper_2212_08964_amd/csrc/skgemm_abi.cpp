@@ -59,6 +59,8 @@ struct skgemm_plan_s {
     std::vector<int32_t> order;             // caller's index of each problem in iteration-space order
     int t_work;                             // tiles with MAC-loop iterations (they come first)
     int64_t batch;                          // strided batch of equal problems (1 = one GEMM)
+    bool conv;                              // implicit-GEMM convolution (tile variants 3 and 4)
+    ConvArgs cv;
     int64_t sk_iters;
 };
 
@@ -97,6 +99,8 @@ TileCfg tile_for(int dt, int v) {
         }
     }
     if ((v == 1 || v == 2) && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
+    if (v == 3 && (dt == DT_BF16 || dt == DT_F16)) return kTile16;     // convolution
+    if (v == 4 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 1 && dt == DT_F8) return kTileF8S;
     if (v == 1 && dt == DT_F64) return kTileF64L;
     return TileCfg{0, 0, 0};
@@ -119,8 +123,9 @@ void model_for(int dt, int v, double* m) {
     if (dt == DT_F64 && v == 1) { m[0] = 7.98; m[1] = 1.22; m[2] = 2.04; m[3] = 1.13; m[4] = 3.84; return; }
     if (dt == DT_F64) { m[0] = 5.00; m[1] = 1.23; m[2] = 0.713; m[3] = 1.13; m[4] = 2.09; return; }
     if (dt == DT_F32) { m[0] = 6.20; m[1] = 1.25; m[2] = 2.07; m[3] = 0.569; m[4] = 3.99; return; }
+    // the convolution variants take the constants of the GEMM tile of their shape
     if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
-    if (v == 1) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
+    if (v == 1 || v == 4) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
     m[0] = 9.88; m[1] = 2.78; m[2] = 1.351; m[3] = 0.941; m[4] = 1.693;
 }
 
@@ -578,6 +583,7 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
     skgemm_plan_s* cand[kVariants] = {};
     skgemm_status_t last = SKGEMM_ERR_UNSUPPORTED;
     for (int v = 0; v < kVariants; ++v) {
+        if ((v >= 3) != base->conv) continue;     // the convolution kernels are variants 3 and 4
         const TileCfg tc_ = tile_for(base->dtype, v);
         if (!tc_.bm || !kernel_exists(base->dtype, base->akc, base->bkc, v)) continue;
         if (named && ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) ||
@@ -686,9 +692,53 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     base.M = M; base.N = N; base.K = K;
     base.G = 0;
     base.batch = 1;
+    base.conv = false;
     base.order.assign(1, 0);
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
+    if (st != SKGEMM_OK) return st;
+    *out = pl;
+    return SKGEMM_OK;
+}
+
+skgemm_status_t skgemm_conv_plan(skgemm_plan_t* out, const skgemm_conv_t* cv, skgemm_dtype_t t_in,
+                                 skgemm_dtype_t t_out, const skgemm_options_t* opt) {
+    if (!out || !cv) return SKGEMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    const skgemm_conv_t& c = *cv;
+    if (c.n < 0 || c.h < 1 || c.w < 1 || c.c < 1 || c.k < 0 || c.r < 1 || c.s < 1 || c.pad_h < 0 || c.pad_w < 0 ||
+        c.stride_h < 1 || c.stride_w < 1 || c.dil_h < 1 || c.dil_w < 1)
+        return SKGEMM_ERR_INVALID_ARG;
+    const int64_t P = (int64_t(c.h) + 2 * c.pad_h - int64_t(c.dil_h) * (c.r - 1) - 1) / c.stride_h + 1;
+    const int64_t Q = (int64_t(c.w) + 2 * c.pad_w - int64_t(c.dil_w) * (c.s - 1) - 1) / c.stride_w + 1;
+    if (int64_t(c.h) + 2 * c.pad_h < int64_t(c.dil_h) * (c.r - 1) + 1 ||
+        int64_t(c.w) + 2 * c.pad_w < int64_t(c.dil_w) * (c.s - 1) + 1)
+        return SKGEMM_ERR_INVALID_ARG;                     // the window does not fit the padded image
+    if (t_in != SKGEMM_BF16 && t_in != SKGEMM_F16) return SKGEMM_ERR_UNSUPPORTED;
+    // whole k-slabs of channels (one filter tap per slab) and 32-bit gather offsets
+    if (c.c % kTile16.bk != 0) return SKGEMM_ERR_UNSUPPORTED;
+    const int64_t in_bytes = int64_t(c.n) * c.h * c.w * c.c * elem_bytes(t_in);
+    if (in_bytes > kMaxDim) return SKGEMM_ERR_UNSUPPORTED;
+    const int64_t M = int64_t(c.n) * P * Q, N = c.k, K = int64_t(c.r) * c.s * c.c;
+    if (M > kMaxDim || K > kMaxDim) return SKGEMM_ERR_UNSUPPORTED;
+    skgemm_options_t o;
+    skgemm_default_options(&o);
+    if (opt) o = *opt;
+    if (o.hybrid_min_waves <= 0) o.hybrid_min_waves = 2;
+    skgemm_plan_s base{};
+    // the GEMM view: A (gathered) K-contiguous, the filters a column-major B, C row-major
+    skgemm_status_t st = init_common(&base, SKGEMM_ROW_MAJOR, SKGEMM_COL_MAJOR, SKGEMM_ROW_MAJOR, t_in, t_in, t_out, o);
+    if (st != SKGEMM_OK) return st;
+    base.M = M; base.N = N; base.K = K;
+    base.G = 0;
+    base.batch = 1;
+    base.conv = true;
+    base.cv = ConvArgs{int32_t(c.n), int32_t(c.h), int32_t(c.w), int32_t(c.c), int32_t(P), int32_t(Q), int32_t(c.r),
+                       int32_t(c.s), int32_t(c.pad_h), int32_t(c.pad_w), int32_t(c.stride_h), int32_t(c.stride_w),
+                       int32_t(c.dil_h), int32_t(c.dil_w)};
+    base.order.assign(1, 0);
+    skgemm_plan_s* pl = nullptr;
+    st = plan_variants(&base, o, 1, &base.M, &base.N, &base.K, &pl);
     if (st != SKGEMM_OK) return st;
     *out = pl;
     return SKGEMM_OK;
@@ -714,6 +764,7 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
     if (st != SKGEMM_OK) return st;
     base.G = G;
     base.batch = 1;
+    base.conv = false;
     // iteration-space order: problems with MAC-loop iterations in the given
     // order, then the K = 0 problems that have tiles (epilogue only)
     base.order.clear();
@@ -798,13 +849,14 @@ static void fill_schedule_args(const skgemm_plan_s* pl, KArgs* a, void* workspac
     a->coop_s = pl->coop_s;
     a->batch = int32_t(pl->batch);
     a->t1 = pl->tm * pl->tn;
+    if (pl->conv) a->conv = pl->cv;
 }
 
 static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                                 int64_t ldc, float alpha, float beta, const float* scale_a, const float* scale_b,
                                 void* workspace, size_t ws_bytes, int32_t* trace, uint64_t* times,
                                 size_t trace_records, hipStream_t stream, const int64_t* strides = nullptr) {
-    if (!pl || pl->G) return SKGEMM_ERR_INVALID_ARG;
+    if (!pl || pl->G || pl->conv) return SKGEMM_ERR_INVALID_ARG;
     if ((pl->batch > 1) != (strides != nullptr)) return SKGEMM_ERR_INVALID_ARG;
     GroupEntry e;
     std::memset(&e, 0, sizeof(e));
@@ -890,6 +942,7 @@ skgemm_status_t skgemm_batched_plan(skgemm_plan_t* out, int64_t batch, int64_t M
     base.M = M; base.N = N; base.K = K;
     base.G = 0;
     base.batch = batch;
+    base.conv = false;
     base.order.assign(1, 0);
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
@@ -932,6 +985,43 @@ skgemm_status_t skgemm_batched_run_traced(skgemm_plan_t plan, const void* A, int
     if (!trace) return SKGEMM_ERR_INVALID_ARG;
     return batched_impl(plan, A, lda, stride_a, B, ldb, stride_b, C, ldc, stride_c, alpha, beta, scale_a, scale_b,
                         workspace, ws_bytes, trace, trace_records, stream);
+}
+
+static skgemm_status_t conv_impl(skgemm_plan_t pl, const void* x, const void* w, void* y, float alpha, float beta,
+                                 void* workspace, size_t ws_bytes, int32_t* trace, size_t trace_records,
+                                 hipStream_t stream) {
+    if (!pl || !pl->conv) return SKGEMM_ERR_INVALID_ARG;
+    if (pl->M == 0 || pl->N == 0) return SKGEMM_OK;
+    if (!y || !x || !w) return SKGEMM_ERR_INVALID_ARG;
+    if (pl->ws_bytes) {
+        if (!workspace || ws_bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) & 255))
+            return SKGEMM_ERR_WORKSPACE;
+    }
+    if (trace && trace_records < size_t(pl->grid) * size_t(pl->max_segs)) return SKGEMM_ERR_INVALID_ARG;
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.A = x; a.B = w; a.C = y;
+    a.lda = pl->K; a.ldb = pl->K; a.ldc = pl->N;
+    a.M = pl->Ml; a.N = pl->Nl; a.K = pl->Kl;
+    a.tm = pl->tm; a.tn = pl->tn; a.ipt = pl->ipt;
+    a.alpha = alpha;
+    a.beta = beta;
+    fill_schedule_args(pl, &a, workspace, trace, nullptr);
+    if (pl->grid == 0) return SKGEMM_OK;
+    const int rc = launch_gemm(pl->dtype, pl->akc, pl->bkc, pl->variant, a, pl->grid, stream);
+    return rc == int(hipSuccess) ? SKGEMM_OK : SKGEMM_ERR_HIP;
+}
+
+skgemm_status_t skgemm_conv_run(skgemm_plan_t plan, const void* x, const void* w, void* y, float alpha, float beta,
+                                void* workspace, size_t ws_bytes, hipStream_t stream) {
+    return conv_impl(plan, x, w, y, alpha, beta, workspace, ws_bytes, nullptr, 0, stream);
+}
+
+skgemm_status_t skgemm_conv_run_traced(skgemm_plan_t plan, const void* x, const void* w, void* y, float alpha,
+                                       float beta, void* workspace, size_t ws_bytes, int32_t* trace,
+                                       size_t trace_records, hipStream_t stream) {
+    if (!trace) return SKGEMM_ERR_INVALID_ARG;
+    return conv_impl(plan, x, w, y, alpha, beta, workspace, ws_bytes, trace, trace_records, stream);
 }
 
 skgemm_status_t skgemm_grouped_table_size(skgemm_plan_t pl, size_t* bytes) {

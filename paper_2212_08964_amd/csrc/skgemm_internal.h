@@ -50,6 +50,17 @@ struct GroupEntry {
 };
 static_assert(sizeof(GroupEntry) == 128, "group table entry layout");
 
+// Implicit-GEMM convolution (the GEMM view of a 2-D convolution): input x
+// NHWC, filters KRSC, output NPQK.  GEMM rows m = (n P + p) Q + q, columns =
+// output channels, reduction kk = (r S + s) C + c; A[m][kk] is gathered from
+// x (zero outside the image), B is the filters as a column-major matrix with
+// leading dimension R S C, C the output as a row-major matrix.
+struct ConvArgs {
+    int32_t n, h, w, c;                 // input
+    int32_t p, q, r, s;                 // output size and filter window
+    int32_t pad_h, pad_w, str_h, str_w, dil_h, dil_w;
+};
+
 // Kernel arguments, passed by value.  Operands are described relative to the
 // reduction: an operand is "K-contiguous" when consecutive k are adjacent in
 // memory (row-major A, column-major B).
@@ -86,12 +97,15 @@ struct KArgs {
     // the previous problem's.
     int32_t batch, t1;
     int64_t stride_a, stride_b, stride_c;
+    ConvArgs conv;             // implicit-GEMM convolution kernels only
 };
 
 // Tile variants: 0 = the type's default tile, 1 = the small 16-bit / FP8 tile
 // (four waves) or the large FP64 tile, 2 = the small 16-bit tile on eight
 // waves.
-constexpr int kVariants = 3;
+// 3 and 4: the 256x256 and the four-wave 128x128 16-bit tiles with the
+// implicit-GEMM convolution gather for A.
+constexpr int kVariants = 5;
 
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
 int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, int variant, const KArgs& args, int grid,

@@ -73,12 +73,20 @@ template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.b
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
+// Implicit-GEMM convolution: the tiles of variants 0 and 1 with A gathered
+// from the NHWC input (CONV).
+template <> struct Cfg<DT_F16, 3> : Cfg<DT_F16, 0> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_BF16, 3> : Cfg<DT_BF16, 0> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_F16, 4> : Cfg<DT_F16, 1> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_BF16, 4> : Cfg<DT_BF16, 1> { static constexpr bool CONV = true; };
 
 // Optional tile traits: PRIO raises the waves' priority through the MFMA
 // section of each k-slab; WPE overrides the waves per SIMD the register
 // budget is sized for.
 template <class C, class = void> struct PrioOf { static constexpr bool value = false; };
 template <class C> struct PrioOf<C, std::void_t<decltype(C::PRIO)>> { static constexpr bool value = C::PRIO; };
+template <class C, class = void> struct ConvOf { static constexpr bool value = false; };
+template <class C> struct ConvOf<C, std::void_t<decltype(C::CONV)>> { static constexpr bool value = C::CONV; };
 
 template <int DT, int V>
 constexpr int kThreadsOf = 64 * Cfg<DT, V>::WM * Cfg<DT, V>::WN;
@@ -328,6 +336,75 @@ struct Slab {
     }
 };
 
+// The A slab of an implicit-GEMM convolution: R output pixels (GEMM rows) by
+// BK reduction indices, laid out in LDS as a K-contiguous slab.  Every slab
+// lies in one filter tap (r, s) and covers BK consecutive input channels
+// (the planner requires C to be a multiple of BK), so a lane's 16-byte chunk
+// is 8 consecutive channels of one input pixel: one direct-to-LDS load from
+// the pixel's address, or zero (offset out of the buffer range) when the
+// pixel lies in the padding or the row is past the last output pixel.
+template <int EB, int R, int BK, int THREADS>
+struct ConvSlab {
+    static constexpr int VE = 16 / EB;
+    static constexpr int ROWB = BK * EB;
+    static constexpr int BYTES = R * ROWB;
+    static constexpr int NW = THREADS / 64;
+    static constexpr int BLOCKS = BYTES / 1024;
+    static constexpr int PER_WAVE = BLOCKS / NW;
+    static_assert(ROWB == 128 && BLOCKS % NW == 0, "convolution slabs: 128-byte rows split evenly over the waves");
+    using S_ = Slab<EB, R, BK, true, THREADS>;   // the same chunk placement as a K-contiguous GEMM slab
+
+    int hb[PER_WAVE], wb[PER_WAVE], ib[PER_WAVE];   // per chunk: first input row / column of the window, image * H
+    const unsigned char* x;
+    uint32_t bytes;
+    int H, W, C, S, dil_h, dil_w;
+
+    // The chunk rows' output pixels (rows past dout are never inside the image).
+    __device__ __forceinline__ void init_conv(const ConvArgs& cv, const void* X, int o0, int dout, int tid) {
+        x = reinterpret_cast<const unsigned char*>(X);
+        H = uni(cv.h);
+        W = uni(cv.w);
+        C = uni(cv.c);
+        S = uni(cv.s);
+        dil_h = uni(cv.dil_h);
+        dil_w = uni(cv.dil_w);
+        const int P = uni(cv.p), Q = uni(cv.q), sh = uni(cv.str_h), sw = uni(cv.str_w);
+        const int ph = uni(cv.pad_h), pw = uni(cv.pad_w);
+        bytes = uint32_t(uni(int(int64_t(uni(cv.n)) * H * W * C * EB)));
+#pragma unroll
+        for (int j = 0; j < PER_WAVE; ++j) {
+            const int m = o0 + S_::chunk_row(j, tid);
+            const int pq = P * Q;
+            const int img = m / pq, rem = m - img * pq, pp = rem / Q, qq = rem - pp * Q;
+            const bool in = m < dout;
+            hb[j] = in ? pp * sh - ph : -(1 << 30);   // never inside the image
+            wb[j] = in ? qq * sw - pw : 0;
+            ib[j] = in ? img * H : 0;
+        }
+    }
+
+    // Slab of reduction indices [k0, k0 + BK): filter tap k0 / C, channels k0 mod C on.
+    template <bool EDGE>
+    __device__ __forceinline__ void issue(int, int k0, int, int, int, unsigned char* lds, int tid) const {
+        const int rs = k0 / C, c0 = k0 - rs * C;
+        const int r = rs / S, s = rs - r * S;
+        const i32x4 d = {uni(int(uint32_t(reinterpret_cast<uint64_t>(x)))),
+                         uni(int(uint32_t(reinterpret_cast<uint64_t>(x) >> 32) & 0xffffu)), int(bytes), kBufferFlags};
+        const int w = uni(tid >> 6);
+#pragma unroll
+        for (int j = 0; j < PER_WAVE; ++j) {
+            const int h = hb[j] + r * dil_h, ww = wb[j] + s * dil_w;
+            uint32_t off = 0x80000000u;
+            if (uint32_t(h) < uint32_t(H) && uint32_t(ww) < uint32_t(W))
+                off = uint32_t((((ib[j] + h) * W + ww) * C + c0 + S_::chunk_col(j, tid) * VE) * EB);
+            dma16(d, off, lds_addr(lds + (w + j * NW) * 1024));
+        }
+    }
+
+    // Convolution slabs have no ragged inner edge: nothing to fix.
+    __device__ __forceinline__ void fix_edge(int, int, int, int, int, unsigned char*, int) const {}
+};
+
 // ------------------------------------------------------------------ LDS fragment reads
 
 // 16 bytes = 8 k-values of one row of a K-contiguous slab, chunk q (0..7).
@@ -439,11 +516,12 @@ struct Prob {
     int M, N, K, tn, ipt;
     float alpha, beta;
     int raster;          // tile rows per raster group (1 = plain row-major)
+    ConvArgs conv;       // implicit-GEMM convolution (A gathered from its input), else unused
 };
 
 __device__ __forceinline__ Prob uniform(const Prob& p) {
     return Prob{unip(p.A), unip(p.B), unip(p.C), uni64(p.lda), uni64(p.ldb), uni64(p.ldc), uni(p.M), uni(p.N),
-                uni(p.K), uni(p.tn), uni(p.ipt), unif(p.alpha), unif(p.beta), uni(p.raster)};
+                uni(p.K), uni(p.tn), uni(p.ipt), unif(p.alpha), unif(p.beta), uni(p.raster), p.conv};
 }
 
 template <bool B, class T, class F> struct Pick { using type = T; };
@@ -467,7 +545,9 @@ struct Gemm {
     static constexpr int WM = C_::WM, WN = C_::WN, THREADS = 64 * WM * WN, NW = WM * WN;
     static constexpr int WTM = BM / WM, WTN = BN / WN;    // wave tile
     static constexpr int FM = WTM / 32, FN = WTN / 32;    // 32x32 MFMA blocks per wave
-    using SA = Slab<EB, BM, BK, AKC, THREADS>;
+    static constexpr bool CONV = ConvOf<C_>::value;
+    static_assert(!CONV || (AKC && BKC && (DT == DT_BF16 || DT == DT_F16)), "convolution: 16-bit, filters K-contiguous");
+    using SA = typename Pick<CONV, ConvSlab<EB, BM, BK, THREADS>, Slab<EB, BM, BK, AKC, THREADS>>::type;
     using SB = Slab<EB, BN, BK, BKC, THREADS>;
     static constexpr int STAGE = SA::BYTES + SB::BYTES;
     static constexpr int NS = C_::NS;
@@ -834,7 +914,8 @@ struct Gemm {
         tid = opaque(tid);
         SA sa;
         SB sb;
-        sa.init(a.A, a.lda, m0, a.M, kbeg, a.K, tid);
+        if constexpr (CONV) sa.init_conv(a.conv, a.A, m0, a.M, tid);
+        else sa.init(a.A, a.lda, m0, a.M, kbeg, a.K, tid);
         sb.init(a.B, a.ldb, n0, a.N, kbeg, a.K, tid);
         __syncthreads();   // LDS may still be in use (previous epilogue or loop)
         prologue(a, sa, sb, kbeg, kend, kedge, m0, n0, st, tid, std::make_integer_sequence<int, NS - 1>{});
@@ -1267,7 +1348,7 @@ struct Gemm {
     }
 
     static __device__ __forceinline__ Prob entry_prob(const GroupEntry& e, int raster) {
-        return Prob{e.A, e.B, e.C, e.lda, e.ldb, e.ldc, e.M, e.N, e.K, e.tn, e.ipt, e.alpha, e.beta, raster};
+        return Prob{e.A, e.B, e.C, e.lda, e.ldb, e.ldc, e.M, e.N, e.K, e.tn, e.ipt, e.alpha, e.beta, raster, ConvArgs{}};
     }
 
     // Logical workgroup index of hardware workgroup b.  Workgroups are handed
@@ -1338,7 +1419,7 @@ struct Gemm {
         int dp_tile = a.sk_tiles + wg;
         int seq = 0;
         const Prob single = {a.A, a.B, a.C, a.lda, a.ldb, a.ldc, a.M, a.N, a.K, a.tn, a.ipt, a.alpha, a.beta,
-                             a.raster};
+                             a.raster, a.conv};
         Acc acc;
         for (;;) {
             const bool sk_left = sk_it < sk_end, dp_left = dp_tile < a.t;

@@ -33,6 +33,7 @@ EXPORTED = [
     "skgemm_grouped_run_traced", "skgemm_quantize_workspace_size", "skgemm_quantize_e4m3",
     "skgemm_run_timed", "skgemm_realtime_hz", "skgemm_run_noalloc",
     "skgemm_batched_plan", "skgemm_batched_run", "skgemm_batched_run_traced",
+    "skgemm_conv_plan", "skgemm_conv_run", "skgemm_conv_run_traced",
 ]
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
@@ -55,6 +56,11 @@ class GroupArgs(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float)]
+
+
+class ConvDesc(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("n", "h", "w", "c", "k", "r", "s", "pad_h", "pad_w", "stride_h",
+                                               "stride_w", "dil_h", "dil_w")]
 
 
 class SkgemmError(RuntimeError):
@@ -99,6 +105,10 @@ def lib():
                                                         ctypes.c_float, ctypes.c_float, vp, vp, vp, sz, vp, sz, vp]
                 L.skgemm_run_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.c_float, ctypes.c_float,
                                                  vp, vp, vp]
+                L.skgemm_conv_plan.argtypes = [P(vp), P(ConvDesc), ctypes.c_int, ctypes.c_int, P(Options)]
+                L.skgemm_conv_run.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, sz, vp]
+                L.skgemm_conv_run_traced.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, sz, vp,
+                                                     sz, vp]
                 L.skgemm_plan_info.argtypes = [vp, P(i64), i32]
                 L.skgemm_model_constants.argtypes = [vp, P(ctypes.c_double)]
                 L.skgemm_schedule.argtypes = [vp, vp, sz, P(sz)]
@@ -270,6 +280,36 @@ class BatchedPlan(Plan):
                                                    int(ldc), int(sc), float(alpha), float(beta), scale_a, scale_b,
                                                    workspace, int(ws_bytes), trace, int(trace_records), stream),
                    "skgemm_batched_run_traced")
+
+
+class ConvPlan(Plan):
+    """Owns one implicit-GEMM convolution skgemm_plan_t (x NHWC, w KRSC, y NPQK)."""
+
+    def __init__(self, n, h, w, c, k, r, s, pad=(0, 0), stride=(1, 1), dilation=(1, 1), ta=BF16, tc=None,
+                 policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto", spin_limit=0):
+        self._h = ctypes.c_void_p()
+        o = _options(policy, force_g, hybrid_min_waves, num_cus, occupancy, tile, raster_rows, xcds, share, fixup,
+                     spin_limit)
+        d = ConvDesc(int(n), int(h), int(w), int(c), int(k), int(r), int(s), int(pad[0]), int(pad[1]),
+                     int(stride[0]), int(stride[1]), int(dilation[0]), int(dilation[1]))
+        tc = ta if tc is None else tc
+        _check(lib().skgemm_conv_plan(ctypes.byref(self._h), ctypes.byref(d), ta, tc, ctypes.byref(o)),
+               "skgemm_conv_plan")
+        self.desc = d
+        self.ta, self.tc = ta, tc
+        i = self.info()
+        self.M, self.N, self.K = i["M"], i["N"], i["K"]
+
+    def conv_run(self, x, w, y, alpha=1.0, beta=0.0, workspace=None, ws_bytes=0, stream=None, trace=None,
+                 trace_records=0):
+        if trace is None:
+            _check(lib().skgemm_conv_run(self._h, x, w, y, float(alpha), float(beta), workspace, int(ws_bytes),
+                                         stream), "skgemm_conv_run")
+        else:
+            _check(lib().skgemm_conv_run_traced(self._h, x, w, y, float(alpha), float(beta), workspace,
+                                                int(ws_bytes), trace, int(trace_records), stream),
+                   "skgemm_conv_run_traced")
 
 
 def _options(policy, force_g, hybrid_min_waves, num_cus, occupancy, tile, raster_rows, xcds, share, fixup,
@@ -712,6 +752,59 @@ def batched_matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, polic
                      workspace=ws.data_ptr() if ws is not None else None, ws_bytes=nws, stream=stream,
                      trace=trace.data_ptr() if trace is not None else None,
                      trace_records=trace.numel() // 8 if trace is not None else 0)
+    if ws is not None and _check_runs:
+        check_workspace(ws, stream)
+    return out
+
+
+_cplan_cache = {}
+
+
+def conv2d(x, w, out=None, *, padding=(0, 0), stride=(1, 1), dilation=(1, 1), out_dtype=None, alpha=1.0,
+           beta=0.0, policy="auto", force_g=0, hybrid_min_waves=2, tile=None, trace=None):
+    """y = alpha * conv2d(x, w) + beta * y as one Stream-K implicit-GEMM launch.
+
+    x is (N, H, W, C) and w is (K, R, S, C), both channels-last and contiguous,
+    in bfloat16 or float16 with C a multiple of 64; the result is (N, P, Q, K)
+    (cross-correlation, zero padding), in the input type or float32."""
+    import torch
+    dts = _torch_dtypes()
+    if x.dim() != 4 or w.dim() != 4 or x.shape[3] != w.shape[3]:
+        raise ValueError("conv2d needs x (N, H, W, C) and w (K, R, S, C)")
+    if x.dtype != w.dtype or x.dtype not in (torch.bfloat16, torch.float16):
+        raise ValueError(f"unsupported input dtypes {x.dtype}, {w.dtype}")
+    if not x.is_contiguous() or not w.is_contiguous():
+        raise ValueError("conv2d needs contiguous channels-last x and w")
+    pad, std, dil = tuple(padding), tuple(stride), tuple(dilation)
+    n, h, wd, c = x.shape
+    k, r, s, _ = w.shape
+    if out_dtype is None:
+        out_dtype = out.dtype if out is not None else x.dtype
+    key = (n, h, wd, c, k, r, s, pad, std, dil, dts[x.dtype], dts[out_dtype], policy, force_g, hybrid_min_waves,
+           tuple(tile) if tile else None)
+    plan = _cplan_cache.get(key)
+    if plan is None:
+        plan = ConvPlan(n, h, wd, c, k, r, s, pad, std, dil, dts[x.dtype], dts[out_dtype], policy=policy,
+                        force_g=force_g, hybrid_min_waves=hybrid_min_waves, tile=tile)
+        if len(_cplan_cache) > 256:
+            _cplan_cache.clear()
+        _cplan_cache[key] = plan
+    P = (h + 2 * pad[0] - dil[0] * (r - 1) - 1) // std[0] + 1
+    Q = (wd + 2 * pad[1] - dil[1] * (s - 1) - 1) // std[1] + 1
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty((n, P, Q, k), dtype=out_dtype, device=x.device)
+    elif tuple(out.shape) != (n, P, Q, k) or not out.is_contiguous() or out.dtype != out_dtype:
+        raise ValueError(f"out must be a contiguous ({n}, {P}, {Q}, {k}) {out_dtype} tensor")
+    nws = plan.workspace_size()
+    stream = torch.cuda.current_stream(x.device).cuda_stream
+    ws = workspace(nws, x.device, stream) if nws else None
+    plan.conv_run(x.data_ptr() if x.numel() else None, w.data_ptr() if w.numel() else None,
+                  out.data_ptr() if out.numel() else None, alpha, beta,
+                  workspace=ws.data_ptr() if ws is not None else None, ws_bytes=nws, stream=stream,
+                  trace=trace.data_ptr() if trace is not None else None,
+                  trace_records=trace.numel() // 8 if trace is not None else 0)
     if ws is not None and _check_runs:
         check_workspace(ws, stream)
     return out

@@ -376,3 +376,87 @@ def test_batched_argument_errors():
     # a batched plan needs the batched run (strides), and a single plan runs through either
     assert L.skgemm_run(p.handle, fake, 64, fake, 64, fake, 64, 1.0, 0.0, None, None, None, 0,
                         None) == sk.ERR_INVALID_ARG
+
+
+CONV_CASES = [
+    # n, h, w, c, k, r, s, pad, stride, dilation
+    (2, 14, 14, 64, 96, 3, 3, (1, 1), (1, 1), (1, 1)),
+    (3, 17, 11, 128, 200, 3, 3, (1, 1), (2, 2), (1, 1)),
+    (1, 9, 13, 64, 64, 3, 3, (2, 2), (1, 1), (2, 2)),
+    (4, 7, 7, 256, 130, 1, 1, (0, 0), (1, 1), (1, 1)),
+    (2, 23, 23, 64, 64, 7, 7, (3, 3), (2, 2), (1, 1)),
+    (1, 5, 8, 192, 33, 2, 3, (0, 1), (1, 2), (1, 1)),
+]
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+@pytest.mark.parametrize("policy", ["auto", "paper", "sk", "dp"])
+def test_conv_plan_is_the_gemm_view(case, policy):
+    """A convolution plan is the plan of its GEMM view (M = n P Q, N = k,
+    K = r s c; A K-contiguous, the filters a column-major B, C row-major) on
+    the tile of the same size: same resolution, same schedule, and that
+    schedule is the oracle enumerator's."""
+    from oracle import conv as oc
+    sk = _lib()
+    n, h, w, c, k, r, s, pad, std, dil = case
+    P, Q = oc.out_size(h, w, r, s, pad[0], pad[1], std[0], std[1], dil[0], dil[1])
+    for tile, (cus, occ) in itertools.product([(256, 256, 64), (128, 128, 64, 4)], [(256, 1), (64, 2)]):
+        cp = sk.ConvPlan(n, h, w, c, k, r, s, pad, std, dil, ta=sk.BF16, policy=policy, tile=tile, num_cus=cus,
+                         occupancy=occ)
+        gp = sk.Plan(n * P * Q, k, r * s * c, sk.ROW_MAJOR, sk.COL_MAJOR, sk.ROW_MAJOR, ta=sk.BF16, policy=policy,
+                     tile=tile, num_cus=cus, occupancy=occ)
+        ci, gi = cp.info(), gp.info()
+        assert (ci["M"], ci["N"], ci["K"]) == (n * P * Q, k, r * s * c)
+        assert ci == gi, (case, tile)
+        assert cp.model_constants() == gp.model_constants()
+        assert cp.schedule() == gp.schedule()
+        ref = oracle_plan_for(ci, cp.model_constants(), policy)
+        assert records_to_schedule(cp.schedule(), ci["grid"]) == S.enumerate_schedule(ref)
+
+
+def test_conv_chooses_between_its_two_tiles():
+    sk = _lib()
+    big = sk.ConvPlan(32, 56, 56, 64, 256, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
+    small = sk.ConvPlan(1, 7, 7, 64, 64, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
+    assert big["tile"] in {(256, 256, 64, 8), (128, 128, 64, 4)}
+    assert small["tile"] == (128, 128, 64, 4)
+
+
+def test_conv_argument_errors():
+    sk = _lib()
+    L = sk.lib()
+    o = sk.default_options()
+    o.num_cus, o.occupancy = 256, 1
+    h = ctypes.c_void_p()
+
+    def plan(*f, ta=sk.BF16, tc=sk.BF16):
+        return L.skgemm_conv_plan(ctypes.byref(h), ctypes.byref(sk.ConvDesc(*f)), ta, tc, ctypes.byref(o))
+
+    ok = (2, 8, 8, 64, 32, 3, 3, 1, 1, 1, 1, 1, 1)
+    assert plan(*ok) == sk.OK
+    L.skgemm_plan_destroy(h)
+    assert plan(2, 8, 8, 96, 32, 3, 3, 1, 1, 1, 1, 1, 1) == sk.ERR_UNSUPPORTED      # c not a multiple of 64
+    assert plan(*ok, ta=sk.F32, tc=sk.F32) == sk.ERR_UNSUPPORTED
+    assert plan(*ok, ta=sk.F8E4M3, tc=sk.F32) == sk.ERR_UNSUPPORTED
+    assert plan(2, 8, 8, 64, 32, 3, 3, 1, 1, 1, 1, 1, 1) == sk.OK
+    L.skgemm_plan_destroy(h)
+    assert plan(2, 2, 8, 64, 32, 3, 3, 0, 0, 1, 1, 1, 1) == sk.ERR_INVALID_ARG      # window taller than the image
+    assert plan(2, 8, 8, 64, 32, 3, 3, 1, 1, 0, 1, 1, 1) == sk.ERR_INVALID_ARG      # stride 0
+    assert plan(2, 8, 8, 64, 32, 3, 3, -1, 1, 1, 1, 1, 1) == sk.ERR_INVALID_ARG     # negative padding
+    assert plan(2, 8, 8, 64, 32, 3, 3, 1, 1, 1, 1, 0, 1) == sk.ERR_INVALID_ARG      # dilation 0
+    assert plan(-1, 8, 8, 64, 32, 3, 3, 1, 1, 1, 1, 1, 1) == sk.ERR_INVALID_ARG
+    # the input must be addressable with 32-bit offsets
+    assert plan(1 << 15, 128, 128, 64, 32, 3, 3, 1, 1, 1, 1, 1, 1) == sk.ERR_UNSUPPORTED
+    assert L.skgemm_conv_plan(ctypes.byref(h), None, sk.BF16, sk.BF16, ctypes.byref(o)) == sk.ERR_INVALID_ARG
+    # a convolution plan runs only through the convolution entry points, and back
+    cp = sk.ConvPlan(2, 8, 8, 64, 32, 3, 3, (1, 1), num_cus=256, occupancy=1)
+    gp = sk.Plan(128, 32, 576, sk.ROW_MAJOR, sk.COL_MAJOR, sk.ROW_MAJOR, ta=sk.BF16, num_cus=256, occupancy=1)
+    fake = 1 << 40
+    assert L.skgemm_run(cp.handle, fake, 576, fake, 576, fake, 32, 1.0, 0.0, None, None, None, 0,
+                        None) == sk.ERR_INVALID_ARG
+    assert L.skgemm_conv_run(gp.handle, fake, fake, fake, 1.0, 0.0, None, 0, None) == sk.ERR_INVALID_ARG
+    assert L.skgemm_conv_run(cp.handle, None, fake, fake, 1.0, 0.0, None, 0, None) == sk.ERR_INVALID_ARG
+    # an empty batch is a no-op
+    z = sk.ConvPlan(0, 8, 8, 64, 32, 3, 3, (1, 1), num_cus=256, occupancy=1)
+    assert z.info()["M"] == 0
+    assert L.skgemm_conv_run(z.handle, None, None, None, 1.0, 0.0, None, 0, None) == sk.OK
