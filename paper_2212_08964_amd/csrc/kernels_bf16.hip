@@ -1,37 +1,11 @@
-// Instantiations of the Stream-K GEMM kernel for one input type (one
-// translation unit per type so they compile in parallel).
-#include "skgemm_kernel.hpp"
+// Lean instantiations (plain GEMMs) of the Stream-K GEMM kernel for one
+// input type, and its workgroup sizes.
+#include "kernel_tables.hpp"
 
 namespace skg {
 
-const void* kernel_fn_bf16(bool akc, bool bkc, int v) {
-    if (v == 0) {
-        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 0>)
-                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false, 0>);
-        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 0>)
-                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 0>);
-    }
-    if (v == 1) {
-        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 1>)
-                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false, 1>);
-        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 1>)
-                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 1>);
-    }
-    if (v == 2) {
-        if (akc) return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 2>)
-                            : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, false, 2>);
-        return bkc ? reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, true, 2>)
-                   : reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, false, false, 2>);
-    }
-    // implicit-GEMM convolution: A gathered, filters K-contiguous
-    if (v == 3 && akc && bkc) return reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 3>);
-    if (v == 4 && akc && bkc) return reinterpret_cast<const void*>(&skgemm_kernel<DT_BF16, true, true, 4>);
-    return nullptr;
-}
+const void* kernel_fn_bf16(bool akc, bool bkc, int v) { return kernel_table<DT_BF16, false>(akc, bkc, v); }
 
-int kernel_threads_bf16(int v) {
-    return v == 0 ? kThreadsOf<DT_BF16, 0> : v == 1 ? kThreadsOf<DT_BF16, 1> : v == 2 ? kThreadsOf<DT_BF16, 2>
-           : v == 3 ? kThreadsOf<DT_BF16, 3> : v == 4 ? kThreadsOf<DT_BF16, 4> : 0;
-}
+int kernel_threads_bf16(int v) { return v == 0 ? kThreadsOf<DT_BF16, 0> : v == 1 ? kThreadsOf<DT_BF16, 1> : v == 2 ? kThreadsOf<DT_BF16, 2> : v == 3 ? kThreadsOf<DT_BF16, 3> : v == 4 ? kThreadsOf<DT_BF16, 4> : 0; }
 
 }  // namespace skg

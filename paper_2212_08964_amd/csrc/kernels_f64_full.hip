@@ -1,0 +1,9 @@
+// Full instantiations (group table, batch, trace, timestamps) of the
+// Stream-K GEMM kernel for one input type.
+#include "kernel_tables.hpp"
+
+namespace skg {
+
+const void* kernel_fn_f64_full(bool akc, bool bkc, int v) { return kernel_table<DT_F64, true>(akc, bkc, v); }
+
+}  // namespace skg

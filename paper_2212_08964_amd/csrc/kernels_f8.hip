@@ -1,15 +1,10 @@
-// Instantiations of the Stream-K GEMM kernel for one input type (one
-// translation unit per type so they compile in parallel).
-#include "skgemm_kernel.hpp"
+// Lean instantiations (plain GEMMs) of the Stream-K GEMM kernel for one
+// input type, and its workgroup sizes.
+#include "kernel_tables.hpp"
 
 namespace skg {
 
-const void* kernel_fn_f8(bool akc, bool bkc, int v) {
-    if (!akc || !bkc) return nullptr;
-    if (v == 0) return reinterpret_cast<const void*>(&skgemm_kernel<DT_F8, true, true, 0>);
-    if (v == 1) return reinterpret_cast<const void*>(&skgemm_kernel<DT_F8, true, true, 1>);
-    return nullptr;
-}
+const void* kernel_fn_f8(bool akc, bool bkc, int v) { return kernel_table<DT_F8, false>(akc, bkc, v); }
 
 int kernel_threads_f8(int v) { return v == 0 ? kThreadsOf<DT_F8, 0> : v == 1 ? kThreadsOf<DT_F8, 1> : 0; }
 
