@@ -425,6 +425,38 @@ def suite(args):
               "three_gemms_ms": round(us_k / 1e3, 4), "three_gemms_tflops": round(fl / us_k / 1e6, 1)})
 
 
+    # implicit-GEMM convolution: the 3x3 convolutions of ResNet-50's four stages and one 1x1
+    # projection, batch 32, channels-last bf16; torch's convolution (MIOpen) on the same
+    # channels-last tensors for context
+    for (n, h, c, k, r, std) in [(32, 56, 64, 64, 3, 1), (32, 28, 128, 128, 3, 1), (32, 14, 256, 256, 3, 1),
+                                 (32, 7, 512, 512, 3, 1), (32, 14, 1024, 256, 1, 1)]:
+        pad = r // 2
+        x = torch.randn((n, h, h, c), generator=gen, device=dev).to(torch.bfloat16)
+        f = (torch.randn((k, r, r, c), generator=gen, device=dev) / (r * r * c) ** 0.5).to(torch.bfloat16)
+        P = (h + 2 * pad - r) // std + 1
+        y = torch.empty((n, P, P, k), device=dev, dtype=torch.bfloat16)
+        fl = 2.0 * n * P * P * k * r * r * c
+        ops = [lambda pol=pol: sk.conv2d(x, f, y, padding=(pad, pad), stride=(std, std), policy=pol)
+               for pol in ("auto", "dp")]
+        times = _best_us_alternating(ops, reps_for(fl))
+        plan = sk.ConvPlan(n, h, h, c, k, r, r, (pad, pad), (std, std), ta=sk.BF16).info()
+        row = {"workload": f"conv bf16 n{n} {h}x{h} c{c} k{k} {r}x{r} s{std}", "dtype": "bf16",
+               "gemm_view": [plan["M"], plan["N"], plan["K"]],
+               "auto_plan": {k_: plan[k_] for k_ in ("policy_name", "g_sk", "BM", "BN", "BK", "t")}}
+        for pol, us in zip(("auto", "dp"), times):
+            row[pol + "_us"] = round(us, 2)
+            row[pol + "_tflops"] = round(fl / us / 1e6, 1)
+        xt = x.permute(0, 3, 1, 2)              # NCHW view, channels-last memory
+        ft = f.permute(0, 3, 1, 2)
+        try:
+            us_t = _best_us(lambda: torch.nn.functional.conv2d(xt, ft, padding=pad, stride=std), reps_for(fl))
+            row["torch_conv2d_us"] = round(us_t, 2)
+            row["torch_conv2d_tflops"] = round(fl / us_t / 1e6, 1)
+        except RuntimeError as e:           # a convolution library without this case
+            row["torch_conv2d_error"] = str(e)[:120]
+        emit(row)
+
+
 def profile_shape(args):
     """One BF16 GEMM (A, B, C row-major, N(0,1) inputs, automatic policy) run
     --profile-steps times back to back, for rocprofv3 kernel traces and
