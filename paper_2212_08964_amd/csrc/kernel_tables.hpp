@@ -21,6 +21,14 @@ const void* any_layout(bool akc, bool bkc) {
     return bkc ? kernel_ptr<DT, false, true, V, FULL>() : kernel_ptr<DT, false, false, V, FULL>();
 }
 
+// K-contiguous A, either B (the skinny tile: a 64-row MN-contiguous slab has
+// rows shorter than the slab layout's minimum)
+template <int DT, int V, bool FULL>
+const void* akc_only(bool akc, bool bkc) {
+    if (!akc) return nullptr;
+    return bkc ? kernel_ptr<DT, true, true, V, FULL>() : kernel_ptr<DT, true, false, V, FULL>();
+}
+
 // K-contiguous A and B only (FP8; the convolution kernels)
 template <int DT, int V, bool FULL>
 const void* kc_only(bool akc, bool bkc) {
@@ -36,6 +44,7 @@ const void* kernel_table(bool akc, bool bkc, int v) {
             case 2: return any_layout<DT, 2, FULL>(akc, bkc);
             case 3: return kc_only<DT, 3, FULL>(akc, bkc);    // implicit-GEMM convolution
             case 4: return kc_only<DT, 4, FULL>(akc, bkc);
+            case 5: return akc_only<DT, 5, FULL>(akc, bkc);    // skinny tile
             default: return nullptr;
         }
     } else if constexpr (DT == DT_F8) {

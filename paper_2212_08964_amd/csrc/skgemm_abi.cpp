@@ -101,6 +101,7 @@ TileCfg tile_for(int dt, int v) {
     if ((v == 1 || v == 2) && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 3 && (dt == DT_BF16 || dt == DT_F16)) return kTile16;     // convolution
     if (v == 4 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
+    if (v == 5 && (dt == DT_BF16 || dt == DT_F16)) return kTile16K;     // skinny
     if (v == 1 && dt == DT_F8) return kTileF8S;
     if (v == 1 && dt == DT_F64) return kTileF64L;
     return TileCfg{0, 0, 0};
@@ -126,6 +127,7 @@ void model_for(int dt, int v, double* m) {
     // the convolution variants take the constants of the GEMM tile of their shape
     if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
     if (v == 1 || v == 4) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
+    if (v == 5) { m[0] = 5.99; m[1] = 1.49; m[2] = 0.703; m[3] = 0.570; m[4] = 1.009; return; }
     m[0] = 9.88; m[1] = 2.78; m[2] = 1.351; m[3] = 0.941; m[4] = 1.693;
 }
 
@@ -583,7 +585,14 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
     skgemm_plan_s* cand[kVariants] = {};
     skgemm_status_t last = SKGEMM_ERR_UNSUPPORTED;
     for (int v = 0; v < kVariants; ++v) {
-        if ((v >= 3) != base->conv) continue;     // the convolution kernels are variants 3 and 4
+        if (is_conv_variant(v) != base->conv) continue;     // the convolution kernels are variants 3 and 4
+        // the skinny tile only where every launched problem has at most its
+        // 64 rows (unless the options name it)
+        if (v == 5 && !named) {
+            int64_t rows = 0;
+            for (int j = 0; j < G; ++j) rows = std::max<int64_t>(rows, base->swapped ? N[j] : M[j]);
+            if (rows > kTile16K.bm) continue;
+        }
         const TileCfg tc_ = tile_for(base->dtype, v);
         if (!tc_.bm || !kernel_exists(base->dtype, base->akc, base->bkc, v)) continue;
         if (named && ((o.tile_m && o.tile_m != tc_.bm) || (o.tile_n && o.tile_n != tc_.bn) ||

@@ -73,6 +73,11 @@ template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.b
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
+// Skinny 16-bit tile for problems of at most 64 rows: four waves side by side
+// over 256 columns (64x64 each), so a short A panel is padded to 64 rows, not
+// 128 or 256.
+template <> struct Cfg<DT_F16, 5> { static constexpr int EB = 2, BM = kTile16K.bm, BN = kTile16K.bn, BK = kTile16K.bk, WM = 1, WN = 4, NS = kTile16K.ns; };
+template <> struct Cfg<DT_BF16, 5> { static constexpr int EB = 2, BM = kTile16K.bm, BN = kTile16K.bn, BK = kTile16K.bk, WM = 1, WN = 4, NS = kTile16K.ns; };
 // Implicit-GEMM convolution: the tiles of variants 0 and 1 with A gathered
 // from the NHWC input (CONV).
 template <> struct Cfg<DT_F16, 3> : Cfg<DT_F16, 0> { static constexpr bool CONV = true; };

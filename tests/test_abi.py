@@ -65,7 +65,7 @@ def test_plan_argument_errors():
     assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
                          ctypes.byref(o)) == sk.ERR_INVALID_ARG
     o.share = 0
-    o.tile_m = 64
+    o.tile_m = 32
     o.force_g = 0
     assert L.skgemm_plan(ctypes.byref(h), 512, 512, 4096, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
                          ctypes.byref(o)) == sk.ERR_UNSUPPORTED
@@ -460,3 +460,25 @@ def test_conv_argument_errors():
     z = sk.ConvPlan(0, 8, 8, 64, 32, 3, 3, (1, 1), num_cus=256, occupancy=1)
     assert z.info()["M"] == 0
     assert L.skgemm_conv_run(z.handle, None, None, None, 1.0, 0.0, None, 0, None) == sk.OK
+
+
+def test_skinny_tile_only_for_short_problems():
+    """The skinny 64x256x64 tile is a candidate only where every launched
+    problem has at most 64 rows (and A is K-contiguous), unless the options
+    name it; its plans follow the enumerator like every other tile's."""
+    sk = _lib()
+    for (M, N, K), la, lc in itertools.product([(1, 1000, 3000), (16, 8192, 8192), (64, 4096, 2048), (65, 4096, 2048),
+                                                (300, 200, 100), (128, 8192, 8192)],
+                                               [sk.ROW_MAJOR, sk.COL_MAJOR], [sk.ROW_MAJOR, sk.COL_MAJOR]):
+        p = sk.Plan(M, N, K, la=la, lc=lc, ta=sk.BF16, num_cus=256, occupancy=2)
+        info = p.info()
+        rows = N if lc == sk.COL_MAJOR else M
+        if info["tile"] == (64, 256, 64, 4):
+            assert rows <= 64 and info["a_kcontig"], (M, N, K, la, lc)
+        ref = oracle_plan_for(info, p.model_constants(), "auto")
+        assert records_to_schedule(p.schedule(), info["grid"]) == S.enumerate_schedule(ref)
+    named = sk.Plan(300, 200, 100, ta=sk.BF16, num_cus=256, occupancy=2, tile=(64, 256, 64))
+    assert named.info()["tile"] == (64, 256, 64, 4)
+    with pytest.raises(sk.SkgemmError) as e:      # no skinny kernel reads an MN-contiguous A
+        sk.Plan(16, 300, 200, la=sk.COL_MAJOR, ta=sk.BF16, num_cus=256, occupancy=2, tile=(64, 256, 64))
+    assert e.value.status == sk.ERR_UNSUPPORTED
