@@ -26,7 +26,8 @@ def model_terms(t, ipt, g):
 
 def _launcher(sk, plan, A, B, C, ws, nws):
     """Pre-resolved C-ABI call on the current stream (argument marshalling done once), so
-    that back-to-back launches are not limited by the host."""
+    that back-to-back launches are not limited by the host.  B is K x N row-major, or
+    N x K row-major storage of a column-major K x N operand (plan.lb)."""
     import ctypes
     import torch
     L = sk.lib()
@@ -50,7 +51,13 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     from . import skgemm as sk
     tdt = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32, "f64": torch.float64}[dtype]
     cdt = {"bf16": sk.BF16, "f16": sk.F16, "f32": sk.F32, "f64": sk.F64}[dtype]
-    probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
+    # a tile with no kernel for a row-major B (the tall one) is measured on a column-major B
+    lb = sk.ROW_MAJOR
+    try:
+        probe = sk.Plan(256, 256, 64, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
+    except sk.SkgemmError:
+        lb = sk.COL_MAJOR
+        probe = sk.Plan(256, 256, 64, lb=lb, ta=cdt, tc=cdt, policy="dp", tile=tile).info()
     BM, BN, BK, p = probe["BM"], probe["BN"], probe["BK"], probe["p"]
     full_tile = probe["tile"]        # (BM, BN, BK, waves): pins this exact configuration
     rows, ys, grids = [], [], []
@@ -62,14 +69,14 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
             tn = t // tm
             M, N, K = BM * tm, BN * tn, BK * ipt
             A = torch.randn(M, K, device="cuda").to(tdt)
-            B = torch.randn(K, N, device="cuda").to(tdt)
+            B = torch.randn((K, N) if lb == sk.ROW_MAJOR else (N, K), device="cuda").to(tdt)
             C = torch.empty(M, N, device="cuda", dtype=tdt)
             # grids that split every tile into s equal parts (s divides ipt): the
             # shares then start at the same k-offset in every tile, the form the
             # planner's automatic policy launches
             gs = [t * s for s in range(1, ipt + 1) if ipt % s == 0 and t * s <= p]
             for g in gs:
-                plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="sk", force_g=g, tile=full_tile)
+                plan = sk.Plan(M, N, K, lb=lb, ta=cdt, tc=cdt, policy="sk", force_g=g, tile=full_tile)
                 nws = plan.workspace_size()
                 ws = torch.zeros(max(nws, 256), dtype=torch.uint8, device="cuda")
                 launch = _launcher(sk, plan, A, B, C, ws if nws else None, nws)
@@ -109,9 +116,9 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
         tn = t // tm
         M, N, K = BM * tm, BN * tn, BK * ipt
         A = torch.randn(M, K, device="cuda").to(tdt)
-        B = torch.randn(K, N, device="cuda").to(tdt)
+        B = torch.randn((K, N) if lb == sk.ROW_MAJOR else (N, K), device="cuda").to(tdt)
         C = torch.empty(M, N, device="cuda", dtype=tdt)
-        plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="dp", tile=full_tile)
+        plan = sk.Plan(M, N, K, lb=lb, ta=cdt, tc=cdt, policy="dp", tile=full_tile)
         launch = _launcher(sk, plan, A, B, C, None, 0)
         launch()
         torch.cuda.synchronize()

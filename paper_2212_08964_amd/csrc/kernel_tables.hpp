@@ -29,6 +29,14 @@ const void* akc_only(bool akc, bool bkc) {
     return bkc ? kernel_ptr<DT, true, true, V, FULL>() : kernel_ptr<DT, true, false, V, FULL>();
 }
 
+// either A, K-contiguous B (the tall tile: a 64-column MN-contiguous slab has
+// rows shorter than the slab layout's minimum)
+template <int DT, int V, bool FULL>
+const void* bkc_only(bool akc, bool bkc) {
+    if (!bkc) return nullptr;
+    return akc ? kernel_ptr<DT, true, true, V, FULL>() : kernel_ptr<DT, false, true, V, FULL>();
+}
+
 // K-contiguous A and B only (FP8; the convolution kernels)
 template <int DT, int V, bool FULL>
 const void* kc_only(bool akc, bool bkc) {
@@ -45,6 +53,8 @@ const void* kernel_table(bool akc, bool bkc, int v) {
             case 3: return kc_only<DT, 3, FULL>(akc, bkc);    // implicit-GEMM convolution
             case 4: return kc_only<DT, 4, FULL>(akc, bkc);
             case 5: return akc_only<DT, 5, FULL>(akc, bkc);    // skinny tile
+            case 6: return bkc_only<DT, 6, FULL>(akc, bkc);    // tall tile
+            case 7: return kc_only<DT, 7, FULL>(akc, bkc);     // tall tile, convolution
             default: return nullptr;
         }
     } else if constexpr (DT == DT_F8) {

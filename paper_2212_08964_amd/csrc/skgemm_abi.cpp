@@ -102,6 +102,7 @@ TileCfg tile_for(int dt, int v) {
     if (v == 3 && (dt == DT_BF16 || dt == DT_F16)) return kTile16;     // convolution
     if (v == 4 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 5 && (dt == DT_BF16 || dt == DT_F16)) return kTile16K;     // skinny
+    if ((v == 6 || v == 7) && (dt == DT_BF16 || dt == DT_F16)) return kTile16T;     // tall
     if (v == 1 && dt == DT_F8) return kTileF8S;
     if (v == 1 && dt == DT_F64) return kTileF64L;
     return TileCfg{0, 0, 0};
@@ -128,6 +129,7 @@ void model_for(int dt, int v, double* m) {
     if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
     if (v == 1 || v == 4) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
     if (v == 5) { m[0] = 5.99; m[1] = 1.49; m[2] = 0.703; m[3] = 0.570; m[4] = 1.009; return; }
+    if (v == 6 || v == 7) { m[0] = 5.28; m[1] = 1.87; m[2] = 0.716; m[3] = 0.551; m[4] = 1.009; return; }
     m[0] = 9.88; m[1] = 2.78; m[2] = 1.351; m[3] = 0.941; m[4] = 1.693;
 }
 
@@ -592,6 +594,13 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
             int64_t rows = 0;
             for (int j = 0; j < G; ++j) rows = std::max<int64_t>(rows, base->swapped ? N[j] : M[j]);
             if (rows > kTile16K.bm) continue;
+        }
+        // the tall tile likewise where every launched problem has at most its
+        // 64 columns
+        if ((v == 6 || v == 7) && !named) {
+            int64_t cols = 0;
+            for (int j = 0; j < G; ++j) cols = std::max<int64_t>(cols, base->swapped ? M[j] : N[j]);
+            if (cols > kTile16T.bn) continue;
         }
         const TileCfg tc_ = tile_for(base->dtype, v);
         if (!tc_.bm || !kernel_exists(base->dtype, base->akc, base->bkc, v)) continue;

@@ -31,6 +31,7 @@ constexpr TileCfg kTileF32 = {128, 128, 32, 2};
 constexpr TileCfg kTile16 = {256, 256, 64, 2};    // bf16 and f16
 constexpr TileCfg kTile16S = {128, 128, 64, 2};   // bf16 and f16, small-tile variant
 constexpr TileCfg kTile16K = {64, 256, 64, 2};    // bf16 and f16, skinny-M variant (M <= 64)
+constexpr TileCfg kTile16T = {256, 64, 64, 2};    // bf16 and f16, skinny-N variant (N <= 64)
 constexpr TileCfg kTileF8 = {256, 256, 128, 2};
 constexpr TileCfg kTileF8S = {128, 128, 128, 2};   // fp8, small-tile variant
 constexpr TileCfg kTileF64 = {64, 64, 16, 2};
@@ -106,9 +107,11 @@ struct KArgs {
 // waves.
 // 3 and 4: the 256x256 and the four-wave 128x128 16-bit tiles with the
 // implicit-GEMM convolution gather for A.  5: the skinny 64x256 16-bit tile
-// (four waves side by side) for problems of at most 64 rows.
-constexpr int kVariants = 6;
-constexpr bool is_conv_variant(int v) { return v == 3 || v == 4; }
+// (four waves side by side) for problems of at most 64 rows; 6: the 256x64
+// tile (four waves stacked) for problems of at most 64 columns, and 7 the
+// same with the convolution gather (at most 64 output channels).
+constexpr int kVariants = 8;
+constexpr bool is_conv_variant(int v) { return v == 3 || v == 4 || v == 7; }
 
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
 int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, int variant, const KArgs& args, int grid,

@@ -78,12 +78,18 @@ template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.
 // 128 or 256.
 template <> struct Cfg<DT_F16, 5> { static constexpr int EB = 2, BM = kTile16K.bm, BN = kTile16K.bn, BK = kTile16K.bk, WM = 1, WN = 4, NS = kTile16K.ns; };
 template <> struct Cfg<DT_BF16, 5> { static constexpr int EB = 2, BM = kTile16K.bm, BN = kTile16K.bn, BK = kTile16K.bk, WM = 1, WN = 4, NS = kTile16K.ns; };
+// Its transpose for problems of at most 64 columns (and convolutions with at
+// most 64 output channels): four waves stacked over 256 rows.
+template <> struct Cfg<DT_F16, 6> { static constexpr int EB = 2, BM = kTile16T.bm, BN = kTile16T.bn, BK = kTile16T.bk, WM = 4, WN = 1, NS = kTile16T.ns; };
+template <> struct Cfg<DT_BF16, 6> { static constexpr int EB = 2, BM = kTile16T.bm, BN = kTile16T.bn, BK = kTile16T.bk, WM = 4, WN = 1, NS = kTile16T.ns; };
 // Implicit-GEMM convolution: the tiles of variants 0 and 1 with A gathered
 // from the NHWC input (CONV).
 template <> struct Cfg<DT_F16, 3> : Cfg<DT_F16, 0> { static constexpr bool CONV = true; };
 template <> struct Cfg<DT_BF16, 3> : Cfg<DT_BF16, 0> { static constexpr bool CONV = true; };
 template <> struct Cfg<DT_F16, 4> : Cfg<DT_F16, 1> { static constexpr bool CONV = true; };
 template <> struct Cfg<DT_BF16, 4> : Cfg<DT_BF16, 1> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_F16, 7> : Cfg<DT_F16, 6> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_BF16, 7> : Cfg<DT_BF16, 6> { static constexpr bool CONV = true; };
 
 // Optional tile traits: PRIO raises the waves' priority through the MFMA
 // section of each k-slab; WPE overrides the waves per SIMD the register

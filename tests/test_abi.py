@@ -400,7 +400,8 @@ def test_conv_plan_is_the_gemm_view(case, policy):
     sk = _lib()
     n, h, w, c, k, r, s, pad, std, dil = case
     P, Q = oc.out_size(h, w, r, s, pad[0], pad[1], std[0], std[1], dil[0], dil[1])
-    for tile, (cus, occ) in itertools.product([(256, 256, 64), (128, 128, 64, 4)], [(256, 1), (64, 2)]):
+    for tile, (cus, occ) in itertools.product([(256, 256, 64), (128, 128, 64, 4), (256, 64, 64)],
+                                              [(256, 1), (64, 2)]):
         cp = sk.ConvPlan(n, h, w, c, k, r, s, pad, std, dil, ta=sk.BF16, policy=policy, tile=tile, num_cus=cus,
                          occupancy=occ)
         gp = sk.Plan(n * P * Q, k, r * s * c, sk.ROW_MAJOR, sk.COL_MAJOR, sk.ROW_MAJOR, ta=sk.BF16, policy=policy,
@@ -414,12 +415,18 @@ def test_conv_plan_is_the_gemm_view(case, policy):
         assert records_to_schedule(cp.schedule(), ci["grid"]) == S.enumerate_schedule(ref)
 
 
-def test_conv_chooses_between_its_two_tiles():
+def test_conv_chooses_among_its_tiles():
+    """256x256 and 128x128 for any channel count; the tall 256x64 tile only
+    for at most 64 output channels."""
     sk = _lib()
     big = sk.ConvPlan(32, 56, 56, 64, 256, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
-    small = sk.ConvPlan(1, 7, 7, 64, 64, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
+    small = sk.ConvPlan(1, 7, 7, 64, 128, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
+    narrow = sk.ConvPlan(32, 56, 56, 64, 64, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
     assert big["tile"] in {(256, 256, 64, 8), (128, 128, 64, 4)}
     assert small["tile"] == (128, 128, 64, 4)
+    assert narrow["tile"] == (256, 64, 64, 4)
+    for k in (65, 96, 200):
+        assert sk.ConvPlan(8, 14, 14, 64, k, 3, 3, (1, 1), num_cus=256, occupancy=1).info()["tile"] != (256, 64, 64, 4)
 
 
 def test_conv_argument_errors():
@@ -460,6 +467,27 @@ def test_conv_argument_errors():
     z = sk.ConvPlan(0, 8, 8, 64, 32, 3, 3, (1, 1), num_cus=256, occupancy=1)
     assert z.info()["M"] == 0
     assert L.skgemm_conv_run(z.handle, None, None, None, 1.0, 0.0, None, 0, None) == sk.OK
+
+
+def test_tall_tile_only_for_narrow_problems():
+    """The tall 256x64x64 tile is a candidate only where every launched
+    problem has at most 64 columns (and B is K-contiguous), unless named."""
+    sk = _lib()
+    for (M, N, K), lb, lc in itertools.product([(8192, 16, 8192), (4096, 64, 2048), (3000, 65, 700), (1000, 1, 3000),
+                                                (64, 4096, 512)],
+                                               [sk.ROW_MAJOR, sk.COL_MAJOR], [sk.ROW_MAJOR, sk.COL_MAJOR]):
+        p = sk.Plan(M, N, K, lb=lb, lc=lc, ta=sk.BF16, num_cus=256, occupancy=2)
+        info = p.info()
+        cols = M if lc == sk.COL_MAJOR else N
+        if info["tile"] == (256, 64, 64, 4):
+            assert cols <= 64 and info["b_kcontig"], (M, N, K, lb, lc)
+        ref = oracle_plan_for(info, p.model_constants(), "auto")
+        assert records_to_schedule(p.schedule(), info["grid"]) == S.enumerate_schedule(ref)
+    assert sk.Plan(8192, 16, 8192, lb=sk.COL_MAJOR, ta=sk.BF16, num_cus=256, occupancy=2).info()["tile"] == \
+        (256, 64, 64, 4)
+    with pytest.raises(sk.SkgemmError) as e:      # no tall kernel reads an MN-contiguous B
+        sk.Plan(300, 16, 200, lb=sk.ROW_MAJOR, ta=sk.BF16, num_cus=256, occupancy=2, tile=(256, 64, 64))
+    assert e.value.status == sk.ERR_UNSUPPORTED
 
 
 def test_skinny_tile_only_for_short_problems():

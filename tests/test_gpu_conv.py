@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 TOL_OUT32 = 1e-5
 TOL_16 = 1e-2
-TILES = [(256, 256, 64), (128, 128, 64, 4)]
+TILES = [(256, 256, 64), (128, 128, 64, 4), (256, 64, 64)]
 
 CASES = [
     # n, h, w, c, k, r, s, pad, stride, dilation
@@ -32,6 +32,7 @@ CASES = [
     (2, 23, 23, 64, 64, 7, 7, (3, 3), (2, 2), (1, 1)),
     (1, 5, 8, 192, 33, 2, 3, (0, 1), (1, 2), (1, 1)),
     (5, 12, 12, 64, 300, 3, 3, (0, 0), (1, 1), (1, 1)),
+    (3, 15, 13, 128, 40, 3, 3, (1, 1), (1, 1), (1, 1)),        # fewer than 64 output channels: the tall tile
 ]
 
 
@@ -81,7 +82,7 @@ def test_conv_parity(case, dtype):
 
 
 @pytest.mark.parametrize("tile", TILES)
-@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[4]])
+@pytest.mark.parametrize("case", [CASES[1], CASES[2], CASES[4], CASES[7]])
 def test_conv_integer_exact_every_policy(case, tile):
     """Padding, stride and dilation cases with ragged M and N edges: every
     policy and a range of Stream-K grids give the oracle's exact result."""
@@ -143,6 +144,17 @@ def test_conv_empty_batch_and_argument_checks():
     with pytest.raises(sk().SkgemmError) as e:
         sk().conv2d(x, f)
     assert e.value.status == sk().ERR_UNSUPPORTED
+
+
+def test_conv_narrow_layer_takes_the_tall_tile():
+    """ResNet-50's first-stage 3x3 convolution (64 output channels, 100352
+    output pixels) plans on the tall tile; a small narrow case runs its
+    automatic plan against the oracle."""
+    assert sk().ConvPlan(32, 56, 56, 64, 64, 3, 3, (1, 1), ta=sk().BF16).info()["tile"] == (256, 64, 64, 4)
+    case = CASES[7]
+    x, f = inputs(case, torch.bfloat16, seed=12)
+    y = conv(x, f, case, out_dtype=torch.float32)
+    assert og.rel_frobenius(to_f64(y), oracle(x, f, case)) <= TOL_OUT32
 
 
 def test_conv_resnet_layer_sampled_images():
