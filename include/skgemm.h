@@ -89,9 +89,14 @@ typedef struct {
     int32_t tile_m, tile_n, tile_k;   /* 0 = the planner picks among the dtype's
                                          compiled tiles by modelled time; else must
                                          name one: FP32 128x128x32; FP16/BF16
-                                         256x256x64 or 128x128x64; FP8 256x256x128
-                                         or 128x128x128; FP64 64x64x16 or
-                                         128x128x16 */
+                                         256x256x64, 128x128x64, 64x256x64 (A
+                                         K-contiguous; picked automatically only
+                                         where every launched problem has at most
+                                         64 rows) or 256x64x64 (B K-contiguous; at
+                                         most 64 columns); FP8 256x256x128 or
+                                         128x128x128; FP64 64x64x16 or 128x128x16.
+                                         A named tile with no kernel for the
+                                         operands' contiguity: SKGEMM_ERR_UNSUPPORTED */
     int32_t hybrid_min_waves;     /* full waves needed for the two-tile hybrid (default 2) */
     int32_t num_cus;              /* >0: plan for this many CUs instead of querying */
     int32_t occupancy;            /* >0: workgroups per CU instead of querying */
@@ -348,7 +353,8 @@ skgemm_status_t skgemm_batched_run_traced(skgemm_plan_t plan,
  * c must be a multiple of 64 and x at most 2^31 - 1 bytes
  * (SKGEMM_ERR_UNSUPPORTED otherwise).  plan_info describes the GEMM view;
  * workspace and options as for skgemm_plan / skgemm_run (the tile options
- * name 256x256x64 or 128x128x64). */
+ * name 256x256x64, 128x128x64 or 256x64x64; the last is picked automatically
+ * only for at most 64 output channels). */
 typedef struct {
     int32_t n, h, w, c;                       /* input */
     int32_t k, r, s;                          /* filters: k output channels, r x s window */
