@@ -162,14 +162,14 @@ def fixup_waits(cases, ws, stream, torch, np):
             continue
         cap = c.sk.trace_capacity()
         tr = torch.full((cap * 8,), -1, dtype=torch.int32, device="cuda:0")
-        tm = torch.zeros((cap * 5,), dtype=torch.int64, device="cuda:0")
+        tm = torch.zeros((cap * 7,), dtype=torch.int64, device="cuda:0")
         args = (c.A.data_ptr(), c.K, c.B.data_ptr(), c.N, c.C.data_ptr(), c.N, 1.0, 0.0, None, None,
                 ws.data_ptr(), c.sk.workspace_size())
         c.sk.run(*args, stream=stream)
         c.sk.run_timed(*args, tr.data_ptr(), tm.data_ptr(), cap, stream=stream)
         torch.cuda.synchronize()
         recs = tr.cpu().numpy().reshape(-1, 8)
-        st = tm.cpu().numpy().reshape(-1, 5).astype(np.float64) / hz * 1e6
+        st = tm.cpu().numpy().reshape(-1, 7)[:, :5].astype(np.float64) / hz * 1e6
         used = recs[:, 0] >= 0
         recs, st = recs[used], st[used]
         contrib = {}
@@ -705,9 +705,20 @@ def main():
             ms = float(np.median(times))
             tf = 2.0 * L_ ** 3 / (ms * 1e-3) / 1e12
             info = plan.info()
+            # the shader clock under this load, from one timed run of the same plan
+            # (shader-clock ticks over real time, summed over its segments)
+            cap = plan.trace_capacity()
+            tr = torch.full((cap * 8,), -1, dtype=torch.int32, device="cuda:0")
+            tm = torch.zeros((cap * 7,), dtype=torch.int64, device="cuda:0")
+            plan.run_timed(lc.A.data_ptr(), L_, lc.B.data_ptr(), L_, lc.C.data_ptr(), L_, 1.0, 0.0, None, None,
+                           lws.data_ptr(), lws.numel(), tr.data_ptr(), tm.data_ptr(), cap, stream=sptr)
+            torch.cuda.synchronize()
+            st = tm.cpu().numpy().reshape(-1, 7)[tr.cpu().numpy().reshape(-1, 8)[:, 0] >= 0].astype(np.float64)
+            ghz = float((st[:, 6] - st[:, 5]).sum() / ((st[:, 4] - st[:, 0]).sum() / sk.realtime_hz()) / 1e9)
             large[f"bf16_{L_}"] = {"tflops": round(tf, 1), "pct_peak": round(100.0 * tf / PEAK_BF16_TFLOPS, 2),
                                    "us": round(ms * 1e3, 2), "policy": info["policy_name"],
-                                   "tile": list(info["tile"])}
+                                   "tile": list(info["tile"]), "shader_ghz": round(ghz, 3),
+                                   "pct_peak_at_shader_clock": round(100.0 * tf / (PEAK_BF16_TFLOPS * ghz / 2.4), 2)}
             del lc, lws
         torch.cuda.synchronize()
 

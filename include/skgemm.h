@@ -217,15 +217,18 @@ skgemm_status_t skgemm_run_traced(skgemm_plan_t plan,
                                   void* workspace, size_t ws_bytes,
                                   int32_t* trace, size_t trace_records, hipStream_t stream);
 
-/* Same as skgemm_run_traced, and each traced segment also gets five
- * timestamps of the device's constant-rate real-time clock
- * (skgemm_realtime_hz ticks per second), taken by the workgroup's first
- * thread: {segment start, MAC loop done, partial stores and ready flags
- * done, fix-up waits done, segment done}.  times is device memory of
- * 5 * trace_records uint64 values, laid out like the records (record i's
- * stamps at 5 * i).  The gap between the third and fourth stamp is the time
- * a workgroup spent waiting for its peers' partial tiles (the Wait of the
- * basic Stream-K algorithm); it is zero for segments that wait for nobody. */
+/* Same as skgemm_run_traced, and each traced segment also gets seven
+ * values, taken by the workgroup's first thread: five timestamps of the
+ * device's constant-rate real-time clock (skgemm_realtime_hz ticks per
+ * second) {segment start, MAC loop done, partial stores and ready flags
+ * done, fix-up waits done, segment done}, then the shader-clock counter at
+ * the segment's start and at its end (so (v6 - v5) / (v4 - v0) times
+ * skgemm_realtime_hz is the shader clock under the launch's own load).
+ * times is device memory of 7 * trace_records uint64 values, laid out like
+ * the records (record i's values at 7 * i).  The gap between the third and
+ * fourth stamp is the time a workgroup spent waiting for its peers' partial
+ * tiles (the Wait of the basic Stream-K algorithm); it is zero for segments
+ * that wait for nobody. */
 skgemm_status_t skgemm_run_timed(skgemm_plan_t plan,
                                  const void* A, int64_t lda, const void* B, int64_t ldb,
                                  void* C, int64_t ldc, float alpha, float beta,

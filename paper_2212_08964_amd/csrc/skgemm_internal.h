@@ -21,7 +21,7 @@ constexpr int kAutoMaxWaves = 4;
 constexpr int kTraceFields = 8;
 // Timestamps per traced segment (device real-time clock): start, MAC loop
 // done, partial stores and flags done, fix-up waits done, segment done.
-constexpr int kTimeFields = 5;
+constexpr int kTimeFields = 7;
 constexpr int32_t kErrTimeout = 6;
 
 // Compiled tile configurations per input type (BM x BN x BK).

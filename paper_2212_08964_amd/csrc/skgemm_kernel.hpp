@@ -1227,6 +1227,10 @@ struct Gemm {
     static __device__ __forceinline__ void stamp(uint64_t* ts, int f, int tid) {
         if (ts && tid == 0) ts[f] = __builtin_amdgcn_s_memrealtime();
     }
+    // The shader-clock counter, into field f of a timed run's record.
+    static __device__ __forceinline__ void stamp_clock(uint64_t* ts, int f, int tid) {
+        if (ts && tid == 0) ts[f] = __builtin_amdgcn_s_memtime();
+    }
 
     static __device__ __forceinline__ void finish(const KArgs& ka, const Prob& a, int tile, Acc& acc, int tid,
                                                   const Stages& sts, int wg, const Exit& x, uint64_t* ts) {
@@ -1521,6 +1525,7 @@ struct Gemm {
                                : nullptr;
             ++seq;
             stamp(ts, 0, tid);
+            stamp_clock(ts, 5, tid);
 
             mac_loop(pr, st, tile, lo, hi, acc, tid);
             stamp(ts, 1, tid);
@@ -1550,6 +1555,7 @@ struct Gemm {
             }
             finish(a, pr, tile, acc, tid, st, wg, x, ts);
             stamp(ts, 4, tid);
+            stamp_clock(ts, 6, tid);
         }
     }
 };

@@ -520,7 +520,7 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     ``out`` is given it receives the result and supplies C for beta != 0.
     ``trace``, when given, is an int32 device tensor of at least
     8 * plan.trace_capacity() elements that receives the schedule records;
-    ``times`` (int64, 5 per record) adds each segment's timestamps.
+    ``times`` (int64, 7 per record) adds each segment's timestamps and shader-clock counts.
     ``check`` (default: set_error_checks) synchronises after the launch and
     raises SkgemmError(ERR_TIMEOUT), with the workspace cleared, if a fix-up
     wait expired."""
@@ -577,7 +577,7 @@ def matmul(A, B, out=None, *, out_dtype=None, alpha=1.0, beta=0.0, scale_a=None,
     elif times is None:
         plan.run_traced(*args, trace.data_ptr(), trace.numel() // 8, stream=stream)
     else:
-        n = min(trace.numel() // 8, times.numel() // 5)
+        n = min(trace.numel() // 8, times.numel() // 7)
         plan.run_timed(*args, trace.data_ptr(), times.data_ptr(), n, stream=stream)
     if ws is not None and (_check_runs if check is None else check):
         check_workspace(ws, stream)

@@ -587,20 +587,26 @@ def test_timed_run_stamps_and_schedule(shape, policy, g, fixup):
     p = sk().get_plan(M, N, K, 0, 0, 0, sk().BF16, sk().F32, policy, g, 2, None, fixup)
     cap = p.trace_capacity()
     tr = torch.full((cap * 8,), -7, dtype=torch.int32, device=dev())
-    ts = torch.zeros((cap * 5,), dtype=torch.int64, device=dev())
+    ts = torch.zeros((cap * 7,), dtype=torch.int64, device=dev())
     C = mm(A, B, trace=tr, times=ts, **kw)
     C0 = mm(A, B, **kw)
     assert torch.equal(C, C0)
     info = p.info()
     recs = tr.cpu().numpy().reshape(-1, 8)
-    stamps = ts.cpu().numpy().reshape(-1, 5)
+    stamps = ts.cpu().numpy().reshape(-1, 7)
     used = recs[:, 0] != -7
     got = records_to_schedule([tuple(int(v) for v in r) for r in recs[used]], info["grid"])
     assert got == S.enumerate_schedule(oracle_plan_for(info, p.model_constants(), policy, force_g=g))
-    st = stamps[used]
+    st = stamps[used][:, :5]
+    clk = stamps[used][:, 5:]
     assert np.all(st > 0) and np.all(np.diff(st, axis=1) >= 0)
     hz = sk().realtime_hz()
     assert 1e6 <= hz <= 1e10
+    # the shader clock over the whole launch: between 0.5 and 3 GHz
+    ticks = clk[:, 1].astype(np.float64) - clk[:, 0]
+    assert np.all(ticks > 0)
+    ghz = ticks.sum() / ((st[:, 4] - st[:, 0]).astype(np.float64).sum() / hz) / 1e9
+    assert 0.5 < ghz < 3.0, ghz
     per_wg = {}
     for r, s_ in zip(recs[used], st):
         per_wg.setdefault(int(r[0]), []).append((int(r[1]), s_))
