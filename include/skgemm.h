@@ -157,7 +157,10 @@ typedef struct skgemm_plan_s* skgemm_plan_t;
  * opt->num_cus and opt->occupancy are set).  la / lb / lc are the layouts of
  * A, B and C; ta == tb is required.  FP8 needs A row-major and B
  * column-major (K contiguous in both); skgemm_quantize_e4m3 writes either.
- * On success *out receives a plan that skgemm_plan_destroy frees. */
+ * On success *out receives a plan that skgemm_plan_destroy frees.  With
+ * SKGEMM_LOG=1 in the environment every plan function prints one line per
+ * plan it builds on stderr (launch kind, shape, tile, resolved policy and
+ * grid, modelled time). */
 skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
                             skgemm_layout_t la, skgemm_layout_t lb, skgemm_layout_t lc,
                             skgemm_dtype_t ta, skgemm_dtype_t tb, skgemm_dtype_t tc,

@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -59,7 +61,7 @@ struct skgemm_plan_s {
     std::vector<int32_t> order;             // caller's index of each problem in iteration-space order
     int t_work;                             // tiles with MAC-loop iterations (they come first)
     int64_t batch;                          // strided batch of equal problems (1 = one GEMM)
-    bool conv;                              // implicit-GEMM convolution (tile variants 3 and 4)
+    bool conv;                              // implicit-GEMM convolution (tile variants 3, 4 and 7)
     ConvArgs cv;
     int64_t sk_iters;
 };
@@ -694,6 +696,27 @@ static void add_problem(skgemm_plan_s* pl, int64_t M, int64_t N, int64_t K) {
     pl->iter_base.push_back(pl->iter_base.back() + tm * tn * ipt);
 }
 
+// SKGEMM_LOG=1 in the environment: one line on stderr per plan built, with
+// the decision (launch kind, shape, tile, resolved policy and grid, modelled
+// time).  Read once per process.
+static void log_plan(const skgemm_plan_s* pl) {
+    static const bool on = [] {
+        const char* v = std::getenv("SKGEMM_LOG");
+        return v && v[0] && !(v[0] == '0' && !v[1]);
+    }();
+    if (!on) return;
+    static const char* const kPol[] = {"auto", "dp", "sk", "dp_1tile_sk", "2tile_sk_dp", "paper"};
+    const char* kind = pl->conv ? "conv" : pl->G ? "grouped" : pl->batch > 1 ? "batched" : "gemm";
+    const double est = plan_estimate(pl, nullptr);
+    std::fprintf(stderr,
+                 "skgemm: plan %s M=%lld N=%lld K=%lld G=%d batch=%lld dtype=%d tile=%dx%dx%d/%d policy=%s "
+                 "tiles=%d ipt=%d sk_tiles=%d g_sk=%d grid=%d p=%d est_us=%.2f\n",
+                 kind, (long long)pl->M, (long long)pl->N, (long long)pl->K, pl->G, (long long)pl->batch, pl->dtype,
+                 pl->BM, pl->BN, pl->BK, kernel_threads(pl->dtype, pl->variant) / 64,
+                 pl->policy >= 0 && pl->policy <= 5 ? kPol[pl->policy] : "?", pl->t, pl->ipt, pl->sk_tiles,
+                 pl->g_sk, pl->grid, pl->p, est);
+}
+
 skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K, skgemm_layout_t la,
                             skgemm_layout_t lb, skgemm_layout_t lc, skgemm_dtype_t ta, skgemm_dtype_t tb,
                             skgemm_dtype_t tc, const skgemm_options_t* opt) {
@@ -715,6 +738,7 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
     if (st != SKGEMM_OK) return st;
+    log_plan(pl);
     *out = pl;
     return SKGEMM_OK;
 }
@@ -758,6 +782,7 @@ skgemm_status_t skgemm_conv_plan(skgemm_plan_t* out, const skgemm_conv_t* cv, sk
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &base.M, &base.N, &base.K, &pl);
     if (st != SKGEMM_OK) return st;
+    log_plan(pl);
     *out = pl;
     return SKGEMM_OK;
 }
@@ -795,6 +820,7 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, G, M, N, K, &pl);
     if (st != SKGEMM_OK) return st;
+    log_plan(pl);
     *out = pl;
     return SKGEMM_OK;
 }
@@ -965,6 +991,7 @@ skgemm_status_t skgemm_batched_plan(skgemm_plan_t* out, int64_t batch, int64_t M
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
     if (st != SKGEMM_OK) return st;
+    log_plan(pl);
     *out = pl;
     return SKGEMM_OK;
 }

@@ -510,3 +510,27 @@ def test_skinny_tile_only_for_short_problems():
     with pytest.raises(sk.SkgemmError) as e:      # no skinny kernel reads an MN-contiguous A
         sk.Plan(16, 300, 200, la=sk.COL_MAJOR, ta=sk.BF16, num_cus=256, occupancy=2, tile=(64, 256, 64))
     assert e.value.status == sk.ERR_UNSUPPORTED
+
+
+def test_plan_log_environment_switch():
+    """SKGEMM_LOG=1 prints one line per plan built (launch kind, shape, tile,
+    resolved policy and grid); unset, the library prints nothing."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2212_08964_amd import skgemm as sk\n"
+            "sk.Plan(300, 200, 900, ta=sk.BF16, policy='sk', force_g=12, num_cus=256, occupancy=1)\n"
+            "sk.ConvPlan(2, 8, 8, 64, 32, 3, 3, (1, 1), num_cus=256, occupancy=1)\n"
+            "sk.GroupedPlan([64, 128], [64, 64], [64, 64], ta=sk.BF16, num_cus=256, occupancy=1)\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    env = dict(os.environ, SKGEMM_LOG="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    lines = [ln for ln in out.stderr.splitlines() if ln.startswith("skgemm: plan")]
+    assert len(lines) == 3, out.stderr
+    assert " gemm M=300 N=200 K=900 " in lines[0] and "policy=sk" in lines[0] and "g_sk=12" in lines[0]
+    assert lines[1].startswith("skgemm: plan conv M=128 N=32 K=576")
+    assert lines[2].startswith("skgemm: plan grouped") and "G=2" in lines[2]
+    env["SKGEMM_LOG"] = "0"
+    quiet = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert quiet.returncode == 0 and "skgemm: plan" not in quiet.stderr
