@@ -84,6 +84,8 @@ def parse():
                     help="with --profile-steps: which pass to run (the automatic policy or the DP baseline)")
     ap.add_argument("--profile-shape", default="",
                     help="MxNxK: run only this BF16 GEMM (automatic policy) --profile-steps times, for profilers")
+    ap.add_argument("--relayout", default="auto", choices=["auto", "never"],
+                    help="operand re-layout of misaligned rows: the planner's rule, or never")
     ap.add_argument("--dump", default="", help="write per-shape timings (JSON lines) to this path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many Stream-K steps (for profiler runs) and print timings")
@@ -100,7 +102,7 @@ class Case:
     __slots__ = ("M", "N", "K", "A", "B", "C", "sk", "dp", "flops", "bytes", "fixup_bytes", "t", "p")
 
 
-def build_cases(shapes, torch, sk):
+def build_cases(shapes, torch, sk, relayout=0):
     cases = []
     dev = torch.device("cuda:0")
     gen = torch.Generator(device=dev)
@@ -111,11 +113,12 @@ def build_cases(shapes, torch, sk):
         c.A = torch.randn((M, K), generator=gen, device=dev, dtype=torch.float32).to(torch.bfloat16)
         c.B = torch.randn((K, N), generator=gen, device=dev, dtype=torch.float32).to(torch.bfloat16)
         c.C = torch.empty((M, N), device=dev, dtype=torch.bfloat16)
-        c.sk = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="auto")
+        c.sk = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="auto",
+                       relayout=relayout)
         info = c.sk.info()
         # the baseline: the same kernel and tile with one workgroup per tile
         c.dp = sk.Plan(M, N, K, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.ROW_MAJOR, sk.BF16, sk.BF16, policy="dp",
-                       tile=info["tile"])
+                       tile=info["tile"], relayout=relayout)
         c.t, c.p = info["t"], info["p"]
         c.flops = 2.0 * M * N * K
         c.bytes = 2 * (M * K + K * N + M * N)       # read A and B once, write C once (bf16)
@@ -512,7 +515,7 @@ def main():
 
     shapes = W.sweep_shapes(args.shapes, seed=0)
     t0 = time.perf_counter()
-    cases = build_cases(shapes, torch, sk)
+    cases = build_cases(shapes, torch, sk, relayout=0 if args.relayout == "auto" else -1)
     plan_s = time.perf_counter() - t0
     # planning cost alone (host, microseconds per plan)
     tp = time.perf_counter()
@@ -753,6 +756,9 @@ def main():
                    "baseline": "same kernel and tile, policy=dp (one workgroup per tile)",
                    "tiles": "256x256x64, or 128x128x64 (4 or 8 waves) where the planner predicts it faster "
                             "(same tile for both)",
+                   "relayout": {"auto": "planner's rule (misaligned operand rows copied to 128-byte lines "
+                                        "when predicted faster; the copy is timed)",
+                                "never": "off"}[args.relayout],
                    "total_gflop": round(total_flops / 1e9, 1), "parallelism": "single GPU"},
         "pct_mfma_peak": round(100.0 * value / PEAK_BF16_TFLOPS, 2),
         "dp_value": round(dp_value, 3),

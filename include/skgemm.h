@@ -143,6 +143,17 @@ typedef struct {
                                      finishes with the sum it has, so the kernel
                                      always exits.  A small value forces that path
                                      (tests of the error handling). */
+    int32_t relayout;             /* copy of misaligned operands into 128-byte
+                                     aligned lines before the GEMM (single-GEMM
+                                     plans, see skgemm_run): 0 = where it is
+                                     predicted to pay (the operand is read once
+                                     per panel of the other operand: the
+                                     misaligned bytes moved, its size times that
+                                     panel count, against the copy's 2 bytes
+                                     moved per operand byte), -1 = never,
+                                     1 / 2 / 3 = always
+                                     for A / B / both (the operands as given by
+                                     the caller) when their lines are misaligned */
 } skgemm_options_t;
 
 typedef enum { SKGEMM_SHARE_PROPORTIONAL = 0, SKGEMM_SHARE_LEADING = 1 } skgemm_share_t;
@@ -167,19 +178,27 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
                             const skgemm_options_t* opt);
 
 /* Bytes of device workspace a run of this plan needs (0 when the plan has no
- * Stream-K region).  The workspace holds an error word, the ready flags (a
- * fixed area of 512 KiB for up to 4096 Stream-K workgroups) and the FP32
- * partial tiles, one per Stream-K workgroup.  It must be 256-byte aligned and
- * zero-filled once after allocation; the kernel leaves its flags at zero again
- * on success, so it can be reused without clearing, also by other plans (the
- * flag area is at the same place for every plan).  After SKGEMM_ERR_TIMEOUT it
- * must be zero-filled again. */
+ * Stream-K region and re-lays out no operand).  The workspace holds an error
+ * word, the ready flags (a fixed area of 512 KiB for up to 4096 Stream-K
+ * workgroups) and the FP32 partial tiles, one per Stream-K workgroup (the
+ * fix-up part, plan_info field 28), then, for a single-GEMM plan that the
+ * model says gains from it, room for a copy of A and/or B with 128-byte
+ * aligned lines (plan_info fields 26 and 27; see skgemm_run).  It must be
+ * 256-byte aligned and zero-filled once after allocation; the kernel leaves
+ * its flags at zero again on success, so it can be reused without clearing,
+ * also by other plans (the flag area is at the same place for every plan).
+ * After SKGEMM_ERR_TIMEOUT it must be zero-filled again. */
 skgemm_status_t skgemm_workspace_size(skgemm_plan_t plan, size_t* bytes);
 
 /* Run a planned GEMM.  lda/ldb/ldc follow each operand's layout and must be
  * at least its contiguous extent.  scale_a / scale_b point to one FP32 value
  * on the device each (NULL = 1).  workspace may be NULL when the workspace
- * size is 0. */
+ * size is 0.  When the plan re-lays out an operand and its leading dimension
+ * in bytes is not a multiple of 128, the run first copies it into the
+ * workspace with 128-byte aligned lines (a second kernel on the same stream)
+ * and multiplies the copy: the result is bitwise the same.  With a workspace
+ * smaller than skgemm_workspace_size but at least its fix-up part the run
+ * multiplies the operands as given. */
 skgemm_status_t skgemm_run(skgemm_plan_t plan,
                            const void* A, int64_t lda, const void* B, int64_t ldb,
                            void* C, int64_t ldc, float alpha, float beta,
@@ -190,9 +209,10 @@ skgemm_status_t skgemm_run(skgemm_plan_t plan,
  * graph capture, serving loops that must not call hipMalloc): the fix-up
  * workspace is a 64 MiB device array the library holds on every GPU it runs
  * on until the process ends, so the caller passes no workspace.  Plans whose
- * skgemm_workspace_size exceeds 64 MiB are refused with
+ * fix-up workspace (plan_info field 28) exceeds 64 MiB are refused with
  * SKGEMM_ERR_WORKSPACE (e.g. more than 254 Stream-K workgroups with
- * 256x256 FP32 partial tiles).  Allocates nothing: before the GEMM it
+ * 256x256 FP32 partial tiles); operands are multiplied as given (no
+ * re-layout copy).  Allocates nothing: before the GEMM it
  * clears the error word and the plan's flag lines with a small kernel on
  * `stream` (capturable), then runs skgemm_run on the array.  All calls on
  * one GPU share its array: calls that overlap in time on one GPU (on
@@ -255,8 +275,10 @@ skgemm_status_t skgemm_realtime_hz(int64_t* hz);
  * tile under the split fix-up (0 = owner fix-up), 23 workgroups per CU
  * (p = CUs * field 23), 24 wavefronts per workgroup, 25 batch (1 unless a
  * strided batched plan, whose fields 7 and 8 describe one problem and
- * field 9 counts the tiles of the whole batch).
- * n is the capacity of info; up to 26 values are written. */
+ * field 9 counts the tiles of the whole batch), 26 / 27 the launched A / B is
+ * copied to 128-byte aligned lines when passed misaligned (0/1), 28 bytes of
+ * the fix-up part of the workspace.
+ * n is the capacity of info; up to 29 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)

@@ -23,7 +23,7 @@ BUILD_DIR = os.path.join(PKG, "_build")
 # the largest units first, so the pool finishes together
 SOURCES = ["kernels_bf16.hip", "kernels_bf16_full.hip", "kernels_f16.hip", "kernels_f16_full.hip",
            "kernels_f64.hip", "kernels_f64_full.hip", "kernels_f8.hip", "kernels_f8_full.hip",
-           "kernels_f32.hip", "kernels_f32_full.hip", "dispatch.hip", "quant.hip", "noalloc.hip",
+           "kernels_f32.hip", "kernels_f32_full.hip", "dispatch.hip", "quant.hip", "noalloc.hip", "pack.hip",
            "skgemm_abi.cpp"]
 
 ARCH = "gfx950"

@@ -58,16 +58,16 @@ __global__ void __launch_bounds__(256) clear_words(int32_t* p, int n) {
 extern "C" skgemm_status_t skgemm_run_noalloc(skgemm_plan_t plan, const void* A, int64_t lda, const void* B,
                                               int64_t ldb, void* C, int64_t ldc, float alpha, float beta,
                                               const float* scale_a, const float* scale_b, hipStream_t stream) {
-    size_t need = 0;
-    skgemm_status_t st = skgemm_workspace_size(plan, &need);
+    // the fix-up part of the workspace only (plan_info field 28): the
+    // operand re-layout a full-size workspace allows is not done here
+    int64_t info[29] = {};
+    skgemm_status_t st = skgemm_plan_info(plan, info, 29);
     if (st != SKGEMM_OK) return st;
+    const size_t need = size_t(info[28]);
     if (need > kScratchBytes) return SKGEMM_ERR_WORKSPACE;
     if (need == 0) return skgemm_run(plan, A, lda, B, ldb, C, ldc, alpha, beta, scale_a, scale_b, nullptr, 0, stream);
     void* ws = nullptr;
     st = scratch_ptr(&ws);
-    if (st != SKGEMM_OK) return st;
-    int64_t info[14] = {};
-    st = skgemm_plan_info(plan, info, 14);
     if (st != SKGEMM_OK) return st;
     const int64_t g_sk = info[13];
     // The flags are left at zero by every run that completes its waits; an

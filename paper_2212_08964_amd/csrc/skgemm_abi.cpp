@@ -51,6 +51,13 @@ struct skgemm_plan_s {
     double model[5];   // a, b, c, d of the grid-size model; e: c with every workgroup slot busy
     // workspace layout
     size_t ws_bytes, flags_off, partials_off;
+    // re-layout of the launched A (0) and B (1) into the workspace when their
+    // lines are not 128-byte aligned (decided per call from the leading
+    // dimension; planned only where the model says it pays)
+    bool pack[2];
+    int64_t pack_lines[2], pack_cols[2], pack_ld[2];
+    size_t pack_off[2];
+    size_t ws_total;                         // ws_bytes plus the re-layout regions
     int max_segs;
     // iteration space as problems (a single GEMM is one problem)
     int G;                                  // 0 for a single-GEMM plan
@@ -496,6 +503,8 @@ static skgemm_status_t finish_plan(skgemm_plan_s* pl, const skgemm_options_t& o)
     // partial tiles accumulate in FP32, or FP64 for FP64 inputs
     const size_t acc_bytes = pl->dtype == DT_F64 ? 8 : 4;
     pl->ws_bytes = pl->g_sk ? pl->partials_off + size_t(pl->g_sk) * pl->BM * pl->BN * acc_bytes : 0;
+    pl->pack[0] = pl->pack[1] = false;
+    pl->ws_total = pl->ws_bytes;
     int mx = 0;
     for (int x = 0; x < pl->grid; ++x) mx = std::max(mx, walk(*pl, x, [](int, int, int, int, int, int, int) {}));
     pl->max_segs = mx;
@@ -533,6 +542,7 @@ static skgemm_status_t init_common(skgemm_plan_s* pl, skgemm_layout_t la, skgemm
     pl->hybrid_min_waves = o.hybrid_min_waves;
     if (o.share != SKGEMM_SHARE_PROPORTIONAL && o.share != SKGEMM_SHARE_LEADING) return SKGEMM_ERR_INVALID_ARG;
     if (o.fixup != SKGEMM_FIXUP_AUTO && o.fixup != SKGEMM_FIXUP_OWNER) return SKGEMM_ERR_INVALID_ARG;
+    if (o.relayout < -1 || o.relayout > 3) return SKGEMM_ERR_INVALID_ARG;
     pl->fixup_owner = o.fixup == SKGEMM_FIXUP_OWNER;
     pl->share_prop = o.share == SKGEMM_SHARE_PROPORTIONAL;
     pl->raster = o.raster_rows ? o.raster_rows : kDefaultRaster;
@@ -696,6 +706,61 @@ static void add_problem(skgemm_plan_s* pl, int64_t M, int64_t N, int64_t K) {
     pl->iter_base.push_back(pl->iter_base.back() + tm * tn * ipt);
 }
 
+// Operand re-layout (single GEMMs only).  A line of an operand is a row of its
+// contiguous dimension: the M (or N) rows of a K-contiguous operand, the K
+// rows of an MN-contiguous one.  When the lines as the caller is expected to
+// pass them (leading dimension = line length) do not start on 128-byte
+// boundaries, every 128-byte segment of a slab row spans two cache lines and
+// moves from L2 twice (BF16 on MI355X, operands in 64-element-padded storage
+// against the natural leading dimensions: 9-38 % of the GEMM's time).  A copy
+// into 128-byte lines costs a second launch and a pass over the operand, so
+// it pays only where the operand is read many times over: each of the
+// other operand's tile panels (tile columns for A, tile rows for B) reads
+// the whole operand once, so the misaligned bytes moved grow with
+// MB x panels, while the copy moves about 2 MB.  Over the 183 ragged shapes of
+// the BF16 sweep with at least 4 GFLOP, timed with no copy, A, B and both
+// copied, the gain fits (us) 0.0288 MB.panels - 0.339 MB for a K-contiguous
+// operand and 0.0205 MB.panels - 0.346 MB for an MN-contiguous one (the MB
+// terms are the copy at about 6 TB/s); copying where the fit exceeds 6 us
+// saved 2.4 % of those shapes' time in five-fold cross-validation and lost at
+// most 7 % on a shape, against 4.8 % for the best choice per shape and a
+// 13 % loss for always copying.
+constexpr double kPackKcR = 0.0288, kPackKcMb = 0.339;
+constexpr double kPackMnR = 0.0205, kPackMnMb = 0.346;
+constexpr double kPackMarginUs = 6.0;
+constexpr int64_t kPackMaxBytes = int64_t(1) << 31;
+
+static void plan_packing(skgemm_plan_s* pl, int32_t relayout) {
+    const int eb = elem_bytes(pl->ta);
+    // after the fix-up part and never over the error word and flag area, which
+    // every plan sharing a workspace keeps at the same place and expects zero
+    size_t off = (std::max(pl->ws_bytes, pl->partials_off) + 255) & ~size_t(255);
+    for (int x = 0; x < 2; ++x) {
+        const bool kc = x == 0 ? pl->akc : pl->bkc;
+        const int64_t outer = x == 0 ? pl->Ml : pl->Nl;
+        const int64_t lines = kc ? outer : pl->K, cols = kc ? pl->K : outer;
+        const int64_t align = 128 / eb;
+        pl->pack_lines[x] = lines;
+        pl->pack_cols[x] = cols;
+        pl->pack_ld[x] = (cols + align - 1) / align * align;
+        const int64_t bytes = lines * pl->pack_ld[x] * eb;
+        const double mb = double(lines) * double(cols) * eb / 1e6;
+        // panels of the other operand, each of which reads this one whole
+        const double panels = double(x == 0 ? cdiv(pl->Nl, pl->BN) : cdiv(pl->Ml, pl->BM));
+        const double gain = kc ? kPackKcR * mb * panels - kPackKcMb * mb : kPackMnR * mb * panels - kPackMnMb * mb;
+        // relayout masks name the caller's A and B; x is the launched operand
+        const int caller = pl->swapped ? 1 - x : x;
+        const bool wanted = relayout == 0 ? gain > kPackMarginUs : relayout > 0 && ((relayout >> caller) & 1);
+        pl->pack[x] = lines > 0 && cols > 0 && (cols * eb) % 128 != 0 && bytes <= kPackMaxBytes &&
+                      pl->pack_ld[x] <= kMaxDim && wanted;
+        if (pl->pack[x]) {
+            pl->pack_off[x] = off;
+            off += (size_t(bytes) + 255) & ~size_t(255);
+        }
+    }
+    pl->ws_total = (pl->pack[0] || pl->pack[1]) ? off : pl->ws_bytes;
+}
+
 // SKGEMM_LOG=1 in the environment: one line on stderr per plan built, with
 // the decision (launch kind, shape, tile, resolved policy and grid, modelled
 // time).  Read once per process.
@@ -710,11 +775,11 @@ static void log_plan(const skgemm_plan_s* pl) {
     const double est = plan_estimate(pl, nullptr);
     std::fprintf(stderr,
                  "skgemm: plan %s M=%lld N=%lld K=%lld G=%d batch=%lld dtype=%d tile=%dx%dx%d/%d policy=%s "
-                 "tiles=%d ipt=%d sk_tiles=%d g_sk=%d grid=%d p=%d est_us=%.2f\n",
+                 "tiles=%d ipt=%d sk_tiles=%d g_sk=%d grid=%d p=%d est_us=%.2f pack=%d%d\n",
                  kind, (long long)pl->M, (long long)pl->N, (long long)pl->K, pl->G, (long long)pl->batch, pl->dtype,
                  pl->BM, pl->BN, pl->BK, kernel_threads(pl->dtype, pl->variant) / 64,
                  pl->policy >= 0 && pl->policy <= 5 ? kPol[pl->policy] : "?", pl->t, pl->ipt, pl->sk_tiles,
-                 pl->g_sk, pl->grid, pl->p, est);
+                 pl->g_sk, pl->grid, pl->p, est, pl->pack[0] ? 1 : 0, pl->pack[1] ? 1 : 0);
 }
 
 skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K, skgemm_layout_t la,
@@ -738,6 +803,7 @@ skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K,
     skgemm_plan_s* pl = nullptr;
     st = plan_variants(&base, o, 1, &M, &N, &K, &pl);
     if (st != SKGEMM_OK) return st;
+    plan_packing(pl, o.relayout);
     log_plan(pl);
     *out = pl;
     return SKGEMM_OK;
@@ -827,7 +893,7 @@ skgemm_status_t skgemm_grouped_plan(skgemm_plan_t* out, int32_t G, const int64_t
 
 skgemm_status_t skgemm_workspace_size(skgemm_plan_t plan, size_t* bytes) {
     if (!plan || !bytes) return SKGEMM_ERR_INVALID_ARG;
-    *bytes = plan->ws_bytes;
+    *bytes = plan->ws_total;
     return SKGEMM_OK;
 }
 
@@ -912,6 +978,28 @@ static skgemm_status_t run_impl(skgemm_plan_t pl, const void* A, int64_t lda, co
             return SKGEMM_ERR_WORKSPACE;
     }
     if (trace && trace_records < size_t(pl->grid) * size_t(pl->max_segs)) return SKGEMM_ERR_INVALID_ARG;
+    // re-layout of operands whose lines, as passed, are not 128-byte aligned
+    // (only with a workspace of the plan's full size: a smaller one that
+    // still holds the fix-up runs the GEMM on the operands as given)
+    if ((pl->pack[0] || pl->pack[1]) && workspace && ws_bytes >= pl->ws_total &&
+        !(reinterpret_cast<uintptr_t>(workspace) & 255)) {
+        const int eb = elem_bytes(pl->ta);
+        for (int x = 0; x < 2; ++x) {
+            const void*& op = x == 0 ? e.A : e.B;
+            int64_t& ld = x == 0 ? e.lda : e.ldb;
+            if (!pl->pack[x] || (ld * eb) % 128 == 0) continue;
+            // the copy's leading dimension must keep a tile's slab within 32-bit offsets
+            const bool kc = x == 0 ? pl->akc : pl->bkc;
+            const int64_t span = kc ? int64_t(x == 0 ? pl->BM : pl->BN) * pl->pack_ld[x] * eb + 128
+                                    : int64_t(pl->BK) * pl->pack_ld[x] * eb + 512;
+            if (span > kMaxDim) continue;
+            void* dst = static_cast<unsigned char*>(workspace) + pl->pack_off[x];
+            const int rc = launch_pack(op, ld, pl->pack_lines[x], pl->pack_cols[x], dst, pl->pack_ld[x], eb, stream);
+            if (rc != int(hipSuccess)) return SKGEMM_ERR_HIP;
+            op = dst;
+            ld = pl->pack_ld[x];
+        }
+    }
     KArgs a;
     std::memset(&a, 0, sizeof(a));
     a.A = e.A; a.B = e.B; a.C = e.C;
@@ -1129,12 +1217,13 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[26] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[29] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
                            pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
                            pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s,
-                           pl->occ, kernel_threads(pl->dtype, pl->variant) / 64, pl->batch};
-    for (int i = 0; i < n && i < 26; ++i) info[i] = v[i];
+                           pl->occ, kernel_threads(pl->dtype, pl->variant) / 64, pl->batch,
+                           pl->pack[0] ? 1 : 0, pl->pack[1] ? 1 : 0, int64_t(pl->ws_bytes)};
+    for (int i = 0; i < n && i < 29; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 

@@ -113,6 +113,11 @@ struct KArgs {
 constexpr int kVariants = 8;
 constexpr bool is_conv_variant(int v) { return v == 3 || v == 4 || v == 7; }
 
+// Copy `lines` lines of `cols` elements of eb bytes (line i at src + i * ld)
+// to dst with leading dimension ldd, on stream.  Returns a hipError_t value.
+int launch_pack(const void* src, int64_t ld, int64_t lines, int64_t cols, void* dst, int64_t ldd, int eb,
+                void* stream);
+
 // Launch one Stream-K GEMM kernel.  Returns a hipError_t value.
 int launch_gemm(int dtype, bool a_kcontig, bool b_kcontig, int variant, const KArgs& args, int grid,
                 void* stream);

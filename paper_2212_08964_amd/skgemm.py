@@ -38,7 +38,7 @@ EXPORTED = [
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
                "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
-               "share", "coop_s", "occupancy", "waves", "batch"]
+               "share", "coop_s", "occupancy", "waves", "batch", "pack_a", "pack_b", "fixup_ws_bytes"]
 SHARE = {"proportional": 0, "leading": 1}
 SHARE_NAME = {v: k for k, v in SHARE.items()}
 FIXUP = {"auto": 0, "owner": 1}
@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32), ("hybrid_min_waves", ctypes.c_int32),
                 ("num_cus", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("raster_rows", ctypes.c_int32),
                 ("xcds", ctypes.c_int32), ("share", ctypes.c_int32), ("fixup", ctypes.c_int32),
-                ("tile_waves", ctypes.c_int32), ("spin_limit", ctypes.c_int32)]
+                ("tile_waves", ctypes.c_int32), ("spin_limit", ctypes.c_int32), ("relayout", ctypes.c_int32)]
 
 
 class GroupArgs(ctypes.Structure):
@@ -152,9 +152,10 @@ class Plan:
 
     def __init__(self, M, N, K, la=ROW_MAJOR, lb=ROW_MAJOR, lc=ROW_MAJOR, ta=BF16, tc=None,
                  policy="auto", force_g=0, hybrid_min_waves=2, num_cus=0, occupancy=0, tile=None,
-                 raster_rows=0, xcds=0, share="proportional", fixup="auto", spin_limit=0):
+                 raster_rows=0, xcds=0, share="proportional", fixup="auto", spin_limit=0, relayout=0):
         self._h = ctypes.c_void_p()
         o = default_options()
+        o.relayout = int(relayout)
         if tile:
             o.tile_m, o.tile_n, o.tile_k = (int(x) for x in tile[:3])
             if len(tile) > 3:

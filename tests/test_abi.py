@@ -146,10 +146,11 @@ def test_workspace_scales_with_grid_not_problem():
         big = sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
                       tile=tile)
         assert small.info()["tile"][:3] == big.info()["tile"][:3] == tile
-        assert small.workspace_size() == big.workspace_size()
+        # the fix-up part (the rest, if any, holds a re-laid-out operand)
+        assert small.info()["fixup_ws_bytes"] == big.info()["fixup_ws_bytes"]
     # one FP32 partial tile per workgroup: the small tile needs a quarter of the partial storage
     w = {t: sk.Plan(3000, 3000, 40960, ta=sk.BF16, policy="sk", force_g=64, num_cus=256, occupancy=1,
-                    tile=t).workspace_size() for t in [(256, 256, 64), (128, 128, 64)]}
+                    tile=t).info()["fixup_ws_bytes"] for t in [(256, 256, 64), (128, 128, 64)]}
     assert w[(256, 256, 64)] - w[(128, 128, 64)] == 64 * (256 * 256 - 128 * 128) * 4
     dp = sk.Plan(3000, 3000, 4096, ta=sk.BF16, policy="dp", num_cus=256, occupancy=1)
     assert dp.workspace_size() == 0
@@ -302,13 +303,13 @@ def test_spin_limit_option():
     for lim in (0, 1, 1000):
         p = sk.Plan(300, 200, 900, ta=sk.BF16, policy="sk", num_cus=256, occupancy=2, spin_limit=lim)
         assert p.info()["grid"] > 0
-    # 14 int32 fields, in the header's order; the padding after them is not
+    # 15 int32 fields, in the header's order; the padding after them is not
     # touched by the library
-    assert ctypes.sizeof(sk.Options) == 14 * 4
-    guard = (ctypes.c_int32 * 16)(*([0x5A5A5A5A] * 16))
+    assert ctypes.sizeof(sk.Options) == 15 * 4
+    guard = (ctypes.c_int32 * 17)(*([0x5A5A5A5A] * 17))
     L.skgemm_default_options(ctypes.cast(guard, ctypes.POINTER(sk.Options)))
-    assert list(guard[:14]) == [sk.POLICY["auto"], 0, 0, 0, 0, 2] + [0] * 8
-    assert list(guard[14:]) == [0x5A5A5A5A] * 2
+    assert list(guard[:15]) == [sk.POLICY["auto"], 0, 0, 0, 0, 2] + [0] * 9
+    assert list(guard[15:]) == [0x5A5A5A5A] * 2
 
 
 def test_f64_plans():
@@ -534,3 +535,62 @@ def test_plan_log_environment_switch():
     env["SKGEMM_LOG"] = "0"
     quiet = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert quiet.returncode == 0 and "skgemm: plan" not in quiet.stderr
+
+
+def test_operand_relayout_plan():
+    """Single-GEMM plans keep workspace for a 128-byte-line copy of an operand
+    only where its lines (leading dimension = line length) are misaligned and
+    the model says the copy pays; the workspace is the fix-up part plus those
+    256-byte-aligned regions. Grouped, batched and convolution plans never do."""
+    sk = _lib()
+    seen = set()
+    for (M, N, K), occ, lc in itertools.product(
+            [(777, 5555, 3333), (8001, 8001, 8001), (3333, 777, 5555), (4427, 2519, 3013), (1536, 2560, 3072),
+             (228, 173, 292), (4096, 4096, 4096), (8000, 8000, 8000)], [1, 2], [sk.ROW_MAJOR, sk.COL_MAJOR]):
+        p = sk.Plan(M, N, K, lc=lc, ta=sk.BF16, num_cus=256, occupancy=occ)
+        i = p.info()
+        Ml, Nl = i["M"], i["N"]
+        lines_cols = [(Ml, K) if i["a_kcontig"] else (K, Ml), (Nl, K) if i["b_kcontig"] else (K, Nl)]
+        ws = i["fixup_ws_bytes"]
+        # the copies go after the fix-up part, never over the shared flag area
+        off = max(ws, 256 + 4096 * 128)
+        for x, key in enumerate(("pack_a", "pack_b")):
+            lines, cols = lines_cols[x]
+            if i[key]:
+                assert (cols * 2) % 128 != 0, (M, N, K, key)
+                off = ((off + 255) // 256) * 256 + ((lines * (-(-cols // 64) * 64) * 2 + 255) // 256) * 256
+                ws = off
+                seen.add(key)
+        assert p.workspace_size() == ws, (M, N, K, occ, lc)
+        if M % 64 == 0 and N % 64 == 0 and K % 64 == 0:
+            assert not i["pack_a"] and not i["pack_b"]
+    assert seen == {"pack_a", "pack_b"}
+    g = sk.GroupedPlan([777, 3001], [5555, 4001], [3333, 3333], ta=sk.BF16, num_cus=256, occupancy=1).info()
+    b = sk.BatchedPlan(4, 777, 5555, 3333, ta=sk.BF16, num_cus=256, occupancy=1).info()
+    c = sk.ConvPlan(8, 57, 57, 64, 96, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
+    for info in (g, b, c):
+        assert info["pack_a"] == 0 and info["pack_b"] == 0
+
+
+def test_relayout_option():
+    """relayout: -1 never copies, 1 / 2 / 3 copy the caller's A / B / both
+    whenever their lines are misaligned (column-major C swaps the launched
+    operands, not the caller's names), 0 leaves it to the model; other values
+    are refused."""
+    sk = _lib()
+    M, N, K = 777, 5555, 3333          # K and N both misaligned in BF16
+    for lc in (sk.ROW_MAJOR, sk.COL_MAJOR):
+        for rl, want in ((-1, (0, 0)), (1, (1, 0)), (2, (0, 1)), (3, (1, 1))):
+            i = sk.Plan(M, N, K, lc=lc, ta=sk.BF16, num_cus=256, occupancy=1, relayout=rl).info()
+            got = (i["pack_a"], i["pack_b"])
+            assert got == (want[::-1] if lc == sk.COL_MAJOR else want), (lc, rl, got)
+    aligned = sk.Plan(1024, 2048, 4096, ta=sk.BF16, num_cus=256, occupancy=1, relayout=3).info()
+    assert (aligned["pack_a"], aligned["pack_b"]) == (0, 0)
+    L = sk.lib()
+    h = ctypes.c_void_p()
+    o = sk.default_options()
+    o.num_cus, o.occupancy = 256, 1
+    for bad in (4, -2):
+        o.relayout = bad
+        assert L.skgemm_plan(ctypes.byref(h), 64, 64, 64, 0, 0, 0, sk.BF16, sk.BF16, sk.BF16,
+                             ctypes.byref(o)) == sk.ERR_INVALID_ARG

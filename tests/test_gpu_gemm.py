@@ -652,3 +652,50 @@ def test_matmul_fast_path_repeated_signatures():
     pad[:, :K] = A                                     # leading dimension K + 64
     for _ in range(3):
         assert rel(mm(pad[:, :K], B, out_dtype=torch.float32), ref) <= TOL_16_OUT32
+
+
+@pytest.mark.parametrize("c_col", [False, True])
+def test_operand_relayout_bitwise_and_parity(c_col):
+    """Plans that copy a misaligned operand into 128-byte lines before the
+    GEMM: the result is bitwise the one of the same plan run without the copy
+    (a workspace of only the fix-up part) and of operands passed with aligned
+    leading dimensions (no copy at run time), and matches the FP64 oracle on
+    sampled rows."""
+    lc = sk().COL_MAJOR if c_col else sk().ROW_MAJOR
+    cands = [(777, 5555, 3333), (2049, 6001, 4001), (3333, 777, 5555), (4427, 2519, 3013), (1482, 2519, 3013)]
+    found = 0
+    for (M, N, K) in cands:
+        # relayout=3: copy both operands whenever misaligned (the mechanism,
+        # whatever the model would choose)
+        plan = sk().Plan(M, N, K, lc=lc, ta=sk().BF16, relayout=3)
+        info = plan.info()
+        if not (info["pack_a"] or info["pack_b"]):
+            continue
+        found += 1
+        g = W.rng(M)
+        A = torch.from_numpy(W.normal_f32(g, (M, K))).to(torch.bfloat16).to(dev())
+        B = torch.from_numpy(W.normal_f32(g, (K, N))).to(torch.bfloat16).to(dev())
+        # aligned-line copies of the same values (leading dimensions padded to 64 elements)
+        Ap = torch.zeros((M, -(-K // 64) * 64), dtype=torch.bfloat16, device=dev())
+        Bp = torch.zeros((K, -(-N // 64) * 64), dtype=torch.bfloat16, device=dev())
+        Ap[:, :K] = A
+        Bp[:, :N] = B
+        stream = torch.cuda.current_stream().cuda_stream
+
+        def run(a, lda, b, ldb, ws_bytes):
+            C = torch.full((N, M) if c_col else (M, N), float("nan"), dtype=torch.bfloat16, device=dev())
+            ws = torch.zeros(max(ws_bytes, 256), dtype=torch.uint8, device=dev())
+            plan.run(a.data_ptr(), lda, b.data_ptr(), ldb, C.data_ptr(), M if c_col else N, 1.0, 0.0, None, None,
+                     ws.data_ptr() if ws_bytes else None, ws_bytes, stream)
+            torch.cuda.synchronize()
+            return C.t() if c_col else C
+
+        full = run(A, K, B, N, plan.workspace_size())
+        bare = run(A, K, B, N, info["fixup_ws_bytes"])
+        aligned = run(Ap, Ap.shape[1], Bp, Bp.shape[1], plan.workspace_size())
+        assert torch.equal(full, bare), (M, N, K)
+        assert torch.equal(full, aligned), (M, N, K)
+        rows = np.sort(W.rng(7).choice(M, 24, replace=False))
+        ref = og.gemm_rows_f64(to_f64(A), to_f64(B), rows)
+        assert og.rel_frobenius(to_f64(full[torch.from_numpy(rows).to(dev())]), ref) <= TOL_16, (M, N, K)
+    assert found == len(cands)
