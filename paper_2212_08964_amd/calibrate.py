@@ -10,7 +10,21 @@ events, and fits (a, b, c, d) by least squares.  It
 prints the constants normalised to c = 1, in the form the library's model
 table uses.
 
+A second mode fits all five constants of every 16-bit GEMM tile at once on a
+seeded sweep of random shapes (log-uniform M, N, K in [128, 8192], half of
+them multiples of 128, half with +1..127 offsets): each shape is planned with
+the automatic policy on each tile, timed, and (a, b, c, d, e) are fitted by
+least squares on relative error to the planner's estimate of those plans,
+which is linear in the constants once a plan is resolved.  The microbenchmark
+grids above pin the constants of one workgroup per CU on tile-aligned
+problems; the sweep fit reports how well a set of constants predicts the
+shapes the planner meets (ragged edges, co-resident workgroups, hybrids).
+Constants fitted this way were measured in the library and not adopted:
+fitted on warm, repeated timings, they chose splits that lost in a pass of
+distinct, cold GEMMs.
+
 Usage: python -m paper_2212_08964_amd.calibrate [bf16|f16|f32|f64] [BMxBNxBK[xWAVES], e.g. 128x128x64x8]
+       python -m paper_2212_08964_amd.calibrate sweep [n_shapes] [seed]
 """
 from __future__ import annotations
 
@@ -22,6 +36,131 @@ def model_terms(t, ipt, g):
     ipc = math.ceil(t * ipt / g)
     peers = math.ceil(ipt / ipc)
     return [1.0, 1.0 if peers > 1 else 0.0, float(ipc), float(peers - 1)]
+
+
+def estimate_terms(info):
+    """Coefficients of (a, b, c, d, e) in the planner's compute-time estimate
+    of a resolved single-GEMM plan: data-parallel plans run ceil(t/p) waves,
+    a partial wave at the per-iteration time interpolated between c (one
+    busy slot) and e (all p slots busy); Stream-K plans pay a workgroup's
+    data-parallel tiles, a, the fix-up terms b and d, and their share of
+    iterations at the time for g_sk busy slots.  The estimate is the dot
+    product of these coefficients with the constants."""
+    t, ipt, p = info["t"], info["ipt"], info["p"]
+    g, skt, grid = info["g_sk"], info["sk_tiles"], info["grid"]
+    if t == 0:
+        return None
+    if g == 0:
+        full, rem = divmod(t, p)
+        f = min(1.0, rem / p)
+        part = 1.0 if rem else 0.0
+        return [full + part, 0.0, part * ipt * (1.0 - f), 0.0, full * ipt + part * ipt * f]
+    ipc = math.ceil(skt * ipt / g)
+    peers = max(1, math.ceil(ipt / ipc))
+    dp_per_wg = math.ceil((t - skt) / grid)
+    f = min(1.0, g / p)
+    return [1.0 + dp_per_wg, 1.0 if peers > 1 else 0.0, (1.0 - f) * ipc, float(peers - 1),
+            dp_per_wg * ipt + f * ipc]
+
+
+def sweep_shapes(n, seed):
+    """Log-uniform shapes in [128, 8192]: the first half rounded to multiples
+    of 128, the second half a multiple of 128 plus 1..127."""
+    import numpy as np
+    g = np.random.default_rng(seed)
+    d = np.exp(g.uniform(math.log(128), math.log(8192), size=(n, 3)))
+    out = []
+    for i in range(n):
+        if i < n // 2:
+            v = np.maximum(np.rint(d[i] / 128.0), 1) * 128
+        else:
+            v = np.floor(d[i] / 128.0) * 128 + g.integers(1, 128, size=3)
+        out.append(tuple(int(x) for x in v))
+    return out
+
+
+SWEEP_TILES = [(256, 256, 64, 8), (128, 128, 64, 4), (128, 128, 64, 8), (64, 256, 64, 4), (256, 64, 64, 4)]
+
+
+def fit_sweep(n=1000, seed=1, dtype="bf16", verbose=True):
+    """Times every shape of the seeded sweep on every 16-bit GEMM tile (the
+    automatic policy on that tile; a column-major B where the tile has no
+    kernel for a row-major one) and fits (a, b, c, d, e) per tile.  Returns
+    {tile: (constants, rms relative error of the fit, of the current
+    constants, number of shapes)}."""
+    import ctypes
+    import numpy as np
+    import torch
+
+    from . import skgemm as sk
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    cdt = {"bf16": sk.BF16, "f16": sk.F16}[dtype]
+    L = sk.lib()
+    stream = torch.cuda.current_stream()
+    ws = torch.zeros(64 << 20, dtype=torch.uint8, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    rows = {tile: ([], [], []) for tile in SWEEP_TILES}
+    for n_done, (M, N, K) in enumerate(sweep_shapes(n, seed)):
+        A = torch.randn((M, K), generator=gen, device="cuda").to(tdt)
+        Bk = torch.randn((K, N), generator=gen, device="cuda").to(tdt)
+        Bn = None
+        C = torch.empty((M, N), device="cuda", dtype=tdt)
+        for tile in SWEEP_TILES:
+            lb, B = sk.ROW_MAJOR, Bk
+            try:
+                plan = sk.Plan(M, N, K, ta=cdt, tc=cdt, policy="auto", tile=tile)
+            except sk.SkgemmError:
+                try:
+                    plan = sk.Plan(M, N, K, lb=sk.COL_MAJOR, ta=cdt, tc=cdt, policy="auto", tile=tile)
+                except sk.SkgemmError:
+                    continue
+                if Bn is None:
+                    Bn = Bk.t().contiguous()
+                lb, B = sk.COL_MAJOR, Bn
+            info = plan.info()
+            terms = estimate_terms(info)
+            if terms is None:
+                continue
+            nws = plan.workspace_size()
+            if nws > ws.numel():
+                torch.cuda.synchronize()
+                ws = torch.zeros(nws, dtype=torch.uint8, device="cuda")
+            args = (plan.handle, ctypes.c_void_p(A.data_ptr()), K, ctypes.c_void_p(B.data_ptr()),
+                    N if lb == sk.ROW_MAJOR else K, ctypes.c_void_p(C.data_ptr()), N, ctypes.c_float(1.0),
+                    ctypes.c_float(0.0), None, None, ctypes.c_void_p(ws.data_ptr()), nws,
+                    ctypes.c_void_p(stream.cuda_stream))
+            st = L.skgemm_run(*args)
+            if st:
+                raise sk.SkgemmError(st, "skgemm_run")
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                e0.record()
+                for _ in range(8):
+                    L.skgemm_run(*args)
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e3 / 8)
+            ts.sort()
+            rows[tile][0].append(terms)
+            rows[tile][1].append(ts[2])
+            rows[tile][2].append(plan.model_constants())
+        if verbose and n_done % 100 == 0:
+            print(f"{n_done} shapes", flush=True)
+        del A, Bk, Bn, C
+    out = {}
+    for tile, (X, y, cur) in rows.items():
+        if not y:
+            continue
+        X, y, cur = np.array(X), np.array(y), np.array(cur)
+        w = 1.0 / y
+        coef = np.linalg.lstsq(X * w[:, None], y * w, rcond=None)[0]
+        rms = lambda pred: float(np.sqrt(np.mean(np.log(y / np.maximum(pred, 1e-3)) ** 2)))
+        out[tile] = (tuple(float(v) for v in coef), rms(X @ coef), rms(np.sum(X * cur, axis=1)), len(y))
+    return out
 
 
 def _launcher(sk, plan, A, B, C, ws, nws):
@@ -137,6 +276,14 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "sweep":
+        n = int(sys.argv[2]) if len(sys.argv) > 2 else 1000
+        seed = int(sys.argv[3]) if len(sys.argv) > 3 else 1
+        for tile, (coef, rms_fit, rms_cur, cnt) in fit_sweep(n, seed).items():
+            a, b, c, d, e = coef
+            print(f"tile {tile}: a={a:.3f} b={b:.3f} c={c:.3f} d={d:.3f} e={e:.3f}  rms relative error "
+                  f"{rms_fit:.3f} (current constants {rms_cur:.3f}) over {cnt} shapes", flush=True)
+        return
     dtype = sys.argv[1] if len(sys.argv) > 1 else "bf16"
     tile = tuple(int(x) for x in sys.argv[2].split("x")) if len(sys.argv) > 2 else None
     norm, raw, X, y = measure(dtype, tile=tile)

@@ -537,6 +537,42 @@ def test_plan_log_environment_switch():
     assert quiet.returncode == 0 and "skgemm: plan" not in quiet.stderr
 
 
+def test_calibrate_estimate_terms_match_planner():
+    """calibrate.estimate_terms, dotted with a plan's model constants, is the
+    planner's own estimate (printed by SKGEMM_LOG) on every 16-bit GEMM tile
+    and policy, so constants fitted to it mean what the planner uses; where
+    the estimate is larger, the plan's HBM bound set it."""
+    import json
+    import subprocess
+    import sys
+    code = ("import sys, json; sys.path.insert(0, %r)\n"
+            "from paper_2212_08964_amd import skgemm as sk, calibrate as cal\n"
+            "for (M, N, K) in cal.sweep_shapes(40, 3):\n"
+            "    for tile in cal.SWEEP_TILES:\n"
+            "        occ = 1 if tile[0] * tile[1] == 65536 else 2\n"
+            "        for lb in (sk.ROW_MAJOR, sk.COL_MAJOR):\n"
+            "            try:\n"
+            "                p = sk.Plan(M, N, K, lb=lb, ta=sk.BF16, num_cus=256, occupancy=occ, tile=tile)\n"
+            "            except sk.SkgemmError:\n"
+            "                continue\n"
+            "            t = cal.estimate_terms(p.info())\n"
+            "            print(json.dumps(sum(x * y for x, y in zip(t, p.model_constants()))), flush=True)\n"
+            "            break\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, SKGEMM_LOG="1"),
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    mine = [json.loads(x) for x in out.stdout.split()]
+    logged = [float(ln.split("est_us=")[1].split()[0]) for ln in out.stderr.splitlines()
+              if ln.startswith("skgemm: plan")]
+    assert len(mine) == len(logged) == 40 * 5
+    equal = 0
+    for m, e in zip(mine, logged):
+        assert e >= m - 0.006, (m, e)
+        equal += abs(e - m) <= 0.006
+    assert equal >= 0.9 * len(mine)
+
+
 def test_operand_relayout_plan():
     """Single-GEMM plans keep workspace for a 128-byte-line copy of an operand
     only where its lines (leading dimension = line length) are misaligned and
