@@ -96,7 +96,12 @@ typedef struct {
                                          most 64 columns); FP8 256x256x128 or
                                          128x128x128; FP64 64x64x16 or 128x128x16.
                                          A named tile with no kernel for the
-                                         operands' contiguity: SKGEMM_ERR_UNSUPPORTED */
+                                         operands' contiguity: SKGEMM_ERR_UNSUPPORTED.
+                                         A 16-bit 128x128x64 plan whose grid is at
+                                         most the CU count runs an eight-wave
+                                         kernel with three LDS stages (one
+                                         workgroup per CU; plan_info field 29)
+                                         unless tile_waves asks for four */
     int32_t hybrid_min_waves;     /* full waves needed for the two-tile hybrid (default 2) */
     int32_t num_cus;              /* >0: plan for this many CUs instead of querying */
     int32_t occupancy;            /* >0: workgroups per CU instead of querying */
@@ -277,8 +282,9 @@ skgemm_status_t skgemm_realtime_hz(int64_t* hz);
  * strided batched plan, whose fields 7 and 8 describe one problem and
  * field 9 counts the tiles of the whole batch), 26 / 27 the launched A / B is
  * copied to 128-byte aligned lines when passed misaligned (0/1), 28 bytes of
- * the fix-up part of the workspace.
- * n is the capacity of info; up to 29 values are written. */
+ * the fix-up part of the workspace, 29 LDS stages of the kernel's MAC-loop
+ * pipeline (k-slabs in flight = stages - 1).
+ * n is the capacity of info; up to 30 values are written. */
 skgemm_status_t skgemm_plan_info(skgemm_plan_t plan, int64_t* info, int32_t n);
 
 /* Analytical grid-size model constants (Analytical Modeling subsection)

@@ -55,6 +55,7 @@ const void* kernel_table(bool akc, bool bkc, int v) {
             case 5: return akc_only<DT, 5, FULL>(akc, bkc);    // skinny tile
             case 6: return bkc_only<DT, 6, FULL>(akc, bkc);    // tall tile
             case 7: return kc_only<DT, 7, FULL>(akc, bkc);     // tall tile, convolution
+            case 8: return any_layout<DT, 8, FULL>(akc, bkc);  // small tile, three stages
             default: return nullptr;
         }
     } else if constexpr (DT == DT_F8) {

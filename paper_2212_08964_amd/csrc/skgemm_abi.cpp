@@ -112,6 +112,7 @@ TileCfg tile_for(int dt, int v) {
     if (v == 4 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 5 && (dt == DT_BF16 || dt == DT_F16)) return kTile16K;     // skinny
     if ((v == 6 || v == 7) && (dt == DT_BF16 || dt == DT_F16)) return kTile16T;     // tall
+    if (v == kVariantDeep && (dt == DT_BF16 || dt == DT_F16)) return kTile16D;      // three stages
     if (v == 1 && dt == DT_F8) return kTileF8S;
     if (v == 1 && dt == DT_F64) return kTileF64L;
     return TileCfg{0, 0, 0};
@@ -599,7 +600,8 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
     skgemm_plan_s* cand[kVariants] = {};
     skgemm_status_t last = SKGEMM_ERR_UNSUPPORTED;
     for (int v = 0; v < kVariants; ++v) {
-        if (is_conv_variant(v) != base->conv) continue;     // the convolution kernels are variants 3 and 4
+        if (v == kVariantDeep) continue;                   // substituted below, not a candidate
+        if (is_conv_variant(v) != base->conv) continue;     // the convolution kernels are variants 3, 4 and 7
         // the skinny tile only where every launched problem has at most its
         // 64 rows (unless the options name it)
         if (v == 5 && !named) {
@@ -686,6 +688,31 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
         }
     }
     if (!best) return last;
+    // A small-tile plan whose grid fits one workgroup per CU runs the
+    // eight-wave tile on three LDS stages instead: same tile, schedule and
+    // workspace, two k-slabs in flight instead of one.  A lone workgroup on
+    // its CU waits on load latency in the two-stage pipeline; measured on
+    // one-wave data-parallel problems (BF16, 256 tiles of 128x128) the
+    // three-stage kernel runs 9-18 % faster than either two-stage layout,
+    // and loses where tiles outnumber CUs (its 96 KiB of LDS allow one
+    // workgroup per CU).  Not where the options ask for four waves.  The plan
+    // keeps the model constants it was resolved with (the grid fits the new
+    // capacity, so every choice the model made stands).
+    if ((best->variant == 1 || best->variant == 2) && (o.tile_waves == 0 || o.tile_waves == 8) && best->grid > 0 &&
+        best->occ > 0 && kernel_exists(best->dtype, best->akc, best->bkc, kVariantDeep)) {
+        const int cus = best->p / best->occ;
+        int occ = 1;            // its LDS leaves room for one workgroup per CU
+        if (o.occupancy == 0) {
+            int qc = 0, qo = 0;
+            if (device_capacity(best->dtype, best->akc, best->bkc, kVariantDeep, &qc, &qo) != SKGEMM_OK) qo = 0;
+            occ = qo;
+        }
+        if (occ >= 1 && best->grid <= cus) {
+            best->variant = kVariantDeep;
+            best->occ = occ;
+            best->p = cus * occ;
+        }
+    }
     *out = best;
     return SKGEMM_OK;
 }
@@ -775,11 +802,12 @@ static void log_plan(const skgemm_plan_s* pl) {
     const double est = plan_estimate(pl, nullptr);
     std::fprintf(stderr,
                  "skgemm: plan %s M=%lld N=%lld K=%lld G=%d batch=%lld dtype=%d tile=%dx%dx%d/%d policy=%s "
-                 "tiles=%d ipt=%d sk_tiles=%d g_sk=%d grid=%d p=%d est_us=%.2f pack=%d%d\n",
+                 "tiles=%d ipt=%d sk_tiles=%d g_sk=%d grid=%d p=%d est_us=%.2f pack=%d%d stages=%d\n",
                  kind, (long long)pl->M, (long long)pl->N, (long long)pl->K, pl->G, (long long)pl->batch, pl->dtype,
                  pl->BM, pl->BN, pl->BK, kernel_threads(pl->dtype, pl->variant) / 64,
                  pl->policy >= 0 && pl->policy <= 5 ? kPol[pl->policy] : "?", pl->t, pl->ipt, pl->sk_tiles,
-                 pl->g_sk, pl->grid, pl->p, est, pl->pack[0] ? 1 : 0, pl->pack[1] ? 1 : 0);
+                 pl->g_sk, pl->grid, pl->p, est, pl->pack[0] ? 1 : 0, pl->pack[1] ? 1 : 0,
+                 tile_for(pl->dtype, pl->variant).ns);
 }
 
 skgemm_status_t skgemm_plan(skgemm_plan_t* out, int64_t M, int64_t N, int64_t K, skgemm_layout_t la,
@@ -1217,13 +1245,14 @@ skgemm_status_t skgemm_grouped_run_traced(skgemm_plan_t plan, const void* table_
 
 skgemm_status_t skgemm_plan_info(skgemm_plan_t pl, int64_t* info, int32_t n) {
     if (!pl || !info || n < 0) return SKGEMM_ERR_INVALID_ARG;
-    const int64_t v[29] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
+    const int64_t v[30] = {pl->Ml, pl->Nl, pl->Kl, pl->swapped ? 1 : 0, pl->BM, pl->BN, pl->BK, pl->tm, pl->tn,
                            pl->t, pl->ipt, pl->policy, pl->sk_tiles, pl->g_sk, pl->grid, pl->sk_first ? 1 : 0,
                            pl->p, pl->hybrid_min_waves, pl->akc ? 1 : 0, pl->bkc ? 1 : 0, pl->G,
                            pl->share_prop ? SKGEMM_SHARE_PROPORTIONAL : SKGEMM_SHARE_LEADING, pl->coop_s,
                            pl->occ, kernel_threads(pl->dtype, pl->variant) / 64, pl->batch,
-                           pl->pack[0] ? 1 : 0, pl->pack[1] ? 1 : 0, int64_t(pl->ws_bytes)};
-    for (int i = 0; i < n && i < 29; ++i) info[i] = v[i];
+                           pl->pack[0] ? 1 : 0, pl->pack[1] ? 1 : 0, int64_t(pl->ws_bytes),
+                           tile_for(pl->dtype, pl->variant).ns};
+    for (int i = 0; i < n && i < 30; ++i) info[i] = v[i];
     return SKGEMM_OK;
 }
 

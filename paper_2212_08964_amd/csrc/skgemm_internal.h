@@ -36,6 +36,7 @@ constexpr TileCfg kTileF8 = {256, 256, 128, 2};
 constexpr TileCfg kTileF8S = {128, 128, 128, 2};   // fp8, small-tile variant
 constexpr TileCfg kTileF64 = {64, 64, 16, 2};
 constexpr TileCfg kTileF64L = {128, 128, 16, 2};   // fp64, large-tile variant
+constexpr TileCfg kTile16D = {128, 128, 64, 3};   // bf16 and f16, small tile on three LDS stages
 
 // One problem of a grouped launch (device table entry, 128 bytes).  Shapes are
 // as launched (operands already swapped when C is column-major).
@@ -109,8 +110,12 @@ struct KArgs {
 // implicit-GEMM convolution gather for A.  5: the skinny 64x256 16-bit tile
 // (four waves side by side) for problems of at most 64 rows; 6: the 256x64
 // tile (four waves stacked) for problems of at most 64 columns, and 7 the
-// same with the convolution gather (at most 64 output channels).
-constexpr int kVariants = 8;
+// same with the convolution gather (at most 64 output channels).  8: the
+// eight-wave 128x128 16-bit tile on three LDS stages (two slabs in flight),
+// one workgroup per CU; the planner substitutes it for variants 1 and 2
+// where the grid fits one workgroup per CU, never as a candidate of its own.
+constexpr int kVariants = 9;
+constexpr int kVariantDeep = 8;
 constexpr bool is_conv_variant(int v) { return v == 3 || v == 4 || v == 7; }
 
 // Copy `lines` lines of `cols` elements of eb bytes (line i at src + i * ld)

@@ -73,6 +73,12 @@ template <> struct Cfg<DT_F16, 1> { static constexpr int EB = 2, BM = kTile16S.b
 template <> struct Cfg<DT_BF16, 1> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 2, NS = kTile16S.ns; };
 template <> struct Cfg<DT_F16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
 template <> struct Cfg<DT_BF16, 2> { static constexpr int EB = 2, BM = kTile16S.bm, BN = kTile16S.bn, BK = kTile16S.bk, WM = 2, WN = 4, NS = kTile16S.ns; };
+// The same eight-wave tile on three LDS stages (96 KiB: one workgroup per
+// CU), so two k-slabs are in flight while one is consumed: a lone workgroup
+// on its CU then hides the load latency the two-stage pipeline exposes.  The
+// register budget stays that of two workgroups per CU.
+template <> struct Cfg<DT_F16, 8> { static constexpr int EB = 2, BM = kTile16D.bm, BN = kTile16D.bn, BK = kTile16D.bk, WM = 2, WN = 4, NS = kTile16D.ns, WPE = 4; };
+template <> struct Cfg<DT_BF16, 8> { static constexpr int EB = 2, BM = kTile16D.bm, BN = kTile16D.bn, BK = kTile16D.bk, WM = 2, WN = 4, NS = kTile16D.ns, WPE = 4; };
 // Skinny 16-bit tile for problems of at most 64 rows: four waves side by side
 // over 256 columns (64x64 each), so a short A panel is padded to 64 rows, not
 // 128 or 256.

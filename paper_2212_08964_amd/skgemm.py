@@ -38,7 +38,8 @@ EXPORTED = [
 
 INFO_FIELDS = ["M", "N", "K", "swapped", "BM", "BN", "BK", "tm", "tn", "t", "ipt", "policy",
                "sk_tiles", "g_sk", "grid", "sk_first", "p", "hybrid_min_waves", "a_kcontig", "b_kcontig", "G",
-               "share", "coop_s", "occupancy", "waves", "batch", "pack_a", "pack_b", "fixup_ws_bytes"]
+               "share", "coop_s", "occupancy", "waves", "batch", "pack_a", "pack_b", "fixup_ws_bytes",
+               "stages"]
 SHARE = {"proportional": 0, "leading": 1}
 SHARE_NAME = {v: k for k, v in SHARE.items()}
 FIXUP = {"auto": 0, "owner": 1}

@@ -537,6 +537,41 @@ def test_plan_log_environment_switch():
     assert quiet.returncode == 0 and "skgemm: plan" not in quiet.stderr
 
 
+def test_three_stage_small_tile_substitution():
+    """A 16-bit 128x128x64 plan whose grid fits one workgroup per CU runs the
+    eight-wave kernel on three LDS stages (occupancy 1), with the schedule,
+    workspace and model constants of the plan it replaces; never for larger
+    grids, four requested waves, other tiles, other input types or
+    convolutions."""
+    sk = _lib()
+    kw = dict(num_cus=256, occupancy=2)
+    for ta in (sk.BF16, sk.F16):
+        i = sk.Plan(2048, 2048, 1024, ta=ta, policy="dp", tile=(128, 128, 64), **kw).info()   # 256 tiles
+        assert (i["stages"], i["waves"], i["occupancy"], i["p"], i["grid"]) == (3, 8, 1, 256, 256)
+        i = sk.Plan(2048, 4096, 1024, ta=ta, policy="dp", tile=(128, 128, 64), **kw).info()   # 512 tiles
+        assert (i["stages"], i["occupancy"], i["p"]) == (2, 2, 512)
+        i = sk.Plan(2048, 2048, 1024, ta=ta, policy="dp", tile=(128, 128, 64, 4), **kw).info()
+        assert (i["stages"], i["waves"]) == (2, 4)
+        assert sk.Plan(2048, 2048, 1024, ta=ta, tile=(256, 256, 64), **kw).info()["stages"] == 2
+    for g, want in ((200, 3), (256, 3), (300, 2)):
+        deep = sk.Plan(1000, 1000, 5000, ta=sk.BF16, policy="sk", force_g=g, tile=(128, 128, 64, 8), **kw)
+        i = deep.info()
+        assert (i["g_sk"], i["stages"]) == (g, want)
+        four = sk.Plan(1000, 1000, 5000, ta=sk.BF16, policy="sk", force_g=g, tile=(128, 128, 64, 4), **kw)
+        assert deep.schedule() == four.schedule()
+        assert deep.workspace_size() == four.workspace_size()
+        eight = sk.Plan(1000, 1000, 5000, ta=sk.BF16, policy="sk", force_g=300, tile=(128, 128, 64, 8), **kw)
+        assert deep.model_constants() == eight.model_constants()
+    # the automatic plan of a one-wave problem; other types and launch kinds never
+    assert sk.Plan(1536, 2048, 2048, ta=sk.BF16, **kw).info()["stages"] in (2, 3)
+    assert sk.Plan(1024, 1024, 1024, lb=sk.COL_MAJOR, ta=sk.F8E4M3, tc=sk.BF16, tile=(128, 128, 128), policy="dp", **kw).info()["stages"] == 2
+    assert sk.Plan(1024, 1024, 1024, ta=sk.F32, tc=sk.F32, **kw).info()["stages"] == 2
+    assert sk.Plan(512, 512, 512, ta=sk.F64, tc=sk.F64, tile=(128, 128, 16), **kw).info()["stages"] == 2
+    assert sk.ConvPlan(2, 16, 16, 64, 128, 3, 3, (1, 1), ta=sk.BF16, tile=(128, 128, 64), **kw).info()["stages"] == 2
+    g = sk.GroupedPlan([300, 500], [600, 400], [700, 700], ta=sk.BF16, tile=(128, 128, 64), **kw).info()
+    assert g["stages"] == (3 if g["grid"] <= 256 else 2)
+
+
 def test_calibrate_estimate_terms_match_planner():
     """calibrate.estimate_terms, dotted with a plan's model constants, is the
     planner's own estimate (printed by SKGEMM_LOG) on every 16-bit GEMM tile

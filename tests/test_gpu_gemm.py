@@ -699,3 +699,46 @@ def test_operand_relayout_bitwise_and_parity(c_col):
         ref = og.gemm_rows_f64(to_f64(A), to_f64(B), rows)
         assert og.rel_frobenius(to_f64(full[torch.from_numpy(rows).to(dev())]), ref) <= TOL_16, (M, N, K)
     assert found == len(cands)
+
+
+@pytest.mark.parametrize("b_col", [False, True])
+@pytest.mark.parametrize("policy,g", [("dp", 0), ("sk", 0), ("sk", 200), ("auto", 0)])
+def test_three_stage_tile_bitwise_and_exact(policy, g, b_col):
+    """Where a 16-bit 128x128x64 plan's grid fits one workgroup per CU, the
+    eight-wave kernel on three LDS stages runs it: the result is bitwise the
+    four-wave two-stage kernel's on the same schedule (same k-order per output
+    element), integer-valued inputs give the oracle's exact result, and its
+    trace is the enumerator's schedule."""
+    from helpers import resolved
+    shapes = [(1000, 1500, 777), (2048, 2048, 1024), (384, 4096, 5000), (129, 130, 131), (640, 3456, 896)]
+    found = 0
+    for (M, N, K) in shapes:
+        lb = sk().COL_MAJOR if b_col else sk().ROW_MAJOR
+        plan = sk().Plan(M, N, K, lb=lb, ta=sk().BF16, tc=sk().F32, policy=policy, force_g=g, tile=(128, 128, 64, 8))
+        info = plan.info()
+        if info["stages"] != 3:
+            assert info["grid"] > info["p"] // info["occupancy"] or info["grid"] > 256, (M, N, K)
+            continue
+        found += 1
+        pol, fg = resolved(info)
+        four = dict(policy=pol, force_g=fg, tile=(128, 128, 64, 4))
+        assert sk().Plan(M, N, K, lb=lb, ta=sk().BF16, tc=sk().F32, **four).schedule() == plan.schedule()
+        gen = W.rng(M + N + K)
+        for integer in (False, True):
+            make = W.integer_f32 if integer else W.normal_f32
+            A = torch.from_numpy(make(gen, (M, K))).to(torch.bfloat16).to(dev())
+            B = torch.from_numpy(make(gen, (K, N))).to(torch.bfloat16).to(dev())
+            if b_col:
+                B = B.t().contiguous().t()
+            c8 = mm(A, B, out_dtype=torch.float32, policy=pol, force_g=fg, tile=(128, 128, 64, 8))
+            c4 = mm(A, B, out_dtype=torch.float32, **four)
+            assert torch.equal(c8, c4), (M, N, K, integer)
+            if integer:
+                assert np.array_equal(to_f64(c8), oracle(A, B)), (M, N, K)
+        # the traced run of the same plan follows the enumerator's schedule
+        tr = torch.full((plan.trace_capacity() * 8,), -7, dtype=torch.int32, device=dev())
+        mm(A, B, out_dtype=torch.float32, policy=pol, force_g=fg, tile=(128, 128, 64, 8), trace=tr)
+        recs = [tuple(int(v) for v in rec) for rec in tr.cpu().numpy().reshape(-1, 8) if rec[0] != -7]
+        ref = oracle_plan_for(info, plan.model_constants(), pol, force_g=fg)
+        assert records_to_schedule(recs, info["grid"]) == S.enumerate_schedule(ref), (M, N, K)
+    assert found >= 2
