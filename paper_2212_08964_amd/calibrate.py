@@ -245,10 +245,14 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
     coef, *_ = np.linalg.lstsq(X[one], y[one], rcond=None)
     a, b, c, d = (float(v) for v in coef)
     # e: per-iteration time with all p slots busy, from a data-parallel problem
-    # of four full waves (four tiles per slot) at two depths
+    # of four full waves (four tiles per slot) at two depths.  A tile whose
+    # plans of at most one workgroup per CU run a kernel of their own (the
+    # three-stage small tile) is measured on one full wave of that kernel.
+    big = sk.Plan(BM * 4 * p, BN, BK * 16, lb=lb, ta=cdt, tc=cdt, policy="dp", tile=full_tile).info()
+    waves = 1 if big["stages"] != probe["stages"] else 4
     tw = []
     for ipt in (16, 64):
-        t = 4 * p
+        t = waves * (cus if waves == 1 else p)
         tm = 1
         while tm * tm < t:
             tm *= 2
@@ -268,7 +272,7 @@ def measure(dtype="bf16", reps=20, verbose=True, tile=None):
             launch()
         e1.record()
         e1.synchronize()
-        tw.append(e0.elapsed_time(e1) / 5 * 1e3 / 4)      # microseconds per wave
+        tw.append(e0.elapsed_time(e1) / 5 * 1e3 / waves)      # microseconds per wave
         if verbose:
             print(f"full waves: t={t} ipt={ipt}: {tw[-1]:.2f} us per wave", flush=True)
     e = (tw[1] - tw[0]) / (64 - 16)

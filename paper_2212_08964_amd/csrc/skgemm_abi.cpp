@@ -136,6 +136,9 @@ void model_for(int dt, int v, double* m) {
     if (dt == DT_F64) { m[0] = 5.00; m[1] = 1.23; m[2] = 0.713; m[3] = 1.13; m[4] = 2.09; return; }
     if (dt == DT_F32) { m[0] = 6.20; m[1] = 1.25; m[2] = 2.07; m[3] = 0.569; m[4] = 3.99; return; }
     // the convolution variants take the constants of the GEMM tile of their shape
+    // the three-stage small tile: calibrate.py's grid mode with e from one
+    // full wave of it (one workgroup per CU)
+    if (v == kVariantDeep) { m[0] = 5.98; m[1] = 1.21; m[2] = 0.581; m[3] = 0.658; m[4] = 0.608; return; }
     if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
     if (v == 1 || v == 4) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
     if (v == 5) { m[0] = 5.99; m[1] = 1.49; m[2] = 0.703; m[3] = 0.570; m[4] = 1.009; return; }
@@ -590,6 +593,49 @@ static double plan_estimate_compute(const skgemm_plan_s* pl) {
            d * double(peers - 1);
 }
 
+// Plan of tile variant v for the problems of base under options o; nullptr
+// with *st set when the variant cannot run them (SKGEMM_ERR_HIP: out of
+// host memory).  The three-stage small tile holds one workgroup per CU, so a
+// co-residency given in the options counts as 1 for it.
+static skgemm_plan_s* build_variant(const skgemm_plan_s* base, int v, const skgemm_options_t& o, int G,
+                                    const int64_t* M, const int64_t* N, const int64_t* K, skgemm_status_t* st) {
+    skgemm_options_t ov = o;
+    if (v == kVariantDeep && ov.occupancy) ov.occupancy = 1;
+    const TileCfg tc_ = tile_for(base->dtype, v);
+    skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s(*base);
+    if (!pl) {
+        *st = SKGEMM_ERR_HIP;
+        return nullptr;
+    }
+    pl->variant = v;
+    pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
+    model_for(pl->dtype, v, pl->model);
+    for (int j = 0; j < G; ++j) {
+        const int i = pl->order[j];
+        add_problem(pl, M[i], N[i], K[i]);
+    }
+    *st = SKGEMM_OK;
+    if (!pl->G) {
+        pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(pl->K);
+        pl->tm = pl->ptm[0]; pl->tn = pl->ptn[0]; pl->ipt = pl->pipt[0];
+        const int64_t tiles = int64_t(pl->tm) * pl->tn * pl->batch;
+        if (tiles > kMaxDim || tiles * pl->ipt > kMaxDim) {
+            *st = SKGEMM_ERR_UNSUPPORTED;
+        } else if (pl->batch > 1) {
+            // a strided batch is one iteration space of batch * t1 tiles
+            // (problem after problem), each with the same iterations
+            pl->tile_base[1] = int32_t(tiles);
+            pl->iter_base[1] = tiles * pl->ipt;
+        }
+    }
+    if (*st == SKGEMM_OK) *st = finish_plan(pl, ov);
+    if (*st != SKGEMM_OK) {
+        delete pl;
+        return nullptr;
+    }
+    return pl;
+}
+
 // Builds the plan for every admissible tile variant (the one the options
 // name, else all that exist) and keeps the one with the smallest modelled
 // runtime (the default tile on ties), after choosing between the two wave
@@ -622,36 +668,14 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
                       (o.tile_k && o.tile_k != tc_.bk)))
             continue;
         if (o.tile_waves && kernel_threads(base->dtype, v) != 64 * o.tile_waves) continue;
-        skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s(*base);
-        if (!pl) {
-            for (skgemm_plan_s* c : cand) delete c;
-            return SKGEMM_ERR_HIP;
-        }
-        pl->variant = v;
-        pl->BM = tc_.bm; pl->BN = tc_.bn; pl->BK = tc_.bk;
-        model_for(pl->dtype, v, pl->model);
-        for (int j = 0; j < G; ++j) {
-            const int i = pl->order[j];
-            add_problem(pl, M[i], N[i], K[i]);
-        }
         skgemm_status_t st = SKGEMM_OK;
-        if (!pl->G) {
-            pl->Ml = pl->pM[0]; pl->Nl = pl->pN[0]; pl->Kl = int32_t(pl->K);
-            pl->tm = pl->ptm[0]; pl->tn = pl->ptn[0]; pl->ipt = pl->pipt[0];
-            const int64_t tiles = int64_t(pl->tm) * pl->tn * pl->batch;
-            if (tiles > kMaxDim || tiles * pl->ipt > kMaxDim) {
-                st = SKGEMM_ERR_UNSUPPORTED;
-            } else if (pl->batch > 1) {
-                // a strided batch is one iteration space of batch * t1 tiles
-                // (problem after problem), each with the same iterations
-                pl->tile_base[1] = int32_t(tiles);
-                pl->iter_base[1] = tiles * pl->ipt;
+        skgemm_plan_s* pl = build_variant(base, v, o, G, M, N, K, &st);
+        if (!pl) {
+            if (st == SKGEMM_ERR_HIP) {
+                for (skgemm_plan_s* c : cand) delete c;
+                return st;
             }
-        }
-        if (st == SKGEMM_OK) st = finish_plan(pl, o);
-        if (st != SKGEMM_OK) {
             last = st;
-            delete pl;
             continue;
         }
         cand[v] = pl;
@@ -688,6 +712,48 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
         }
     }
     if (!best) return last;
+    // An automatic single-GEMM plan that splits the small 16-bit tile's tiles
+    // over more workgroups than CUs (two on some CUs) is replaced by a plan
+    // of at most one workgroup per CU on the three-stage kernel where that
+    // was measured faster: with at most half as many tiles as CUs, the
+    // largest split that fits (floor(CUs / t) shares per tile; 56 of 70 BF16
+    // sweep shapes with 12 or more iterations per tile, 6 % less time, warm
+    // and cold); with more, data-parallel tiles where the tiles have fewer
+    // than 32 iterations (33 of 41 shapes, 4-7 % less; with longer tiles the
+    // split's two workgroups per CU win).  The grid-size model does not see
+    // this: its constants come from problems small enough to stay in cache,
+    // where the two kernels' iterations cost the same.
+    if (!best->G && o.policy == SKGEMM_POLICY_AUTO && o.force_g == 0 && (best->variant == 1 || best->variant == 2) &&
+        (o.tile_waves == 0 || o.tile_waves == 8) && best->policy == SKGEMM_POLICY_SK && best->occ > 0 &&
+        kernel_exists(best->dtype, best->akc, best->bkc, kVariantDeep)) {
+        const int cus = best->p / best->occ;
+        if (best->g_sk > cus && best->t <= cus) {
+            skgemm_options_t od = o;
+            bool take = false;
+            if (2 * best->t <= cus && best->ipt >= 12) {
+                od.policy = SKGEMM_POLICY_SK;
+                od.force_g = (cus / best->t) * best->t;
+                take = true;
+            } else if (2 * best->t > cus && best->ipt < 32) {
+                od.policy = SKGEMM_POLICY_DP;
+                take = true;
+            }
+            if (take) {
+                skgemm_status_t st = SKGEMM_OK;
+                skgemm_plan_s* d = build_variant(base, kVariantDeep, od, G, M, N, K, &st);
+                if (!d && st == SKGEMM_ERR_HIP) {
+                    delete best;
+                    return st;
+                }
+                if (d && d->grid <= cus) {
+                    delete best;
+                    best = d;
+                } else {
+                    delete d;
+                }
+            }
+        }
+    }
     // A small-tile plan whose grid fits one workgroup per CU runs the
     // eight-wave tile on three LDS stages instead: same tile, schedule and
     // workspace, two k-slabs in flight instead of one.  A lone workgroup on

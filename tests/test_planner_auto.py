@@ -119,3 +119,35 @@ def test_paper_policy_is_the_papers_selection_in_the_library():
         ref = oracle_plan_for(info, p_.model_constants(), "paper")
         assert (ref.policy, ref.sk_tiles, ref.g_sk, ref.grid, ref.sk_first) == (
             info["policy_name"], info["sk_tiles"], info["g_sk"], info["grid"], bool(info["sk_first"]))
+
+
+def test_auto_three_stage_rule():
+    """Automatic plans of the small 16-bit tile that split over more
+    workgroups than CUs: with at most CUs/2 tiles and 12 or more iterations
+    per tile they split floor(CUs/t) ways on the three-stage kernel; with more
+    tiles and fewer than 32 iterations per tile they run data-parallel on it;
+    otherwise the split stands.  The four-wave plan (which asks for four
+    waves, so no rule applies) is the plan before the rule."""
+    import workloads as W
+    sk = _sk()
+    cus = 256
+    seen = set()
+    for (M, N, K) in W.sweep_shapes(600, seed=5):
+        ref = sk.Plan(M, N, K, ta=sk.BF16, num_cus=cus, occupancy=2, tile=(128, 128, 64, 4)).info()
+        got = sk.Plan(M, N, K, ta=sk.BF16, num_cus=cus, occupancy=2, tile=(128, 128, 64)).info()
+        if not (ref["policy_name"] == "sk" and ref["g_sk"] > cus and ref["t"] <= cus):
+            continue
+        t, ipt = ref["t"], ref["ipt"]
+        if 2 * t <= cus and ipt >= 12:
+            assert (got["policy_name"], got["g_sk"], got["stages"], got["p"]) == ("sk", cus // t * t, 3, cus)
+            seen.add("split")
+        elif 2 * t > cus and ipt < 32:
+            assert (got["policy_name"], got["grid"], got["stages"], got["p"]) == ("dp", t, 3, cus)
+            seen.add("dp")
+        else:
+            assert (got["policy_name"], got["g_sk"], got["stages"]) == ("sk", ref["g_sk"], 2)
+            seen.add("kept")
+        # explicit policies and forced grids are never changed
+        exp = sk.Plan(M, N, K, ta=sk.BF16, num_cus=cus, occupancy=2, tile=(128, 128, 64), policy="sk").info()
+        assert exp["stages"] == 2 and exp["g_sk"] > cus
+    assert seen == {"split", "dp", "kept"}
