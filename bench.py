@@ -39,11 +39,11 @@ if ROOT not in sys.path:
 
 METRIC = "TFLOP/s & % MFMA peak, Stream-K vs data-parallel tiles, bf16 shape sweep"
 
-# HBM bytes per launch of the sweep, from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE,
+# HBM bytes per GEMM kernel launch of the sweep, from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE,
 # each scaled by its reading for a plain 256 MiB copy); valid only for the kernel sources
 # they were taken on, identified by the hash below (see profiles/skgemm_bf16_sweep_hbm_traffic.md).
-TRAFFIC_BYTES_PER_LAUNCH = 66.52e6
-TRAFFIC_SOURCES_SHA256 = "e6769f052f7ca5e5"
+TRAFFIC_BYTES_PER_LAUNCH = 62.68e6
+TRAFFIC_SOURCES_SHA256 = "b93fd32550141936"
 
 
 def kernel_sources_hash() -> str:
