@@ -97,11 +97,12 @@ typedef struct {
                                          128x128x128; FP64 64x64x16 or 128x128x16.
                                          A named tile with no kernel for the
                                          operands' contiguity: SKGEMM_ERR_UNSUPPORTED.
-                                         A 16-bit 128x128x64 plan whose grid is at
-                                         most the CU count runs an eight-wave
-                                         kernel with three LDS stages (one
-                                         workgroup per CU; plan_info field 29)
-                                         unless tile_waves asks for four */
+                                         A 16-bit 128x128x64 plan (GEMM or
+                                         convolution) whose grid is at most the
+                                         CU count runs an eight-wave kernel with
+                                         three LDS stages (one workgroup per CU;
+                                         plan_info field 29) unless tile_waves
+                                         asks for four */
     int32_t hybrid_min_waves;     /* full waves needed for the two-tile hybrid (default 2) */
     int32_t num_cus;              /* >0: plan for this many CUs instead of querying */
     int32_t occupancy;            /* >0: workgroups per CU instead of querying */

@@ -56,6 +56,7 @@ const void* kernel_table(bool akc, bool bkc, int v) {
             case 6: return bkc_only<DT, 6, FULL>(akc, bkc);    // tall tile
             case 7: return kc_only<DT, 7, FULL>(akc, bkc);     // tall tile, convolution
             case 8: return any_layout<DT, 8, FULL>(akc, bkc);  // small tile, three stages
+            case 9: return kc_only<DT, 9, FULL>(akc, bkc);     // the same, convolution
             default: return nullptr;
         }
     } else if constexpr (DT == DT_F8) {

@@ -112,7 +112,7 @@ TileCfg tile_for(int dt, int v) {
     if (v == 4 && (dt == DT_BF16 || dt == DT_F16)) return kTile16S;
     if (v == 5 && (dt == DT_BF16 || dt == DT_F16)) return kTile16K;     // skinny
     if ((v == 6 || v == 7) && (dt == DT_BF16 || dt == DT_F16)) return kTile16T;     // tall
-    if (v == kVariantDeep && (dt == DT_BF16 || dt == DT_F16)) return kTile16D;      // three stages
+    if ((v == kVariantDeep || v == kVariantDeepConv) && (dt == DT_BF16 || dt == DT_F16)) return kTile16D;   // three stages
     if (v == 1 && dt == DT_F8) return kTileF8S;
     if (v == 1 && dt == DT_F64) return kTileF64L;
     return TileCfg{0, 0, 0};
@@ -138,7 +138,7 @@ void model_for(int dt, int v, double* m) {
     // the convolution variants take the constants of the GEMM tile of their shape
     // the three-stage small tile: calibrate.py's grid mode with e from one
     // full wave of it (one workgroup per CU)
-    if (v == kVariantDeep) { m[0] = 5.98; m[1] = 1.21; m[2] = 0.581; m[3] = 0.658; m[4] = 0.608; return; }
+    if (v == kVariantDeep || v == kVariantDeepConv) { m[0] = 5.98; m[1] = 1.21; m[2] = 0.581; m[3] = 0.658; m[4] = 0.608; return; }
     if (v == 2) { m[0] = 5.38; m[1] = 1.51; m[2] = 0.583; m[3] = 0.648; m[4] = 0.981; return; }
     if (v == 1 || v == 4) { m[0] = 5.60; m[1] = 1.38; m[2] = 0.603; m[3] = 0.577; m[4] = 0.899; return; }
     if (v == 5) { m[0] = 5.99; m[1] = 1.49; m[2] = 0.703; m[3] = 0.570; m[4] = 1.009; return; }
@@ -600,7 +600,7 @@ static double plan_estimate_compute(const skgemm_plan_s* pl) {
 static skgemm_plan_s* build_variant(const skgemm_plan_s* base, int v, const skgemm_options_t& o, int G,
                                     const int64_t* M, const int64_t* N, const int64_t* K, skgemm_status_t* st) {
     skgemm_options_t ov = o;
-    if (v == kVariantDeep && ov.occupancy) ov.occupancy = 1;
+    if ((v == kVariantDeep || v == kVariantDeepConv) && ov.occupancy) ov.occupancy = 1;
     const TileCfg tc_ = tile_for(base->dtype, v);
     skgemm_plan_s* pl = new (std::nothrow) skgemm_plan_s(*base);
     if (!pl) {
@@ -646,7 +646,7 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
     skgemm_plan_s* cand[kVariants] = {};
     skgemm_status_t last = SKGEMM_ERR_UNSUPPORTED;
     for (int v = 0; v < kVariants; ++v) {
-        if (v == kVariantDeep) continue;                   // substituted below, not a candidate
+        if (v == kVariantDeep || v == kVariantDeepConv) continue;   // substituted below, not candidates
         if (is_conv_variant(v) != base->conv) continue;     // the convolution kernels are variants 3, 4 and 7
         // the skinny tile only where every launched problem has at most its
         // 64 rows (unless the options name it)
@@ -723,9 +723,13 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
     // split's two workgroups per CU win).  The grid-size model does not see
     // this: its constants come from problems small enough to stay in cache,
     // where the two kernels' iterations cost the same.
-    if (!best->G && o.policy == SKGEMM_POLICY_AUTO && o.force_g == 0 && (best->variant == 1 || best->variant == 2) &&
-        (o.tile_waves == 0 || o.tile_waves == 8) && best->policy == SKGEMM_POLICY_SK && best->occ > 0 &&
-        kernel_exists(best->dtype, best->akc, best->bkc, kVariantDeep)) {
+    // (the small tile's GEMM variants 1 and 2 take variant 8; its
+    // convolution variant 4 takes variant 9)
+    const int deep = best->variant == 4 ? kVariantDeepConv : best->variant == 1 || best->variant == 2 ? kVariantDeep : -1;
+    const bool deep_ok = deep >= 0 && (o.tile_waves == 0 || o.tile_waves == 8) && best->occ > 0 &&
+                         kernel_exists(best->dtype, best->akc, best->bkc, deep);
+    if (deep_ok && !best->G && o.policy == SKGEMM_POLICY_AUTO && o.force_g == 0 &&
+        best->policy == SKGEMM_POLICY_SK) {
         const int cus = best->p / best->occ;
         if (best->g_sk > cus && best->t <= cus) {
             skgemm_options_t od = o;
@@ -740,7 +744,7 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
             }
             if (take) {
                 skgemm_status_t st = SKGEMM_OK;
-                skgemm_plan_s* d = build_variant(base, kVariantDeep, od, G, M, N, K, &st);
+                skgemm_plan_s* d = build_variant(base, deep, od, G, M, N, K, &st);
                 if (!d && st == SKGEMM_ERR_HIP) {
                     delete best;
                     return st;
@@ -764,17 +768,16 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
     // workgroup per CU).  Not where the options ask for four waves.  The plan
     // keeps the model constants it was resolved with (the grid fits the new
     // capacity, so every choice the model made stands).
-    if ((best->variant == 1 || best->variant == 2) && (o.tile_waves == 0 || o.tile_waves == 8) && best->grid > 0 &&
-        best->occ > 0 && kernel_exists(best->dtype, best->akc, best->bkc, kVariantDeep)) {
+    if (deep_ok && best->variant != deep && best->grid > 0) {
         const int cus = best->p / best->occ;
         int occ = 1;            // its LDS leaves room for one workgroup per CU
         if (o.occupancy == 0) {
             int qc = 0, qo = 0;
-            if (device_capacity(best->dtype, best->akc, best->bkc, kVariantDeep, &qc, &qo) != SKGEMM_OK) qo = 0;
+            if (device_capacity(best->dtype, best->akc, best->bkc, deep, &qc, &qo) != SKGEMM_OK) qo = 0;
             occ = qo;
         }
         if (occ >= 1 && best->grid <= cus) {
-            best->variant = kVariantDeep;
+            best->variant = deep;
             best->occ = occ;
             best->p = cus * occ;
         }

@@ -114,9 +114,11 @@ struct KArgs {
 // eight-wave 128x128 16-bit tile on three LDS stages (two slabs in flight),
 // one workgroup per CU; the planner substitutes it for variants 1 and 2
 // where the grid fits one workgroup per CU, never as a candidate of its own.
-constexpr int kVariants = 9;
+// 9: the same with the convolution gather, substituted for variant 4.
+constexpr int kVariants = 10;
 constexpr int kVariantDeep = 8;
-constexpr bool is_conv_variant(int v) { return v == 3 || v == 4 || v == 7; }
+constexpr int kVariantDeepConv = 9;
+constexpr bool is_conv_variant(int v) { return v == 3 || v == 4 || v == 7 || v == 9; }
 
 // Copy `lines` lines of `cols` elements of eb bytes (line i at src + i * ld)
 // to dst with leading dimension ldd, on stream.  Returns a hipError_t value.

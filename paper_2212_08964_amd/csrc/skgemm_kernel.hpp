@@ -96,6 +96,8 @@ template <> struct Cfg<DT_F16, 4> : Cfg<DT_F16, 1> { static constexpr bool CONV 
 template <> struct Cfg<DT_BF16, 4> : Cfg<DT_BF16, 1> { static constexpr bool CONV = true; };
 template <> struct Cfg<DT_F16, 7> : Cfg<DT_F16, 6> { static constexpr bool CONV = true; };
 template <> struct Cfg<DT_BF16, 7> : Cfg<DT_BF16, 6> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_F16, 9> : Cfg<DT_F16, 8> { static constexpr bool CONV = true; };
+template <> struct Cfg<DT_BF16, 9> : Cfg<DT_BF16, 8> { static constexpr bool CONV = true; };
 
 // Optional tile traits: PRIO raises the waves' priority through the MFMA
 // section of each k-slab; WPE overrides the waves per SIMD the register

@@ -417,14 +417,15 @@ def test_conv_plan_is_the_gemm_view(case, policy):
 
 
 def test_conv_chooses_among_its_tiles():
-    """256x256 and 128x128 for any channel count; the tall 256x64 tile only
-    for at most 64 output channels."""
+    """256x256 and 128x128 for any channel count (the 128x128 one on eight
+    waves and three stages where the grid fits one workgroup per CU); the
+    tall 256x64 tile only for at most 64 output channels."""
     sk = _lib()
     big = sk.ConvPlan(32, 56, 56, 64, 256, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
     small = sk.ConvPlan(1, 7, 7, 64, 128, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
     narrow = sk.ConvPlan(32, 56, 56, 64, 64, 3, 3, (1, 1), num_cus=256, occupancy=1).info()
-    assert big["tile"] in {(256, 256, 64, 8), (128, 128, 64, 4)}
-    assert small["tile"] == (128, 128, 64, 4)
+    assert big["tile"] in {(256, 256, 64, 8), (128, 128, 64, 4), (128, 128, 64, 8)}
+    assert small["tile"] == (128, 128, 64, 8) and small["stages"] == 3
     assert narrow["tile"] == (256, 64, 64, 4)
     for k in (65, 96, 200):
         assert sk.ConvPlan(8, 14, 14, 64, k, 3, 3, (1, 1), num_cus=256, occupancy=1).info()["tile"] != (256, 64, 64, 4)
@@ -540,9 +541,9 @@ def test_plan_log_environment_switch():
 def test_three_stage_small_tile_substitution():
     """A 16-bit 128x128x64 plan whose grid fits one workgroup per CU runs the
     eight-wave kernel on three LDS stages (occupancy 1), with the schedule,
-    workspace and model constants of the plan it replaces; never for larger
-    grids, four requested waves, other tiles, other input types or
-    convolutions."""
+    workspace and model constants of the plan it replaces (a convolution
+    plan: the same kernel with the gather); never for larger grids, four
+    requested waves, other tiles or other input types."""
     sk = _lib()
     kw = dict(num_cus=256, occupancy=2)
     for ta in (sk.BF16, sk.F16):
@@ -567,7 +568,12 @@ def test_three_stage_small_tile_substitution():
     assert sk.Plan(1024, 1024, 1024, lb=sk.COL_MAJOR, ta=sk.F8E4M3, tc=sk.BF16, tile=(128, 128, 128), policy="dp", **kw).info()["stages"] == 2
     assert sk.Plan(1024, 1024, 1024, ta=sk.F32, tc=sk.F32, **kw).info()["stages"] == 2
     assert sk.Plan(512, 512, 512, ta=sk.F64, tc=sk.F64, tile=(128, 128, 16), **kw).info()["stages"] == 2
-    assert sk.ConvPlan(2, 16, 16, 64, 128, 3, 3, (1, 1), ta=sk.BF16, tile=(128, 128, 64), **kw).info()["stages"] == 2
+    cv = sk.ConvPlan(2, 16, 16, 64, 128, 3, 3, (1, 1), ta=sk.BF16, tile=(128, 128, 64), **kw).info()
+    assert (cv["stages"], cv["waves"], cv["occupancy"]) == (3, 8, 1) and cv["grid"] <= 256
+    cv4 = sk.ConvPlan(2, 16, 16, 64, 128, 3, 3, (1, 1), ta=sk.BF16, tile=(128, 128, 64, 4), **kw).info()
+    assert (cv4["stages"], cv4["waves"]) == (2, 4)
+    big = sk.ConvPlan(32, 56, 56, 64, 128, 3, 3, (1, 1), ta=sk.BF16, tile=(128, 128, 64), policy="dp", **kw).info()
+    assert big["stages"] == 2 and big["grid"] > 256
     g = sk.GroupedPlan([300, 500], [600, 400], [700, 700], ta=sk.BF16, tile=(128, 128, 64), **kw).info()
     assert g["stages"] == (3 if g["grid"] <= 256 else 2)
 

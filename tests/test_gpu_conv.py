@@ -168,3 +168,30 @@ def test_conv_resnet_layer_sampled_images():
     for i in (0, 37, 63):
         ref = oracle(x[i:i + 1], f, case)
         assert og.rel_frobenius(to_f64(y[i:i + 1]), ref) <= TOL_OUT32, i
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[2], CASES[6]])
+def test_conv_three_stage_tile_bitwise_and_exact(case):
+    """Convolution plans of the 128x128 tile whose grid fits one workgroup per
+    CU run the eight-wave three-stage kernel with the gather: bitwise the
+    four-wave kernel's result on the same schedule, and exact on
+    integer-valued inputs."""
+    from helpers import resolved
+    n, h, w, c, k, r, s, pad, std, dil = case
+    found = 0
+    for pol in ("auto", "dp", "sk"):
+        plan = sk().ConvPlan(n, h, w, c, k, r, s, pad, std, dil, ta=sk().BF16, tc=sk().F32, policy=pol,
+                             tile=(128, 128, 64))
+        info = plan.info()
+        if info["stages"] != 3:
+            continue
+        found += 1
+        p4, g4 = resolved(info)
+        for integer in (False, True):
+            x, f = inputs(case, torch.bfloat16, seed=21, integer=integer)
+            y8 = conv(x, f, case, out_dtype=torch.float32, policy=p4, force_g=g4, tile=(128, 128, 64))
+            y4 = conv(x, f, case, out_dtype=torch.float32, policy=p4, force_g=g4, tile=(128, 128, 64, 4))
+            assert torch.equal(y8, y4), (case, pol, integer)
+            if integer:
+                assert np.array_equal(to_f64(y8), oracle(x, f, case)), (case, pol)
+    assert found >= 1
