@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--shapes", type=int, default=1000)
+    ap.add_argument("--shape-seed", type=int, default=0,
+                    help="seed of the sweep's shapes (the benchmark is seed 0; others check planner rules "
+                         "on shapes they were not measured on)")
     ap.add_argument("--reps", type=int, default=8,
                     help="back-to-back launches per timed round for the per-shape ratios (best of 3 rounds)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
@@ -513,7 +516,7 @@ def main():
     import workloads as W
     from paper_2212_08964_amd import skgemm as sk
 
-    shapes = W.sweep_shapes(args.shapes, seed=0)
+    shapes = W.sweep_shapes(args.shapes, seed=args.shape_seed)
     t0 = time.perf_counter()
     cases = build_cases(shapes, torch, sk, relayout=0 if args.relayout == "auto" else -1)
     plan_s = time.perf_counter() - t0
@@ -752,7 +755,7 @@ def main():
         "config": {"workload": "bf16 shape sweep: 1000 GEMMs, M,N,K log-uniform in [128,8192] "
                                "(half multiples of 128, half +1..127), A,B iid N(0,1) bf16, FP32 accumulate, "
                                "bf16 out, row-major",
-                   "n_shapes": n, "policy": "auto (DP waves + Stream-K remainder)",
+                   "n_shapes": n, "shape_seed": args.shape_seed, "policy": "auto (DP waves + Stream-K remainder)",
                    "baseline": "same kernel and tile, policy=dp (one workgroup per tile)",
                    "tiles": "256x256x64, or 128x128x64 (4 or 8 waves) where the planner predicts it faster "
                             "(same tile for both)",
