@@ -495,9 +495,18 @@ def profile_shape(args):
     torch.cuda.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / steps
     info = plan.info()
-    print(json.dumps({"shape": [M, N, K], "plan": {k: info[k] for k in ("policy_name", "tile", "g_sk", "grid")},
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy probe: {nb} bytes read, {nb} bytes written", flush=True)
+    print(json.dumps({"shape": [M, N, K], "plan": {k: info[k] for k in ("policy_name", "tile", "g_sk", "grid", "stages")},
                       "launches": steps, "us_per_launch": round(us, 2),
-                      "tflops": round(2.0 * M * N * K / (us * 1e-6) / 1e12, 1)}), flush=True)
+                      "tflops": round(2.0 * M * N * K / (us * 1e-6) / 1e12, 1),
+                      "algorithmic_bytes": 2 * (M * K + K * N + M * N)}), flush=True)
 
 
 def main():
