@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
     SKGEMM_OK = 0,
     SKGEMM_ERR_INVALID_ARG = 1,   /* bad shape, leading dimension, pointer or enum */
-    SKGEMM_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+    SKGEMM_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
     SKGEMM_ERR_WORKSPACE = 3,     /* workspace missing, misaligned or too small */
     SKGEMM_ERR_CAPACITY = 4,      /* grid larger than the co-resident workgroups
                                      (or than 4096 Stream-K workgroups) */
