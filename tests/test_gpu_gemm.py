@@ -391,10 +391,12 @@ def test_determinism_under_concurrent_noise(fixup):
 def test_sweep_sample_as_benchmarked():
     """Every 20th shape of the BF16 sweep the benchmark times (bf16 in and out,
     row-major, automatic policy, the planner's tile), on sampled rows against
-    the FP64 oracle; the plans cover data-parallel, split and hybrid cases."""
+    the FP64 oracle; the plans cover data-parallel, split and hybrid cases on
+    both the two- and the three-stage kernels."""
     shapes = W.sweep_shapes(1000, seed=0)[::20]
     gen = torch.Generator(device="cpu").manual_seed(0)
     seen = set()
+    stages = set()
     for (M, N, K) in shapes:
         A = torch.randn((M, K), generator=gen).to(torch.bfloat16).to(dev())
         B = torch.randn((K, N), generator=gen).to(torch.bfloat16).to(dev())
@@ -402,11 +404,13 @@ def test_sweep_sample_as_benchmarked():
         assert C.dtype == torch.bfloat16
         info = sk().get_plan(M, N, K, 0, 0, 0, sk().BF16, sk().BF16, "auto", 0, 2, None).info()
         seen.add((info["policy_name"], info["coop_s"] > 0))
+        stages.add(info["stages"])
         rows = np.unique(np.random.default_rng(M + N + K).integers(0, M, 6))
         ref = og.gemm_rows_f64(to_f64(A), to_f64(B), rows)
         got = to_f64(C[torch.from_numpy(rows).to(dev())])
         assert og.rel_frobenius(got, ref) <= TOL_16, (M, N, K, info["policy_name"])
     assert ("sk", True) in seen and ("dp", False) in seen
+    assert stages == {2, 3}
 
 
 @pytest.mark.parametrize("fixup", ["auto", "owner"])
