@@ -638,8 +638,8 @@ static skgemm_plan_s* build_variant(const skgemm_plan_s* base, int v, const skge
 
 // Builds the plan for every admissible tile variant (the one the options
 // name, else all that exist) and keeps the one with the smallest modelled
-// runtime (the default tile on ties), after choosing between the two wave
-// layouts of the small 16-bit tile by the rule below.
+// runtime (the default tile on ties); the small 16-bit tile competes on its
+// eight-wave layout (the four-wave one only where the options ask for it).
 static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t& o, int G, const int64_t* M,
                                      const int64_t* N, const int64_t* K, skgemm_plan_s** out) {
     const bool named = o.tile_m || o.tile_n || o.tile_k;
@@ -680,19 +680,15 @@ static skgemm_status_t plan_variants(skgemm_plan_s* base, const skgemm_options_t
         }
         cand[v] = pl;
     }
-    // The small 16-bit tile on eight waves runs data-parallel tiles faster
-    // (measured over the shape sweep: 8 % on the problems that stay
-    // data-parallel, 3 % on the split ones, whose own data-parallel baseline
-    // gains 8 % too).  It replaces the four-wave tile where both plans are
-    // data-parallel; where the four-wave plan splits, that plan is kept.
+    // The small 16-bit tile on eight waves runs data-parallel tiles 8 % and
+    // split ones 3 % faster than on four (BF16 sweep), so it replaces the
+    // four-wave tile.  Keeping the four-wave tile for split plans, whose
+    // data-parallel baseline also gains from eight waves, held the per-shape
+    // Stream-K / data-parallel ratio 1 % higher but cost 1.4 % of the sweep's
+    // time (0.9 % on a sweep drawn with another seed).
     if (cand[1] && cand[2]) {
-        if (cand[1]->g_sk == 0 && cand[2]->g_sk == 0) {
-            delete cand[1];
-            cand[1] = nullptr;
-        } else {
-            delete cand[2];
-            cand[2] = nullptr;
-        }
+        delete cand[1];
+        cand[1] = nullptr;
     }
     // smallest estimate; between plans the HBM bound makes equal, the smaller
     // compute-model time

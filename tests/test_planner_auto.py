@@ -122,32 +122,30 @@ def test_paper_policy_is_the_papers_selection_in_the_library():
 
 
 def test_auto_three_stage_rule():
-    """Automatic plans of the small 16-bit tile that split over more
-    workgroups than CUs: with at most CUs/2 tiles and 12 or more iterations
-    per tile they split floor(CUs/t) ways on the three-stage kernel; with more
-    tiles and fewer than 32 iterations per tile they run data-parallel on it;
-    otherwise the split stands.  The four-wave plan (which asks for four
-    waves, so no rule applies) is the plan before the rule."""
+    """Automatic plans of the small 16-bit tile: a split over more workgroups
+    than CUs (two-stage kernel) stands only where the three-stage rule does
+    not apply (with at most CUs/2 tiles, fewer than 12 iterations per tile;
+    with more tiles, 32 or more); the rule's replacements have the forms it
+    defines (floor(CUs/t) shares per tile, or data-parallel tiles, on the
+    three-stage kernel); explicit policies are never changed."""
     import workloads as W
     sk = _sk()
     cus = 256
     seen = set()
     for (M, N, K) in W.sweep_shapes(600, seed=5):
-        ref = sk.Plan(M, N, K, ta=sk.BF16, num_cus=cus, occupancy=2, tile=(128, 128, 64, 4)).info()
         got = sk.Plan(M, N, K, ta=sk.BF16, num_cus=cus, occupancy=2, tile=(128, 128, 64)).info()
-        if not (ref["policy_name"] == "sk" and ref["g_sk"] > cus and ref["t"] <= cus):
-            continue
-        t, ipt = ref["t"], ref["ipt"]
-        if 2 * t <= cus and ipt >= 12:
-            assert (got["policy_name"], got["g_sk"], got["stages"], got["p"]) == ("sk", cus // t * t, 3, cus)
-            seen.add("split")
-        elif 2 * t > cus and ipt < 32:
-            assert (got["policy_name"], got["grid"], got["stages"], got["p"]) == ("dp", t, 3, cus)
-            seen.add("dp")
-        else:
-            assert (got["policy_name"], got["g_sk"], got["stages"]) == ("sk", ref["g_sk"], 2)
+        t, ipt = got["t"], got["ipt"]
+        if got["stages"] == 2 and got["policy_name"] == "sk" and got["g_sk"] > cus and t <= cus:
+            assert not (2 * t <= cus and ipt >= 12) and not (2 * t > cus and ipt < 32), (M, N, K)
             seen.add("kept")
-        # explicit policies and forced grids are never changed
+        elif got["stages"] == 3 and got["policy_name"] == "sk" and 2 * t <= cus and ipt >= 12 \
+                and got["g_sk"] == cus // t * t:
+            assert got["p"] == cus and got["waves"] == 8
+            seen.add("split")
+        elif got["stages"] == 3 and got["policy_name"] == "dp" and 2 * t > cus and ipt < 32:
+            assert got["grid"] == t <= cus
+            seen.add("dp")
+        # explicit policies and forced grids are never changed by the rule
         exp = sk.Plan(M, N, K, ta=sk.BF16, num_cus=cus, occupancy=2, tile=(128, 128, 64), policy="sk").info()
-        assert exp["stages"] == 2 and exp["g_sk"] > cus
+        assert exp["stages"] == (3 if exp["grid"] <= cus else 2)
     assert seen == {"split", "dp", "kept"}
