@@ -42,8 +42,8 @@ METRIC = "TFLOP/s & % MFMA peak, Stream-K vs data-parallel tiles, bf16 shape swe
 # HBM bytes per GEMM kernel launch of the sweep, from two rocprofv3 PMC runs (FETCH_SIZE, WRITE_SIZE,
 # each scaled by its reading for a plain 256 MiB copy); valid only for the kernel sources
 # they were taken on, identified by the hash below (see profiles/skgemm_bf16_sweep_hbm_traffic.md).
-TRAFFIC_BYTES_PER_LAUNCH = 62.66e6
-TRAFFIC_SOURCES_SHA256 = "786b2929f65ec6f0"
+TRAFFIC_BYTES_PER_LAUNCH = 60.93e6
+TRAFFIC_SOURCES_SHA256 = "5d9a6fb7e5a2408e"
 
 
 def kernel_sources_hash() -> str:
